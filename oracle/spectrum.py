@@ -1,0 +1,75 @@
+"""Shell binning of a per-mode quantity in |k| (oracle side).
+
+Test infrastructure only (FP64 CPU oracle).
+
+The paper bins the source-term ratio in a grid of k values and reports the
+mean and the scatter in each bin (Sec. 3, the procedure paragraph and the
+discussion of the source-term figure).  Readings taken here:
+  * nbins equal shells of width dk = k_Nyq / nbins, k_Nyq = pi n / L;
+  * shell index b = floor(|k| / dk), computed exactly in integers from the
+    integer mode numbers: b = isqrt(floor(|m|^2 nbins^2 / (n/2)^2));
+  * the DC mode and modes with b >= nbins are left out (so every Nyquist
+    plane is left out);
+  * each half-spectrum mode stands for itself and its conjugate partner:
+    weight 2 for 0 < m_z < n/2, weight 1 on the m_z = 0 plane;
+  * mean = sum(w q) / sum(w); std = sqrt(max(0, sum(w q^2)/sum(w) - mean^2))
+    (population scatter); k_mean = sum(w |k|)/sum(w); an empty bin reports
+    zeros.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .fields import modes
+from .model import Model
+
+
+def isqrt_array(v: np.ndarray) -> np.ndarray:
+    """Exact floor(sqrt(v)) for non-negative int64 arrays."""
+    r = np.floor(np.sqrt(v.astype(np.float64))).astype(np.int64)
+    r = np.where(r * r > v, r - 1, r)
+    r = np.where((r + 1) * (r + 1) <= v, r + 1, r)
+    return r
+
+
+def shell_index(n: int, nbins: int):
+    """(bin index, weight) on the half spectrum; -1 marks modes left out."""
+    mx, my, mz = modes(n)
+    m2 = (mx * mx + my * my + mz * mz).astype(np.int64)
+    h = n // 2
+    b = isqrt_array((m2 * nbins * nbins) // (h * h))
+    w = np.where(mz == 0, 1, 2).astype(np.int64) * np.ones_like(m2)
+    b = np.where((m2 == 0) | (b >= nbins), -1, b)
+    return b, w
+
+
+def bin_shells(q: np.ndarray, m: Model, nbins: int):
+    """(k_mean, count, mean, std) per shell for per-mode values ``q``."""
+    q = np.asarray(q, dtype=np.float64)
+    b, w = shell_index(m.n, nbins)
+    mx, my, mz = modes(m.n)
+    kk = (2.0 * math.pi / m.box) * np.sqrt((mx * mx + my * my + mz * mz).astype(np.float64))
+    kk = np.broadcast_to(kk, b.shape)
+    sel = b >= 0
+    bs, ws = b[sel], w[sel].astype(np.float64)
+    qs, ks = np.broadcast_to(q, b.shape)[sel], kk[sel]
+    cnt = np.bincount(bs, weights=ws, minlength=nbins)
+    sk = np.bincount(bs, weights=ws * ks, minlength=nbins)
+    sq = np.bincount(bs, weights=ws * qs, minlength=nbins)
+    sq2 = np.bincount(bs, weights=ws * qs * qs, minlength=nbins)
+    nz = cnt > 0
+    safe = np.where(nz, cnt, 1.0)
+    kmean = np.where(nz, sk / safe, 0.0)
+    mean = np.where(nz, sq / safe, 0.0)
+    var = np.where(nz, sq2 / safe - mean * mean, 0.0)
+    std = np.sqrt(np.maximum(var, 0.0))
+    return kmean, cnt, mean, std
+
+
+def source_power(sk, m: Model, nbins: int):
+    """Shell-averaged power of the source, q = V |S(k)/n^3|^2."""
+    s = sk.detach().numpy() if hasattr(sk, "detach") else np.asarray(sk)
+    q = m.volume * np.abs(s / m.n ** 3) ** 2
+    return bin_shells(q, m, nbins)
