@@ -1,0 +1,212 @@
+/*
+ * lpt2.h -- C ABI of the MI355X (gfx950) library for FFT-based second-order
+ * Lagrangian displacements in modified gravity.
+ *
+ * Method: Moretti, Mozzon, Monaco, Munari & Baldi (2019), "Fast numerical
+ * method to generate halo catalogs in modified gravity (part I):
+ * second-order Lagrangian Perturbation Theory".  The problem as the paper
+ * states it (Sec. 3, procedure paragraph; Sec. 2.4): given a linear density
+ * field on a regular periodic grid, a cosmology, a gravity model (mu(k,a) and
+ * the expansion coefficients M_k) and an output time a, return the first-
+ * and second-order displacement of every grid particle, with the
+ * second-order growth factored as D2(k,a) times the GR spatial part.
+ *
+ * Conventions shared by every entry point
+ *   - real fields are float or double [n][n][n], C order (x slowest, z
+ *     fastest); particle (ix,iy,iz) sits at q = (ix,iy,iz) L/n;
+ *   - displacement fields are [3][n][n][n] (component-major), in Mpc/h;
+ *   - F is the unnormalised forward DFT, F^-1 carries 1/n^3;
+ *     k = 2 pi m / L with m the signed FFT index;
+ *   - the DC mode and every Nyquist plane (|m_i| = n/2) are zero in delta(k),
+ *     S(k) and every k-space multiplier;
+ *   - the precision of every field pointer is the plan's (LPT2_FP32: float,
+ *     LPT2_FP64: double); growth factors, multipliers and twiddles are built
+ *     in FP64 and rounded once;
+ *   - field pointers are DEVICE pointers owned by the caller; host arrays are
+ *     owned by the caller; the plan owns its workspace and tables;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *   - no entry point throws; each returns an lpt2_status, and the message of
+ *     the last failure on a plan is available from lpt2_last_error().
+ *   - a plan may be used by one host thread / one stream at a time; a
+ *     concurrent call on the same plan returns LPT2_ESTATE.
+ */
+#ifndef LPT2_H
+#define LPT2_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lpt2_plan_s* lpt2_plan_t;        /* opaque; owns workspace and tables */
+
+typedef enum {
+  LPT2_OK = 0,
+  LPT2_EINVAL = -1,        /* bad argument value or null pointer             */
+  LPT2_EUNSUPPORTED = -2,  /* valid request this library does not implement  */
+  LPT2_ENOMEM = -3,        /* device or host allocation failed               */
+  LPT2_EDEVICE = -4,       /* HIP runtime or kernel launch error             */
+  LPT2_ESTATE = -5         /* plan busy or used in the wrong order           */
+} lpt2_status;
+
+typedef enum { LPT2_FP64 = 0, LPT2_FP32 = 1 } lpt2_precision;
+
+/* Gravity model (Sec. 2.2-2.4).  GR: mu = 1.  FR_HS: Hu-Sawicki f(R) with
+ * n = 1, eq. mihusawicki for M1 = 3 m^2 and M2, mu(k,a) = 1 + (1/3)
+ * (k^2/a^2)/(k^2/a^2 + m^2).  MU_CONST: constant mu (a test model with no
+ * scalar mass; its growth starts on the EdS power-law mode). */
+typedef enum { LPT2_GRAV_GR = 0, LPT2_GRAV_FR_HS = 1, LPT2_GRAV_MU_CONST = 2 } lpt2_gravity;
+
+/* How D2(k,a) is obtained (Sec. 2.4 approximate factorisation; Sec. 3
+ * triangle comparison; Sec. 5 eq. lcdm-fit).
+ *   EDS      D2 = -3/7 D1^2
+ *   T1       eq. full-d2 on the orthogonal isosceles triangle (k1 = k2, 90 deg)
+ *   TRIANGLE eq. full-d2 on k1/k2 = tri_ratio at tri_theta_deg
+ *   WINTHER  T1 geometry with D1(k)^2 in place of D1(k1) D1(k2)
+ *   BOUCHET  D2 = -3/7 D1^2 Omega_m(a)^(-1/143)                          */
+typedef enum {
+  LPT2_D2_EDS = 0, LPT2_D2_T1 = 1, LPT2_D2_TRIANGLE = 2,
+  LPT2_D2_WINTHER = 3, LPT2_D2_BOUCHET = 4
+} lpt2_factorisation;
+
+typedef enum { LPT2_SPEC_POWER = 0, LPT2_SPEC_RATIO = 1 } lpt2_spec_quantity;
+
+typedef struct {
+  int    n;               /* cells per side: a power of two, 8..512            */
+  double box;             /* side length L in Mpc/h, > 0                       */
+  double omega_m;         /* flat background: Omega_L = 1 - Omega_m           */
+  double h;               /* BBKS shape parameter Gamma = Omega_m h            */
+  double n_s;             /* primordial tilt                                   */
+  double sigma8;          /* top-hat 8 Mpc/h normalisation of P(k) at a = 1    */
+  int    gravity;         /* lpt2_gravity                                      */
+  double fr0_abs;         /* |f_R0| > 0 for LPT2_GRAV_FR_HS                    */
+  int    hs_n;            /* Hu-Sawicki n: must be 1                           */
+  double mu_const;        /* mu for LPT2_GRAV_MU_CONST                         */
+  int    factorisation;   /* lpt2_factorisation                                */
+  double tri_ratio;       /* k1/k2 for LPT2_D2_TRIANGLE, > 0                   */
+  double tri_theta_deg;   /* angle between k1 and k2, in (0, 180)              */
+  int    nk_growth;       /* growth-table nodes, 2..1023 (default 256)         */
+  double kmin, kmax;      /* node range in h/Mpc (default 1e-3, 10)            */
+  double a_init;          /* ODE start (default 1e-3)                          */
+  int    ode_steps;       /* fixed RK4 steps in ln a (default 4096)            */
+  int    precision;       /* lpt2_precision                                    */
+} lpt2_config;
+
+/* Fill *cfg with the defaults above (GR, 32^3, L = 128, Omega_m = 0.3,
+ * h = 0.7, n_s = 0.96, sigma8 = 0.8, EDS, FP64). */
+void lpt2_config_default(lpt2_config* cfg);
+
+/* Create a plan for n_cfgs grid configurations; counts[i] >= 1 realisations
+ * of cfgs[i] (counts may be NULL for one realisation each).  Validates every
+ * field on the host before any device work: n not a power of two in 8..512,
+ * hs_n != 1 or an unknown precision -> LPT2_EUNSUPPORTED; box <= 0,
+ * fr0_abs <= 0 for f(R), bad growth grid or null out -> LPT2_EINVAL.
+ * Allocates the workspace for the largest grid and the FP64 twiddles on the
+ * current device.  On failure *out is NULL. */
+lpt2_status lpt2_plan(const lpt2_config* cfgs, int n_cfgs, const int* counts, lpt2_plan_t* out);
+
+/* Release every device and host resource of the plan (NULL is a no-op). */
+lpt2_status lpt2_destroy(lpt2_plan_t plan);
+
+/* Total realisations held by the plan (sum of counts). */
+int lpt2_realisations(lpt2_plan_t plan);
+
+/* Grid size and precision of realisation r (0-based). */
+lpt2_status lpt2_realisation_info(lpt2_plan_t plan, int r, int* n, int* precision);
+
+/* Displacements at scale factor a > 0 (Sec. 3 procedure; eq. position):
+ *   delta(k) = F[w] sqrt(P(k) n^3/V) mask,
+ *   psi1     = F^-1[ i k D1(k,a)/k^2 delta(k) ],
+ *   S        = sum_{i<j} (phi_,ii phi_,jj - phi_,ij^2),  phi_,ij = F^-1[-k_i k_j/k^2 delta(k)]
+ *              (eq. second-ini, from the unevolved potential),
+ *   psi2     = F^-1[ D2(k,a) (-i k/k^2) F[S] mask ].
+ * noise[r], psi1[r], psi2[r] are device pointers for realisation r of the
+ * plan (arrays of lpt2_realisations() entries): noise [n][n][n] unit white
+ * noise; psi1 and psi2 [3][n][n][n] outputs.  The first call for a new a
+ * builds its growth tables on `stream` (FP64 RK4 on the GPU, then per-|m|^2
+ * tables) and caches them; later calls with the same a allocate nothing and
+ * never synchronise, so they can be captured in a hipGraph. */
+lpt2_status lpt2_displace(lpt2_plan_t plan, double a, const void* const* noise,
+                          void* const* psi1, void* const* psi2, void* stream);
+
+/* Shell-binned spectrum of the source for realisation 0 (Sec. 3: bin a
+ * per-mode quantity in k, report mean and 1-sigma scatter).
+ * quantity = LPT2_SPEC_POWER: q = V |S(k)/n^3|^2 of the displacement path's
+ * source.  quantity = LPT2_SPEC_RATIO: q = Re(S_MG conj S_GR)/|S_GR|^2 with
+ * S_MG = S1+S2+S3+S4 of eqs. full, s1-s4 (evolved with D1(k,a); S1 with the
+ * term -mu(k) F[phi_ij phi_ij] that its GR limit requires) and S_GR from the
+ * unevolved field; modes with S_GR = 0 are left out.
+ * nbins shells of width k_Nyq/nbins, integer-exact shell index
+ * isqrt(|m|^2 nbins^2 / (n/2)^2); weight 2 for 0 < m_z < n/2, else 1; DC and
+ * modes beyond the last shell are left out.  Writes nbins values to each host
+ * array: mean k, weighted count, mean q, population std of q (zeros for an
+ * empty shell).  Synchronises `stream` before returning.  nbins in 1..4096. */
+lpt2_status lpt2_source_spectrum(lpt2_plan_t plan, double a, const void* noise, int nbins,
+                                 int quantity, double* k_mean, double* count,
+                                 double* mean, double* std_dev, void* stream);
+
+/* Analytic MG/GR source ratio of triangle configurations at the wavenumbers
+ * k[0..nk) (Sec. 3, triangle comparison): R(k) = D1(k1) D1(k2) B / (D1_GR^2
+ * (1 - cos^2 theta)), B the braced factor of eq. full-d2; winther != 0 uses
+ * D1(k)^2.  Host arrays; growth tables as for lpt2_displace. */
+lpt2_status lpt2_triangle_ratio(lpt2_plan_t plan, double a, double ratio, double theta_deg,
+                                int winther, const double* k, int nk, double* out);
+
+/* Vector-Jacobian product of lpt2_displace: given g_psi1[r], g_psi2[r]
+ * (device, [3][n][n][n]) returns g_noise[r] = d/dw sum(g_psi1 psi1 + g_psi2 psi2)
+ * (device, [n][n][n]).  phi_,ij are recomputed from noise[r], not stored.
+ * Each linear block F^-1 M F is transposed as F^-1 conj(M) F; the quadratic
+ * source is differentiated by the product rule.  Same allocation and
+ * synchronisation rules as lpt2_displace. */
+lpt2_status lpt2_backward(lpt2_plan_t plan, double a, const void* const* noise,
+                          const void* const* g_psi1, const void* const* g_psi2,
+                          void* const* g_noise, void* stream);
+
+/* Cloud-in-cell density of the displaced particles of realisation 0:
+ * delta[g] = sum_p prod_axes max(0, 1 - |x_p - g L/n|/(L/n)) - 1, periodic,
+ * x_p = q_p + psi1_p + psi2_p.  delta is a device [n][n][n] output.  The
+ * float atomics make the summation order, and so the last bits, vary from
+ * run to run. */
+lpt2_status lpt2_paint_cic(lpt2_plan_t plan, const void* psi1, const void* psi2,
+                           void* delta, void* stream);
+
+/* Transpose of lpt2_paint_cic at the same displacements: g_psi [3][n][n][n]
+ * = d/dx_p sum_g g_delta[g] delta[g] (the same array serves as the gradient
+ * for psi1 and psi2).  Deterministic (a gather). */
+lpt2_status lpt2_paint_cic_backward(lpt2_plan_t plan, const void* psi1, const void* psi2,
+                                    const void* g_delta, void* g_psi, void* stream);
+
+/* Growth tables at a (host copies, nk_growth doubles each): node k, D1(k,a),
+ * D2(k,a), normalised so that D1(k -> 0, a = 1) = 1 (Sec. 2.4).  Synchronises. */
+lpt2_status lpt2_growth_table(lpt2_plan_t plan, double a, double* k, double* d1, double* d2);
+
+/* Test entry: 3D real FFT of realisation 0's grid in the library's internal
+ * spectral layout.  direction = -1: in is a real [n][n][n] field, out is
+ * complex [n][n][n/2] (interleaved re,im; the m_z = n/2 plane is not stored)
+ * holding the unnormalised F.  direction = +1: in is complex [n][n][n/2],
+ * taken as the half spectrum of a real field with a zero m_z = n/2 plane and
+ * real m_z = 0 column values; out is the real field n^3 F^-1 (unnormalised).
+ * Device pointers; `in` is left unchanged. */
+lpt2_status lpt2_fft3d(lpt2_plan_t plan, int direction, const void* in, void* out, void* stream);
+
+/* Per-kernel timing with HIP events on the calling stream.  enable != 0
+ * records an event pair around every kernel launch of later calls; the
+ * counters accumulate until lpt2_profile_reset.  lpt2_profile_get reports
+ * kernel i (0-based, i < lpt2_profile_count): its name (static storage),
+ * launches, summed milliseconds and algorithmic bytes per launch (the
+ * compulsory reads and writes of that kernel).  Synchronises. */
+lpt2_status lpt2_profile_enable(lpt2_plan_t plan, int enable);
+lpt2_status lpt2_profile_reset(lpt2_plan_t plan);
+int         lpt2_profile_count(lpt2_plan_t plan);
+lpt2_status lpt2_profile_get(lpt2_plan_t plan, int i, const char** name, long long* launches,
+                             double* total_ms, double* bytes_per_launch);
+
+/* Bytes of device workspace held by the plan. */
+long long lpt2_workspace_bytes(lpt2_plan_t plan);
+
+const char* lpt2_strerror(lpt2_status status);
+const char* lpt2_last_error(lpt2_plan_t plan);   /* "" if none; NULL plan: last plan-less error */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LPT2_H */

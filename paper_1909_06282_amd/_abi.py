@@ -1,0 +1,108 @@
+"""ctypes declarations of the C ABI in include/lpt2.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblpt2.so")
+
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
+FP64, FP32 = 0, 1
+GRAV_GR, GRAV_FR_HS, GRAV_MU_CONST = 0, 1, 2
+D2_EDS, D2_T1, D2_TRIANGLE, D2_WINTHER, D2_BOUCHET = 0, 1, 2, 3, 4
+SPEC_POWER, SPEC_RATIO = 0, 1
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("n", C.c_int),
+        ("box", C.c_double),
+        ("omega_m", C.c_double),
+        ("h", C.c_double),
+        ("n_s", C.c_double),
+        ("sigma8", C.c_double),
+        ("gravity", C.c_int),
+        ("fr0_abs", C.c_double),
+        ("hs_n", C.c_int),
+        ("mu_const", C.c_double),
+        ("factorisation", C.c_int),
+        ("tri_ratio", C.c_double),
+        ("tri_theta_deg", C.c_double),
+        ("nk_growth", C.c_int),
+        ("kmin", C.c_double),
+        ("kmax", C.c_double),
+        ("a_init", C.c_double),
+        ("ode_steps", C.c_int),
+        ("precision", C.c_int),
+    ]
+
+
+EXPORTS = [
+    "lpt2_config_default", "lpt2_plan", "lpt2_destroy", "lpt2_realisations", "lpt2_realisation_info",
+    "lpt2_displace", "lpt2_source_spectrum", "lpt2_triangle_ratio", "lpt2_backward", "lpt2_paint_cic",
+    "lpt2_paint_cic_backward", "lpt2_growth_table", "lpt2_fft3d", "lpt2_profile_enable",
+    "lpt2_profile_reset", "lpt2_profile_count", "lpt2_profile_get", "lpt2_workspace_bytes",
+    "lpt2_strerror", "lpt2_last_error",
+]
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load liblpt2.so from the package directory; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                           "or python -m paper_1909_06282_amd.build")
+    L = C.CDLL(LIB_PATH)
+    vp, vpp, dp, ip = C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_double), C.POINTER(C.c_int)
+    plan_t = C.c_void_p
+    L.lpt2_config_default.argtypes = [C.POINTER(Config)]
+    L.lpt2_config_default.restype = None
+    L.lpt2_plan.argtypes = [C.POINTER(Config), C.c_int, ip, C.POINTER(plan_t)]
+    L.lpt2_destroy.argtypes = [plan_t]
+    L.lpt2_realisations.argtypes = [plan_t]
+    L.lpt2_realisation_info.argtypes = [plan_t, C.c_int, ip, ip]
+    L.lpt2_displace.argtypes = [plan_t, C.c_double, vpp, vpp, vpp, vp]
+    L.lpt2_source_spectrum.argtypes = [plan_t, C.c_double, vp, C.c_int, C.c_int, dp, dp, dp, dp, vp]
+    L.lpt2_triangle_ratio.argtypes = [plan_t, C.c_double, C.c_double, C.c_double, C.c_int, dp, C.c_int, dp]
+    L.lpt2_backward.argtypes = [plan_t, C.c_double, vpp, vpp, vpp, vpp, vp]
+    L.lpt2_paint_cic.argtypes = [plan_t, vp, vp, vp, vp]
+    L.lpt2_paint_cic_backward.argtypes = [plan_t, vp, vp, vp, vp, vp]
+    L.lpt2_growth_table.argtypes = [plan_t, C.c_double, dp, dp, dp]
+    L.lpt2_fft3d.argtypes = [plan_t, C.c_int, vp, vp, vp]
+    L.lpt2_profile_enable.argtypes = [plan_t, C.c_int]
+    L.lpt2_profile_reset.argtypes = [plan_t]
+    L.lpt2_profile_count.argtypes = [plan_t]
+    L.lpt2_profile_get.argtypes = [plan_t, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_longlong), dp, dp]
+    L.lpt2_workspace_bytes.argtypes = [plan_t]
+    L.lpt2_workspace_bytes.restype = C.c_longlong
+    L.lpt2_strerror.argtypes = [C.c_int]
+    L.lpt2_strerror.restype = C.c_char_p
+    L.lpt2_last_error.argtypes = [plan_t]
+    L.lpt2_last_error.restype = C.c_char_p
+    for name in ("lpt2_plan", "lpt2_destroy", "lpt2_realisation_info", "lpt2_displace", "lpt2_source_spectrum",
+                 "lpt2_triangle_ratio", "lpt2_backward", "lpt2_paint_cic", "lpt2_paint_cic_backward",
+                 "lpt2_growth_table", "lpt2_fft3d", "lpt2_profile_enable", "lpt2_profile_reset",
+                 "lpt2_profile_get"):
+        getattr(L, name).restype = C.c_int
+    L.lpt2_realisations.restype = C.c_int
+    L.lpt2_profile_count.restype = C.c_int
+    _lib = L
+    return L
+
+
+class LPT2Error(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"lpt2 status {status}: {message}")
+        self.status = status
+
+
+def check(status: int, plan=None) -> None:
+    if status != OK:
+        L = load()
+        msg = L.lpt2_last_error(plan).decode() if plan is not None else L.lpt2_last_error(None).decode()
+        raise LPT2Error(status, msg or L.lpt2_strerror(status).decode())

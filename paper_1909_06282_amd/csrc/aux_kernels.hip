@@ -1,0 +1,434 @@
+// Auxiliary kernels: FP64 growth ODE, per-|m|^2 radial tables, the
+// deterministic shell binner, cloud-in-cell paint and its transpose, and
+// real-space helpers of the full modified-gravity source.
+#include <hip/hip_runtime.h>
+
+#include "cx.hpp"
+#include "kernels.hpp"
+
+namespace lpt2 {
+
+// ---------------------------------------------------------------------------
+// growth ODE: one thread per k node (eq. d1, eq. full-d2), one more for the
+// k = 0 normalisation run to a = 1; then normalised D1, D2 tables.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_growth(GrowthSetup g, double* __restrict__ d1n, double* __restrict__ d2n) {
+  __shared__ double s1[1024], s2[1024];
+  const int i = threadIdx.x;
+  if (i < g.nk) {
+    const double k = exp(g.lkmin + (g.lkmax - g.lkmin) * (double)i / (double)(g.nk - 1));
+    GrowthTri tri;
+    tri.k = k;
+    triangle(k, g.ratio, g.cs, tri.k1, tri.k2);
+    tri.cs = g.cs;
+    tri.bgr = 1.0 - g.cs * g.cs;
+    tri.winther = g.winther;
+    tri.with_d2 = (g.mode == 1);
+    double d1, d2;
+    growth_solve(g.c, tri, g.a_init, g.a, g.steps, d1, d2);
+    s1[i] = d1;
+    s2[i] = d2;
+  } else if (i == g.nk) {
+    GrowthTri tri;
+    tri.k = tri.k1 = tri.k2 = 0.0;
+    tri.cs = 0.0;
+    tri.bgr = 1.0;
+    tri.winther = 0;
+    tri.with_d2 = 0;
+    double d1, d2;
+    growth_solve(g.c, tri, g.a_init, 1.0, g.steps, d1, d2);
+    s1[i] = d1;
+  }
+  __syncthreads();
+  if (i < g.nk) {
+    const double norm = s1[g.nk];
+    const double d1v = s1[i] / norm;
+    double d2v;
+    if (g.mode == 1)
+      d2v = s2[i] / (norm * norm);
+    else if (g.mode == 0)
+      d2v = -3.0 / 7.0 * d1v * d1v;
+    else
+      d2v = -3.0 / 7.0 * d1v * d1v * pow(omega_m_a(g.c, g.a), -1.0 / 143.0);
+    d1n[i] = d1v;
+    d2n[i] = d2v;
+  }
+}
+
+hipError_t launch_growth(const GrowthSetup& g, double* d1n, double* d2n, hipStream_t s) {
+  if (g.nk < 2 || g.nk > 1023) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_growth, dim3(1), dim3(((g.nk + 1 + 63) / 64) * 64), 0, s, g, d1n, d2n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// radial tables per integer |m|^2 (FP64).  k = (2 pi/L) sqrt(n2),
+// A = sqrt(P(k) n^3 / V), 1/n^3 of the inverse DFT folded in:
+//   PSI1 = A D1 (L/2pi) / n2 / n^3    (times  i m_i)
+//   PHI  = A / n2 / n^3               (times -m_i m_j)
+//   PSI2 = D2 (L/2pi) / n2 / n^3      (times -i m_i)
+//   A    = A / n^3
+//   R1 = A D1/n2/n^3, R2 = A D1 mu/n2/n^3, R3 = A D1/Pi/n^3,
+//   R4 = (2pi/L)^2 A D1/Pi/n^3, R5 = (2pi/L) A D1/n^3, R6 = (2pi/L) A D1/Pi/n^3,
+//   C2 = -(G/2) mu, C4 = (2G/3)^2 (M2/12)(k^2/a^2)/Pi, C5 = -(2G/3)(m^2/(2a^2))/Pi.
+// ---------------------------------------------------------------------------
+__global__ void k_radial(RadialSetup r, const double* __restrict__ d1n, const double* __restrict__ d2n,
+                         double* __restrict__ tabs, long n2cnt) {
+  const long n2 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n2 >= n2cnt) return;
+  double v[TAB_COUNT];
+  for (int i = 0; i < TAB_COUNT; ++i) v[i] = 0.0;
+  if (n2 > 0) {
+    const double kf = 2.0 * kPi / r.box;
+    const double k = kf * sqrt((double)n2);
+    const double n3 = (double)r.n * (double)r.n * (double)r.n;
+    const double t = bbks(r.c, k);
+    const double p = r.amp * pow(k, r.c.ns) * t * t;
+    const double A = sqrt(p * n3 / (r.box * r.box * r.box));
+    const double d1 = interp_lnk(d1n, r.nk, r.lkmin, r.lkmax, k);
+    const double d2 = interp_lnk(d2n, r.nk, r.lkmin, r.lkmax, k);
+    const double inv = 1.0 / n3;
+    const double lf = r.box / (2.0 * kPi);
+    v[TAB_PSI1] = A * d1 * lf / (double)n2 * inv;
+    v[TAB_PHI] = A / (double)n2 * inv;
+    v[TAB_PSI2] = d2 * lf / (double)n2 * inv;
+    v[TAB_A] = A * inv;
+    const double ad = A * d1 * inv;
+    const double a = r.a;
+    const double m2 = (r.c.gravity == GRAV_FR) ? hs_m2(r.c, a) : 0.0;
+    const double mu = mu_of(r.c, k, a, m2);
+    const double G = four_pi_g_rho(r.c, a);
+    v[TAB_R1] = ad / (double)n2;
+    v[TAB_R2] = ad * mu / (double)n2;
+    v[TAB_C2] = -0.5 * G * mu;
+    if (r.c.gravity == GRAV_FR) {
+      const double pk = big_pi(k, a, m2);
+      v[TAB_R3] = ad / pk;
+      v[TAB_R4] = kf * kf * ad / pk;
+      v[TAB_R5] = kf * ad;
+      v[TAB_R6] = kf * ad / pk;
+      const double g3 = 2.0 * G / 3.0;
+      v[TAB_C4] = g3 * g3 * (hs_M2(r.c, a) / 12.0) * (k * k / (a * a)) / pk;
+      v[TAB_C5] = -g3 * (m2 / (2.0 * a * a)) / pk;
+    }
+  }
+  for (int i = 0; i < TAB_COUNT; ++i) tabs[i * n2cnt + n2] = v[i];
+}
+
+hipError_t launch_radial(const RadialSetup& r, const double* d1n, const double* d2n, double* tabs, long n2cnt,
+                         hipStream_t s) {
+  const long blocks = (n2cnt + 255) / 256;
+  hipLaunchKernelGGL(k_radial, dim3((unsigned)blocks), dim3(256), 0, s, r, d1n, d2n, tabs, n2cnt);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Shell binner.  Along z the shell index of a half-spectrum line is
+// non-decreasing, so a wave taking CH consecutive m_z of one line sees
+// sorted keys: a segmented inclusive scan (fixed shuffle tree) gives each
+// segment's sums in its last lane, which adds them to the wave's private LDS
+// histogram.  Waves walk a fixed list of chunks, blocks combine their waves
+// in a fixed order, and a second kernel sums the block partials in block
+// order with Neumaier compensation: the result is bitwise reproducible.
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_bin1(const Cx<T>* __restrict__ A, const Cx<T>* __restrict__ B, int quantity,
+                                              double qscale, int nbins, double kf, double* __restrict__ partial) {
+  constexpr int M = N / 2;
+  constexpr int CH = M < 64 ? M : 64;
+  constexpr int CPL = M / CH;  // chunks per line
+  __shared__ double hist[4][BIN_MAXBINS][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < 4 * BIN_MAXBINS * 4; i += blockDim.x) (&hist[0][0][0])[i] = 0.0;
+  __syncthreads();
+  const long nchunks = (long)N * N * CPL;
+  const long nw = (long)gridDim.x * 4;
+  const long nb2 = (long)nbins * nbins, h2 = (long)(N / 2) * (N / 2);
+  for (long ch = (long)blockIdx.x * 4 + wave; ch < nchunks; ch += nw) {
+    const long line = ch / CPL;
+    const int iz = (int)(ch % CPL) * CH + lane;
+    const int ix = (int)(line / N), iy = (int)(line % N);
+    const long mx = ix < N / 2 ? ix : ix - N, my = iy < N / 2 ? iy : iy - N;
+    int key = -1;
+    double w = 0.0, wk = 0.0, wq = 0.0, wq2 = 0.0;
+    if (lane < CH) {
+      const long n2 = mx * mx + my * my + (long)iz * iz;
+      const long v = (n2 * nb2) / h2;
+      long b = (long)sqrt((double)v);
+      while (b * b > v) --b;
+      while ((b + 1) * (b + 1) <= v) ++b;
+      if (n2 > 0 && b < nbins) {
+        const Cx<T> a = A[line * M + iz];
+        double q = 0.0;
+        bool ok = true;
+        if (quantity == 0) {
+          q = qscale * ((double)a.x * (double)a.x + (double)a.y * (double)a.y);
+        } else {
+          const Cx<T> bb = B[line * M + iz];
+          const double den = (double)bb.x * (double)bb.x + (double)bb.y * (double)bb.y;
+          ok = den > 0.0;
+          q = ok ? ((double)a.x * (double)bb.x + (double)a.y * (double)bb.y) / den : 0.0;
+        }
+        key = (int)b;  // a left-out mode keeps its key (with zero sums) so keys stay contiguous
+        if (ok) {
+          w = iz == 0 ? 1.0 : 2.0;
+          wk = w * kf * sqrt((double)n2);
+          wq = w * q;
+          wq2 = w * q * q;
+        }
+      }
+    }
+    // keys are non-decreasing along the chunk; -1 (DC, beyond the last shell)
+    // can only open or close it, so every key forms one contiguous segment.
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int ok_ = __shfl_up(key, off);
+      const double a0 = __shfl_up(w, off), a1 = __shfl_up(wk, off), a2 = __shfl_up(wq, off), a3 = __shfl_up(wq2, off);
+      if (lane >= off && ok_ == key) {
+        w += a0;
+        wk += a1;
+        wq += a2;
+        wq2 += a3;
+      }
+    }
+    const int next = __shfl_down(key, 1);
+    const bool tail = (lane == 63) || (next != key);
+    if (tail && key >= 0) {
+      double* hb = hist[wave][key];
+      hb[0] += w;
+      hb[1] += wk;
+      hb[2] += wq;
+      hb[3] += wq2;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nbins * 4; i += blockDim.x) {
+    const int b = i >> 2, c = i & 3;
+    partial[((long)blockIdx.x * nbins + b) * 4 + c] = ((hist[0][b][c] + hist[1][b][c]) + hist[2][b][c]) + hist[3][b][c];
+  }
+}
+
+__global__ void k_bin2(const double* __restrict__ partial, int nblk, int nbins, double* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbins) return;
+  double s[4], cmp[4];
+  for (int c = 0; c < 4; ++c) s[c] = cmp[c] = 0.0;
+  for (int k = 0; k < nblk; ++k) {
+    for (int c = 0; c < 4; ++c) {
+      const double x = partial[((long)k * nbins + b) * 4 + c];
+      const double tt = s[c] + x;
+      cmp[c] += (fabs(s[c]) >= fabs(x)) ? (s[c] - tt) + x : (x - tt) + s[c];
+      s[c] = tt;
+    }
+  }
+  for (int c = 0; c < 4; ++c) s[c] += cmp[c];
+  const double cnt = s[0];
+  double km = 0.0, mean = 0.0, sd = 0.0;
+  if (cnt > 0.0) {
+    km = s[1] / cnt;
+    mean = s[2] / cnt;
+    const double var = s[3] / cnt - mean * mean;
+    sd = sqrt(var > 0.0 ? var : 0.0);
+  }
+  out[0 * nbins + b] = km;
+  out[1 * nbins + b] = cnt;
+  out[2 * nbins + b] = mean;
+  out[3 * nbins + b] = sd;
+}
+
+template <typename T, int N>
+static hipError_t bin_t(const void* A, const void* B, int quantity, double qscale, int nbins, double kf,
+                        double* partial, double* out4, hipStream_t s) {
+  hipLaunchKernelGGL((k_bin1<T, N>), dim3(BIN_BLOCKS), dim3(256), 0, s, (const Cx<T>*)A, (const Cx<T>*)B, quantity,
+                     qscale, nbins, kf, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bin2, dim3((nbins + 63) / 64), dim3(64), 0, s, (const double*)partial, BIN_BLOCKS, nbins, out4);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(int prec, int n, const void* A, size_t a_cap, const void* B, size_t b_cap, int quantity,
+                      double qscale, int nbins, double kf, double* partial, double* out4, hipStream_t s) {
+  if (nbins < 1 || nbins > BIN_MAXBINS || !A || !partial || !out4) return hipErrorInvalidValue;
+  const size_t field = (size_t)n * n * (n / 2) * 2 * (prec == PREC_F32 ? 4 : 8);
+  if (a_cap < field || (quantity != 0 && (!B || b_cap < field))) return hipErrorInvalidValue;
+#define CALL(NN)                                                                                      \
+  return prec == PREC_F32 ? bin_t<float, NN>(A, B, quantity, qscale, nbins, kf, partial, out4, s)     \
+                          : bin_t<double, NN>(A, B, quantity, qscale, nbins, kf, partial, out4, s)
+  switch (n) {
+    case 8: CALL(8); case 16: CALL(16); case 32: CALL(32); case 64: CALL(64);
+    case 128: CALL(128); case 256: CALL(256); case 512: CALL(512);
+    default: return hipErrorInvalidValue;
+  }
+#undef CALL
+}
+
+// ---------------------------------------------------------------------------
+// Cloud-in-cell paint (scatter with atomics) and its transpose (gather).
+// Particle p = (ix,iy,iz) moves to u = (ix,iy,iz) + (psi1 + psi2)/cell in
+// cell units; per axis the two nearest nodes get 1 - f and f, f = u - floor(u).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_cic(int n, double inv_cell, const T* __restrict__ p1, const T* __restrict__ p2, T* __restrict__ rho) {
+  const long n3 = (long)n * n * n;
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n3) return;
+  const int ix = (int)(p / ((long)n * n)), iy = (int)((p / n) % n), iz = (int)(p % n);
+  const int id[3] = {ix, iy, iz};
+  int i0[3];
+  double f[3];
+  for (int c = 0; c < 3; ++c) {
+    const double u = (double)id[c] + ((double)p1[c * n3 + p] + (double)p2[c * n3 + p]) * inv_cell;
+    if (!(fabs(u) < 1e15)) return;  // non-finite or absurd displacement: the particle is not painted
+    const double fl = floor(u);
+    f[c] = u - fl;
+    long ii = (long)fl % n;
+    if (ii < 0) ii += n;
+    i0[c] = (int)ii;
+  }
+  for (int o = 0; o < 8; ++o) {
+    const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
+    const double w = (ox ? f[0] : 1.0 - f[0]) * (oy ? f[1] : 1.0 - f[1]) * (oz ? f[2] : 1.0 - f[2]);
+    const int gx = (i0[0] + ox) % n, gy = (i0[1] + oy) % n, gz = (i0[2] + oz) % n;
+    atomicAdd(&rho[((long)gx * n + gy) * n + gz], (T)w);
+  }
+}
+
+template <typename T>
+__global__ void k_cic_back(int n, double inv_cell, const T* __restrict__ p1, const T* __restrict__ p2,
+                           const T* __restrict__ gd, T* __restrict__ gp) {
+  const long n3 = (long)n * n * n;
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n3) return;
+  const int ix = (int)(p / ((long)n * n)), iy = (int)((p / n) % n), iz = (int)(p % n);
+  const int id[3] = {ix, iy, iz};
+  int i0[3];
+  double f[3];
+  for (int c = 0; c < 3; ++c) {
+    const double u = (double)id[c] + ((double)p1[c * n3 + p] + (double)p2[c * n3 + p]) * inv_cell;
+    if (!(fabs(u) < 1e15)) {  // same rule as the paint: the particle has no gradient
+      for (int q = 0; q < 3; ++q) gp[q * n3 + p] = (T)0;
+      return;
+    }
+    const double fl = floor(u);
+    f[c] = u - fl;
+    long ii = (long)fl % n;
+    if (ii < 0) ii += n;
+    i0[c] = (int)ii;
+  }
+  double g[3] = {0.0, 0.0, 0.0};
+  for (int o = 0; o < 8; ++o) {
+    const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
+    const double wx = ox ? f[0] : 1.0 - f[0], wy = oy ? f[1] : 1.0 - f[1], wz = oz ? f[2] : 1.0 - f[2];
+    const double dx = ox ? 1.0 : -1.0, dy = oy ? 1.0 : -1.0, dz = oz ? 1.0 : -1.0;
+    const int gx = (i0[0] + ox) % n, gy = (i0[1] + oy) % n, gz = (i0[2] + oz) % n;
+    const double v = (double)gd[((long)gx * n + gy) * n + gz];
+    g[0] += v * dx * wy * wz;
+    g[1] += v * wx * dy * wz;
+    g[2] += v * wx * wy * dz;
+  }
+  for (int c = 0; c < 3; ++c) gp[c * n3 + p] = (T)(g[c] * inv_cell);
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ x, long count, T value) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x) x[i] = value;
+}
+
+static unsigned grid_for(long count) {
+  long b = (count + 255) / 256;
+  return (unsigned)(b < 65536 ? (b > 0 ? b : 1) : 65536);
+}
+
+hipError_t launch_fill(int prec, void* x, long count, double value, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (prec == PREC_F32)
+    hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(count)), dim3(256), 0, s, (float*)x, count, (float)value);
+  else
+    hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(count)), dim3(256), 0, s, (double*)x, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_cic(int prec, int n, double box, const void* psi1, const void* psi2, void* delta, hipStream_t s) {
+  const long n3 = (long)n * n * n;
+  hipError_t e = launch_fill(prec, delta, n3, -1.0, s);
+  if (e != hipSuccess) return e;
+  const double ic = n / box;
+  const unsigned blocks = (unsigned)((n3 + 255) / 256);
+  if (prec == PREC_F32)
+    hipLaunchKernelGGL(k_cic<float>, dim3(blocks), dim3(256), 0, s, n, ic, (const float*)psi1, (const float*)psi2,
+                       (float*)delta);
+  else
+    hipLaunchKernelGGL(k_cic<double>, dim3(blocks), dim3(256), 0, s, n, ic, (const double*)psi1, (const double*)psi2,
+                       (double*)delta);
+  return hipGetLastError();
+}
+
+hipError_t launch_cic_back(int prec, int n, double box, const void* psi1, const void* psi2, const void* gdelta,
+                           void* gpsi, hipStream_t s) {
+  const long n3 = (long)n * n * n;
+  const double ic = n / box;
+  const unsigned blocks = (unsigned)((n3 + 255) / 256);
+  if (prec == PREC_F32)
+    hipLaunchKernelGGL(k_cic_back<float>, dim3(blocks), dim3(256), 0, s, n, ic, (const float*)psi1,
+                       (const float*)psi2, (const float*)gdelta, (float*)gpsi);
+  else
+    hipLaunchKernelGGL(k_cic_back<double>, dim3(blocks), dim3(256), 0, s, n, ic, (const double*)psi1,
+                       (const double*)psi2, (const double*)gdelta, (double*)gpsi);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// real-space accumulators of the full MG source
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_mg_pair(long count, T w, const T* __restrict__ pa, const T* __restrict__ pm,
+                          const T* __restrict__ c, T* __restrict__ r1, T* __restrict__ r2, T* __restrict__ r5,
+                          T* __restrict__ tr) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x) {
+    const T a = pa[i];
+    r1[i] += w * a * pm[i];
+    r2[i] += w * a * a;
+    if (c) r5[i] += T(2) * w * a * c[i];
+    if (tr) tr[i] += a;
+  }
+}
+template <typename T>
+__global__ void k_mg_dot(long count, const T* __restrict__ p, const T* __restrict__ q, T* __restrict__ r5) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x)
+    r5[i] += p[i] * q[i];
+}
+template <typename T>
+__global__ void k_square(long count, T* __restrict__ x) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x)
+    x[i] = x[i] * x[i];
+}
+
+hipError_t launch_mg_pair(int prec, long count, double w, const void* pa, const void* pm, const void* c, void* r1,
+                          void* r2, void* r5, void* tr, hipStream_t s) {
+  if (prec == PREC_F32)
+    hipLaunchKernelGGL(k_mg_pair<float>, dim3(grid_for(count)), dim3(256), 0, s, count, (float)w, (const float*)pa,
+                       (const float*)pm, (const float*)c, (float*)r1, (float*)r2, (float*)r5, (float*)tr);
+  else
+    hipLaunchKernelGGL(k_mg_pair<double>, dim3(grid_for(count)), dim3(256), 0, s, count, w, (const double*)pa,
+                       (const double*)pm, (const double*)c, (double*)r1, (double*)r2, (double*)r5, (double*)tr);
+  return hipGetLastError();
+}
+hipError_t launch_mg_dot(int prec, long count, const void* p, const void* q, void* r5, hipStream_t s) {
+  if (prec == PREC_F32)
+    hipLaunchKernelGGL(k_mg_dot<float>, dim3(grid_for(count)), dim3(256), 0, s, count, (const float*)p,
+                       (const float*)q, (float*)r5);
+  else
+    hipLaunchKernelGGL(k_mg_dot<double>, dim3(grid_for(count)), dim3(256), 0, s, count, (const double*)p,
+                       (const double*)q, (double*)r5);
+  return hipGetLastError();
+}
+hipError_t launch_square(int prec, long count, void* x, hipStream_t s) {
+  if (prec == PREC_F32)
+    hipLaunchKernelGGL(k_square<float>, dim3(grid_for(count)), dim3(256), 0, s, count, (float*)x);
+  else
+    hipLaunchKernelGGL(k_square<double>, dim3(grid_for(count)), dim3(256), 0, s, count, (double*)x);
+  return hipGetLastError();
+}
+
+}  // namespace lpt2

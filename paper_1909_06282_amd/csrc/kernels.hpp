@@ -1,0 +1,105 @@
+// Host-side launchers of the gfx950 kernels (one entry per kernel family;
+// each dispatches on precision and grid size).  Every launcher is
+// asynchronous on `s`, allocates nothing, and returns the launch status.
+// Each takes the capacity in bytes of every buffer it is given (counted
+// from the pointer passed) and refuses to launch, with
+// hipErrorInvalidValue, if the grid would touch a byte beyond it.
+//
+// Spectral layout used throughout: a half spectrum of an n^3 real field is
+// complex [n][n][n/2] (x slowest), i.e. the m_z = n/2 plane is not stored
+// (every spectrum on the path has it masked to zero).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "physics.hpp"
+
+namespace lpt2 {
+
+enum { PREC_F64 = 0, PREC_F32 = 1 };
+
+// Multiplier code of the fused x-pass.  The value applied to a mode
+// (m_x, m_y, m_z) with |m|^2 = n2 is
+//   scale * m_ci * m_cj * tables[table][n2]   (ci, cj, table < 0: factor 1)
+// times 1, +i or -i (kind 0, 1, 2), and zero on DC and Nyquist planes.
+enum { MUL_REAL = 0, MUL_PI = 1, MUL_MI = 2 };
+constexpr int XOP_MAX = 12;
+struct XOp {
+  int nin, nout;   // nin == 1 (one input, nout outputs) or nout == 1 (sum over nin inputs)
+  int inverse;     // 1: inverse x-FFT after the multiply; 0: store the k-space values
+  int kind[XOP_MAX], ci[XOP_MAX], cj[XOP_MAX], table[XOP_MAX];
+  double scale[XOP_MAX];
+  const double* tables[16];
+};
+
+// z axis (contiguous): nlines lines of n reals <-> n/2 complex
+hipError_t launch_zr2c(int prec, int n, const void* in, size_t in_cap, void* out, size_t out_cap, long nlines,
+                       const void* tw, hipStream_t s);
+hipError_t launch_zc2r(int prec, int n, const void* in, size_t in_cap, void* out, size_t out_cap, long nlines,
+                       const void* tw, hipStream_t s);
+// strided complex column FFT in place: nplanes planes of ncols columns,
+// element (row, col) of plane p at data + p*plane_stride + row*rowstride + col
+hipError_t launch_colfft(int prec, int n, int dir, void* data, size_t cap, long nplanes, long plane_stride,
+                         int ncols, long rowstride, const void* tw, hipStream_t s);
+// fused x pass over the n*(n/2) columns of each field
+hipError_t launch_xpass(int prec, int n, const void* in, size_t in_cap, long in_fstride, void* out, size_t out_cap,
+                        long out_fstride, const XOp& op, long n2cnt, const void* tw, hipStream_t s);
+// z pass: 6 phi_,ij half-spectrum lines (xx,yy,zz,xy,xz,yz at fstride) -> S(k) line
+hipError_t launch_zsource(int prec, int n, const void* phi, size_t phi_cap, long fstride, void* sk, size_t sk_cap,
+                          long nlines, const void* tw, hipStream_t s);
+// z pass of the adjoint: 6 phi lines + real S_bar line -> 6 phi_bar half-spectrum lines
+hipError_t launch_zprodrule(int prec, int n, const void* phi, size_t phi_cap, long fstride, const void* sbar,
+                            size_t sbar_cap, void* out, size_t out_cap, long out_fstride, long nlines, const void* tw,
+                            hipStream_t s);
+
+// ---- auxiliary kernels (aux_kernels.hip) ----
+struct GrowthSetup {
+  Cosmo c;
+  double a_init, a;
+  int steps, nk;
+  double lkmin, lkmax;
+  double ratio, cs;     // triangle k1/k2 and cos(theta)
+  int winther;
+  int mode;             // 0: D2 = -3/7 D1^2; 1: D2 from the ODE; 2: Bouchet fit
+};
+// one block: raw ODE solves on the nk nodes and at k = 0, then normalised tables
+hipError_t launch_growth(const GrowthSetup& g, double* d1n, double* d2n, hipStream_t s);
+
+enum {
+  TAB_PSI1 = 0, TAB_PHI, TAB_PSI2, TAB_A, TAB_R1, TAB_R2, TAB_R3, TAB_R4, TAB_R5, TAB_R6,
+  TAB_C2, TAB_C4, TAB_C5, TAB_COUNT
+};
+struct RadialSetup {
+  Cosmo c;
+  int n;
+  double box, amp, a;
+  int nk;
+  double lkmin, lkmax;
+};
+// per-|m|^2 FP64 tables, TAB_COUNT arrays of n2max + 1 = 3 (n/2)^2 + 1 entries
+hipError_t launch_radial(const RadialSetup& r, const double* d1n, const double* d2n, double* tabs, long n2cnt,
+                         hipStream_t s);
+
+// deterministic shell binner: quantity 0 power (q = qscale |A|^2), 1 ratio
+// (q = Re(A conj B)/|B|^2 where |B| > 0).  partial: [nblk][nbins][4].
+constexpr int BIN_BLOCKS = 512;
+constexpr int BIN_MAXBINS = 512;
+hipError_t launch_bin(int prec, int n, const void* A, size_t a_cap, const void* B, size_t b_cap, int quantity,
+                      double qscale, int nbins, double kf, double* partial, double* out4, hipStream_t s);
+
+hipError_t launch_cic(int prec, int n, double box, const void* psi1, const void* psi2, void* delta, hipStream_t s);
+hipError_t launch_cic_back(int prec, int n, double box, const void* psi1, const void* psi2, const void* gdelta,
+                           void* gpsi, hipStream_t s);
+
+// real-space helpers of the full modified-gravity source
+// (each pointer given to these must hold at least `count` values; the
+// caller checks that, the buffers being whole fields)
+hipError_t launch_fill(int prec, void* x, long count, double value, hipStream_t s);
+// r1 += w pa pm; r2 += w pa^2; r5 += 2 w pa c (if c); tr += pa (if tr)
+hipError_t launch_mg_pair(int prec, long count, double w, const void* pa, const void* pm, const void* c, void* r1,
+                          void* r2, void* r5, void* tr, hipStream_t s);
+// r5 += p q
+hipError_t launch_mg_dot(int prec, long count, const void* p, const void* q, void* r5, hipStream_t s);
+// x = x * x
+hipError_t launch_square(int prec, long count, void* x, hipStream_t s);
+
+}  // namespace lpt2

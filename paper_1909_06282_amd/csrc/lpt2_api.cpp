@@ -1,0 +1,914 @@
+// Host side of the C ABI declared in include/lpt2.h: argument validation,
+// the plan (workspace, twiddles, growth-table cache), the kernel sequences of
+// each entry point, and per-kernel event timing.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lpt2.h"
+#include "kernels.hpp"
+
+using namespace lpt2;
+
+namespace {
+
+thread_local std::string g_err;  // errors without a plan
+
+struct Tables {
+  double a = 0.0;
+  double* d1n = nullptr;   // nk normalised D1 on the nodes
+  double* d2n = nullptr;   // nk normalised D2 on the nodes
+  double* radial = nullptr;  // TAB_COUNT x n2cnt
+};
+
+struct Grid {
+  lpt2_config cfg;
+  int count = 1;
+  int n = 0;
+  long m = 0, nnm = 0, n3 = 0, n2cnt = 0;
+  Cosmo c;
+  double amp = 0.0, lkmin = 0.0, lkmax = 0.0;
+  void* tw = nullptr;
+  std::vector<Tables> tables;
+  std::vector<Tables> gr_tables;  // GR growth at a (for S_GR and the triangle ratios)
+};
+
+struct ProfEntry {
+  const char* name;
+  long long launches;
+  double ms;
+  double bytes;
+};
+
+}  // namespace
+
+struct lpt2_plan_s {
+  std::vector<Grid> grids;
+  std::vector<int> rgrid;  // realisation -> grid
+  int prec = PREC_F64;
+  size_t es = 8;           // bytes per real scalar
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  double* bin_partial = nullptr;
+  double* bin_out = nullptr;
+  std::string err;
+  std::atomic<int> busy{0};
+  bool prof = false;
+  std::vector<ProfEntry> prof_tab;
+  struct Pending { int idx; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+constexpr int WS_FIELDS = 12;  // half-spectrum-sized slots in the workspace
+
+lpt2_status fail(lpt2_plan_t p, lpt2_status st, const std::string& msg) {
+  if (p)
+    p->err = msg;
+  else
+    g_err = msg;
+  return st;
+}
+
+lpt2_status hip_fail(lpt2_plan_t p, hipError_t e, const char* what) {
+  return fail(p, LPT2_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct Busy {
+  lpt2_plan_t p;
+  bool ok;
+  explicit Busy(lpt2_plan_t q) : p(q) {
+    int z = 0;
+    ok = p->busy.compare_exchange_strong(z, 1);
+  }
+  ~Busy() {
+    if (ok) p->busy.store(0);
+  }
+};
+
+bool pow2_in_range(int n) { return n >= 8 && n <= 512 && (n & (n - 1)) == 0; }
+
+// sigma8 normalisation: A = sigma8^2 / [(1/2 pi^2) Int k^3 k^ns T^2 W^2(8k) dln k],
+// composite Simpson on ln k in [ln 1e-5, ln 1e3] with 2^16 intervals.
+double sigma8_amplitude(const Cosmo& c, double sigma8) {
+  const int nint = 1 << 16;
+  const double lo = std::log(1e-5), hi = std::log(1e3), h = (hi - lo) / nint;
+  auto f = [&](int i) {
+    const double k = std::exp(lo + (hi - lo) * (double)i / (double)nint);
+    const double t = bbks(c, k);
+    const double x = 8.0 * k;
+    const double w = 3.0 * (std::sin(x) - x * std::cos(x)) / (x * x * x);
+    return k * k * k * std::pow(k, c.ns) * t * t * w * w / (2.0 * kPi * kPi);
+  };
+  double s = f(0) + f(nint), s4 = 0.0, s2 = 0.0;
+  for (int i = 1; i < nint; i += 2) s4 += f(i);
+  for (int i = 2; i < nint; i += 2) s2 += f(i);
+  s += 4.0 * s4 + 2.0 * s2;
+  return sigma8 * sigma8 / (s * h / 3.0);
+}
+
+lpt2_status validate(const lpt2_config& c, std::string& why) {
+  if (!pow2_in_range(c.n)) {
+    why = "n must be a power of two in 8..512";
+    return LPT2_EUNSUPPORTED;
+  }
+  if (c.precision != LPT2_FP64 && c.precision != LPT2_FP32) {
+    why = "unknown precision";
+    return LPT2_EUNSUPPORTED;
+  }
+  if (!(c.box > 0.0) || !std::isfinite(c.box)) { why = "box must be > 0"; return LPT2_EINVAL; }
+  if (!(c.omega_m > 0.0 && c.omega_m <= 1.0)) { why = "omega_m must be in (0, 1]"; return LPT2_EINVAL; }
+  if (!(c.h > 0.0) || !(c.sigma8 > 0.0) || !std::isfinite(c.n_s)) { why = "h, sigma8 must be > 0"; return LPT2_EINVAL; }
+  if (c.gravity < 0 || c.gravity > 2) { why = "unknown gravity model"; return LPT2_EINVAL; }
+  if (c.gravity == LPT2_GRAV_FR_HS) {
+    if (!(c.fr0_abs > 0.0)) { why = "fr0_abs must be > 0 for f(R)"; return LPT2_EINVAL; }
+    if (c.hs_n != 1) { why = "only Hu-Sawicki n = 1 has its M_k coefficients given"; return LPT2_EUNSUPPORTED; }
+  }
+  if (c.gravity == LPT2_GRAV_MU_CONST && !(c.mu_const > 0.0)) { why = "mu_const must be > 0"; return LPT2_EINVAL; }
+  if (c.factorisation < 0 || c.factorisation > 4) { why = "unknown factorisation"; return LPT2_EINVAL; }
+  if (c.factorisation == LPT2_D2_TRIANGLE &&
+      (!(c.tri_ratio > 0.0) || !(c.tri_theta_deg > 0.0 && c.tri_theta_deg < 180.0))) {
+    why = "triangle needs ratio > 0 and 0 < theta < 180";
+    return LPT2_EINVAL;
+  }
+  if (c.nk_growth < 2 || c.nk_growth > 1023) { why = "nk_growth must be in 2..1023"; return LPT2_EINVAL; }
+  if (!(c.kmin > 0.0) || !(c.kmax > c.kmin)) { why = "need 0 < kmin < kmax"; return LPT2_EINVAL; }
+  if (!(c.a_init > 0.0 && c.a_init < 1.0)) { why = "a_init must be in (0, 1)"; return LPT2_EINVAL; }
+  if (c.ode_steps < 1 || c.ode_steps > (1 << 24)) { why = "ode_steps must be in 1..2^24"; return LPT2_EINVAL; }
+  return LPT2_OK;
+}
+
+double cos_deg(double th) { return th == 90.0 ? 0.0 : std::cos(th * kPi / 180.0); }
+
+// ---- profiling ---------------------------------------------------------------
+int prof_slot(lpt2_plan_t p, const char* name, double bytes) {
+  for (size_t i = 0; i < p->prof_tab.size(); ++i)
+    if (p->prof_tab[i].name == name) return (int)i;
+  p->prof_tab.push_back({name, 0, 0.0, bytes});
+  return (int)p->prof_tab.size() - 1;
+}
+hipEvent_t take_event(lpt2_plan_t p) {
+  if (!p->pool.empty()) {
+    hipEvent_t e = p->pool.back();
+    p->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+void prof_flush(lpt2_plan_t p) {
+  for (auto& q : p->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(q.b) == hipSuccess && hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess)
+      p->prof_tab[q.idx].ms += ms;
+    p->pool.push_back(q.a);
+    p->pool.push_back(q.b);
+  }
+  p->pending.clear();
+}
+
+// Runs one launch, recording an event pair around it in profiling mode.
+template <class F>
+lpt2_status run(lpt2_plan_t p, hipStream_t s, const char* name, double bytes, F&& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  int idx = -1;
+  if (p->prof) {
+    idx = prof_slot(p, name, bytes);
+    a = take_event(p);
+    b = take_event(p);
+    if (a) (void)hipEventRecord(a, s);
+  }
+  hipError_t e = launch();
+  if (e != hipSuccess) return hip_fail(p, e, name);
+  if (p->prof && a && b) {
+    (void)hipEventRecord(b, s);
+    p->pending.push_back({idx, a, b});
+    p->prof_tab[idx].launches++;
+  }
+  return LPT2_OK;
+}
+#define RUN(name, bytes, expr)                                              \
+  do {                                                                      \
+    lpt2_status st_ = run(p, s, name, (double)(bytes), [&]() { return (expr); }); \
+    if (st_ != LPT2_OK) return st_;                                         \
+  } while (0)
+
+// ---- growth tables -------------------------------------------------------------
+lpt2_status build_tables(lpt2_plan_t p, Grid& g, double a, bool gr, hipStream_t s, Tables& out) {
+  const lpt2_config& cf = g.cfg;
+  Tables t;
+  t.a = a;
+  const int nk = cf.nk_growth;
+  hipError_t e = hipMalloc((void**)&t.d1n, sizeof(double) * nk * 2);
+  if (e != hipSuccess) return fail(p, LPT2_ENOMEM, "growth table allocation failed");
+  t.d2n = t.d1n + nk;
+  GrowthSetup gs;
+  gs.c = g.c;
+  if (gr) gs.c.gravity = GRAV_GR;
+  gs.a_init = cf.a_init;
+  gs.a = a;
+  gs.steps = cf.ode_steps;
+  gs.nk = nk;
+  gs.lkmin = g.lkmin;
+  gs.lkmax = g.lkmax;
+  gs.winther = 0;
+  gs.ratio = 1.0;
+  gs.cs = 0.0;
+  switch (gr ? LPT2_D2_EDS : cf.factorisation) {
+    case LPT2_D2_EDS: gs.mode = 0; break;
+    case LPT2_D2_BOUCHET: gs.mode = 2; break;
+    case LPT2_D2_TRIANGLE:
+      gs.mode = 1;
+      gs.ratio = cf.tri_ratio;
+      gs.cs = cos_deg(cf.tri_theta_deg);
+      break;
+    case LPT2_D2_WINTHER: gs.mode = 1; gs.winther = 1; break;
+    default: gs.mode = 1; break;  // T1
+  }
+  lpt2_status st = run(p, s, "growth_ode", 0.0, [&]() { return launch_growth(gs, t.d1n, t.d2n, s); });
+  if (st != LPT2_OK) {
+    (void)hipFree(t.d1n);
+    return st;
+  }
+  if (!gr) {
+    e = hipMalloc((void**)&t.radial, sizeof(double) * TAB_COUNT * g.n2cnt);
+    if (e != hipSuccess) {
+      (void)hipFree(t.d1n);
+      return fail(p, LPT2_ENOMEM, "radial table allocation failed");
+    }
+    RadialSetup rs;
+    rs.c = g.c;
+    rs.n = g.n;
+    rs.box = cf.box;
+    rs.amp = g.amp;
+    rs.a = a;
+    rs.nk = nk;
+    rs.lkmin = g.lkmin;
+    rs.lkmax = g.lkmax;
+    st = run(p, s, "radial_tables", 0.0, [&]() { return launch_radial(rs, t.d1n, t.d2n, t.radial, g.n2cnt, s); });
+    if (st != LPT2_OK) {
+      (void)hipFree(t.d1n);
+      (void)hipFree(t.radial);
+      return st;
+    }
+  }
+  out = t;
+  return LPT2_OK;
+}
+
+lpt2_status get_tables(lpt2_plan_t p, Grid& g, double a, bool gr, hipStream_t s, Tables** out) {
+  std::vector<Tables>& cache = gr ? g.gr_tables : g.tables;
+  for (auto& t : cache)
+    if (t.a == a) {
+      *out = &t;
+      return LPT2_OK;
+    }
+  if (cache.size() >= 32) {  // drop the oldest entry once its users are done
+    (void)hipStreamSynchronize(s);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(cache.front().d1n);
+    if (cache.front().radial) (void)hipFree(cache.front().radial);
+    cache.erase(cache.begin());
+  }
+  Tables t;
+  lpt2_status st = build_tables(p, g, a, gr, s, t);
+  if (st != LPT2_OK) return st;
+  cache.push_back(t);
+  *out = &cache.back();
+  return LPT2_OK;
+}
+
+// ---- x-pass operators ---------------------------------------------------------
+const int PI_[6] = {0, 1, 2, 0, 0, 1}, PJ_[6] = {0, 1, 2, 1, 2, 2};
+
+XOp op_blank(int nin, int nout, int inverse) {
+  XOp op;
+  std::memset(&op, 0, sizeof(op));
+  op.nin = nin;
+  op.nout = nout;
+  op.inverse = inverse;
+  for (int i = 0; i < XOP_MAX; ++i) {
+    op.ci[i] = op.cj[i] = op.table[i] = -1;
+    op.scale[i] = 1.0;
+    op.kind[i] = MUL_REAL;
+  }
+  return op;
+}
+void op_set(XOp& op, int c, int kind, int ci, int cj, int table, double scale) {
+  op.kind[c] = kind;
+  op.ci[c] = ci;
+  op.cj[c] = cj;
+  op.table[c] = table;
+  op.scale[c] = scale;
+}
+void op_tables(XOp& op, const Grid& g, const Tables* t) {
+  for (int i = 0; i < TAB_COUNT; ++i) op.tables[i] = t->radial + (long)i * g.n2cnt;
+}
+
+// ---- pipeline pieces ------------------------------------------------------------
+// Workspace slot i holds one half spectrum (n*n*(n/2) complex = one real
+// n^3 field).  Every launch passes the capacity of each buffer: for a slot,
+// the bytes to the end of the workspace; for a caller's field, its
+// documented size.
+struct Ctx {
+  lpt2_plan_t p;
+  Grid& g;
+  hipStream_t s;
+  size_t cs;  // bytes per complex
+  char* slot(int i) const { return p->ws + (size_t)i * g.nnm * cs; }
+  size_t cap(const void* ptr) const {  // bytes from a workspace pointer to the workspace end
+    const char* q = (const char*)ptr;
+    return (q >= p->ws && q < p->ws + p->ws_bytes) ? (size_t)(p->ws + p->ws_bytes - q) : 0;
+  }
+  size_t field() const { return (size_t)g.n3 * p->es; }  // bytes of one real field
+};
+
+// forward z and y passes of `nf` real fields at `in` into spectral slots
+lpt2_status fwd_zy(Ctx& c, const char* nz, const char* ny, const void* in, size_t in_cap, void* out, int nf) {
+  lpt2_plan_t p = c.p;
+  hipStream_t s = c.s;
+  Grid& g = c.g;
+  const double fb = (double)c.field();
+  RUN(nz, 2.0 * fb * nf, launch_zr2c(p->prec, g.n, in, in_cap, out, c.cap(out), (long)nf * g.n * g.n, g.tw, s));
+  RUN(ny, 2.0 * fb * nf,
+      launch_colfft(p->prec, g.n, -1, out, c.cap(out), (long)nf * g.n, g.n * g.m, (int)g.m, g.m, g.tw, s));
+  return LPT2_OK;
+}
+lpt2_status inv_y(Ctx& c, const char* ny, void* data, int nf) {
+  lpt2_plan_t p = c.p;
+  hipStream_t s = c.s;
+  Grid& g = c.g;
+  const double fb = (double)c.field();
+  RUN(ny, 2.0 * fb * nf,
+      launch_colfft(p->prec, g.n, +1, data, c.cap(data), (long)nf * g.n, g.n * g.m, (int)g.m, g.m, g.tw, s));
+  return LPT2_OK;
+}
+lpt2_status fwd_y(Ctx& c, const char* ny, void* data, int nf) {
+  lpt2_plan_t p = c.p;
+  hipStream_t s = c.s;
+  Grid& g = c.g;
+  const double fb = (double)c.field();
+  RUN(ny, 2.0 * fb * nf,
+      launch_colfft(p->prec, g.n, -1, data, c.cap(data), (long)nf * g.n, g.n * g.m, (int)g.m, g.m, g.tw, s));
+  return LPT2_OK;
+}
+lpt2_status xp(Ctx& c, const char* name, const void* in, void* out, const XOp& op) {
+  lpt2_plan_t p = c.p;
+  hipStream_t s = c.s;
+  Grid& g = c.g;
+  const double fb = (double)c.field();
+  const long fst = g.nnm;
+  RUN(name, fb * (op.nin + op.nout),
+      launch_xpass(p->prec, g.n, in, c.cap(in), fst, out, c.cap(out), fst, op, g.n2cnt, g.tw, s));
+  return LPT2_OK;
+}
+lpt2_status z_c2r(Ctx& c, const char* name, const void* in, void* out, size_t out_cap, int nf) {
+  lpt2_plan_t p = c.p;
+  hipStream_t s = c.s;
+  Grid& g = c.g;
+  const double fb = (double)c.field();
+  RUN(name, 2.0 * fb * nf, launch_zc2r(p->prec, g.n, in, c.cap(in), out, out_cap, (long)nf * g.n * g.n, g.tw, s));
+  return LPT2_OK;
+}
+lpt2_status z_source(Ctx& c, const void* phi, void* sk) {
+  lpt2_plan_t p = c.p;
+  hipStream_t s = c.s;
+  Grid& g = c.g;
+  RUN("z_fused_source", (double)c.field() * 7.0,
+      launch_zsource(p->prec, g.n, phi, c.cap(phi), g.nnm, sk, c.cap(sk), (long)g.n * g.n, g.tw, s));
+  return LPT2_OK;
+}
+#define CHK(x)                      \
+  do {                              \
+    lpt2_status st_ = (x);          \
+    if (st_ != LPT2_OK) return st_; \
+  } while (0)
+
+// psi1, psi2 of one realisation (see lpt2_displace); slots 0..10
+lpt2_status displace_one(Ctx& c, const Tables* t, const void* noise, void* psi1, void* psi2) {
+  Grid& g = c.g;
+  CHK(fwd_zy(c, "z_r2c_noise", "y_fwd_noise", noise, c.field(), c.slot(0), 1));
+  XOp op = op_blank(1, 9, 1);
+  op_tables(op, g, t);
+  for (int i = 0; i < 3; ++i) op_set(op, i, MUL_PI, i, -1, TAB_PSI1, 1.0);
+  for (int q = 0; q < 6; ++q) op_set(op, 3 + q, MUL_REAL, PI_[q], PJ_[q], TAB_PHI, -1.0);
+  CHK(xp(c, "x_fused_psi1_phi", c.slot(0), c.slot(1), op));
+  CHK(inv_y(c, "y_inv_psi1_phi", c.slot(1), 9));
+  CHK(z_c2r(c, "z_c2r_psi1", c.slot(1), psi1, 3 * c.field(), 3));
+  CHK(z_source(c, c.slot(4), c.slot(10)));
+  CHK(fwd_y(c, "y_fwd_source", c.slot(10), 1));
+  XOp o2 = op_blank(1, 3, 1);
+  op_tables(o2, g, t);
+  for (int i = 0; i < 3; ++i) op_set(o2, i, MUL_MI, i, -1, TAB_PSI2, 1.0);
+  CHK(xp(c, "x_fused_psi2", c.slot(10), c.slot(1), o2));
+  CHK(inv_y(c, "y_inv_psi2", c.slot(1), 3));
+  CHK(z_c2r(c, "z_c2r_psi2", c.slot(1), psi2, 3 * c.field(), 3));
+  return LPT2_OK;
+}
+
+// S(k) of the displacement path, k-space, masked, times `scale`, into slot
+// `dst` (uses slots 0..6 and 10)
+lpt2_status source_k(Ctx& c, const Tables* t, const void* noise, int dst, double scale) {
+  Grid& g = c.g;
+  CHK(fwd_zy(c, "z_r2c_noise", "y_fwd_noise", noise, c.field(), c.slot(0), 1));
+  XOp op = op_blank(1, 6, 1);
+  op_tables(op, g, t);
+  for (int q = 0; q < 6; ++q) op_set(op, q, MUL_REAL, PI_[q], PJ_[q], TAB_PHI, -1.0);
+  CHK(xp(c, "x_fused_phi", c.slot(0), c.slot(1), op));
+  CHK(inv_y(c, "y_inv_phi", c.slot(1), 6));
+  CHK(z_source(c, c.slot(1), c.slot(10)));
+  CHK(fwd_y(c, "y_fwd_source", c.slot(10), 1));
+  XOp o = op_blank(1, 1, 0);
+  op_set(o, 0, MUL_REAL, -1, -1, -1, scale);
+  CHK(xp(c, "x_fwd_source", c.slot(10), c.slot(dst), o));
+  return LPT2_OK;
+}
+
+// S_MG(k) = S1+S2+S3+S4 into slot 10 (uses slots 0..10)
+lpt2_status mg_source_k(Ctx& c, const Tables* t, const void* noise) {
+  lpt2_plan_t p = c.p;
+  hipStream_t s = c.s;
+  Grid& g = c.g;
+  const long cnt = g.n3;
+  const bool fr = g.c.gravity == GRAV_FR;
+  if (c.cap(c.slot(10)) < 2 * c.field()) return fail(p, LPT2_EINVAL, "workspace too small");
+  CHK(fwd_zy(c, "z_r2c_noise", "y_fwd_noise", noise, c.field(), c.slot(0), 1));
+  // accumulators (real fields stored in spectral slots): R1 5, R2 6, tr->R3 7, R5 8, chi^2 9
+  for (int i = 5; i <= 9; ++i) RUN("fill", 0.0, launch_fill(p->prec, c.slot(i), cnt, 0.0, s));
+  for (int q = 0; q < 6; ++q) {
+    const int i = PI_[q], j = PJ_[q];
+    XOp op = op_blank(1, fr ? 3 : 2, 1);
+    op_tables(op, g, t);
+    op_set(op, 0, MUL_REAL, i, j, TAB_R1, -1.0);
+    op_set(op, 1, MUL_REAL, i, j, TAB_R2, -1.0);
+    if (fr) op_set(op, 2, MUL_REAL, i, j, TAB_R4, -1.0);
+    CHK(xp(c, "x_mg_phi", c.slot(0), c.slot(1), op));
+    CHK(inv_y(c, "y_inv_mg", c.slot(1), op.nout));
+    CHK(z_c2r(c, "z_c2r_mg", c.slot(1), c.slot(1), c.cap(c.slot(1)), op.nout));  // in place
+    const double w = (i == j) ? 1.0 : 2.0;
+    RUN("mg_pair", 0.0,
+        launch_mg_pair(p->prec, cnt, w, c.slot(1), c.slot(2), fr ? c.slot(3) : nullptr, c.slot(5), c.slot(6),
+                       fr ? c.slot(8) : nullptr, i == j ? c.slot(7) : nullptr, s));
+  }
+  RUN("square", 0.0, launch_square(p->prec, cnt, c.slot(7), s));
+  if (fr) {
+    for (int j = 0; j < 3; ++j) {
+      XOp op = op_blank(1, 2, 1);
+      op_tables(op, g, t);
+      op_set(op, 0, MUL_MI, j, -1, TAB_R5, 1.0);
+      op_set(op, 1, MUL_PI, j, -1, TAB_R6, 1.0);
+      CHK(xp(c, "x_mg_grad", c.slot(0), c.slot(1), op));
+      CHK(inv_y(c, "y_inv_mg", c.slot(1), 2));
+      CHK(z_c2r(c, "z_c2r_mg", c.slot(1), c.slot(1), c.cap(c.slot(1)), 2));
+      RUN("mg_dot", 0.0, launch_mg_dot(p->prec, cnt, c.slot(1), c.slot(2), c.slot(8), s));
+    }
+    XOp op = op_blank(1, 1, 1);
+    op_tables(op, g, t);
+    op_set(op, 0, MUL_REAL, -1, -1, TAB_R3, 1.0);
+    CHK(xp(c, "x_mg_chi", c.slot(0), c.slot(9), op));
+    CHK(inv_y(c, "y_inv_mg", c.slot(9), 1));
+    CHK(z_c2r(c, "z_c2r_mg", c.slot(9), c.slot(9), c.cap(c.slot(9)), 1));
+    RUN("square", 0.0, launch_square(p->prec, cnt, c.slot(9), s));
+  }
+  const int nr = fr ? 5 : 3;
+  CHK(fwd_zy(c, "z_r2c_mg", "y_fwd_mg", c.slot(5), c.cap(c.slot(5)), c.slot(5), nr));
+  const double G = four_pi_g_rho(g.c, t->a);
+  XOp op = op_blank(nr, 1, 0);
+  op_tables(op, g, t);
+  op_set(op, 0, MUL_REAL, -1, -1, -1, G);       // F R1
+  op_set(op, 1, MUL_REAL, -1, -1, TAB_C2, 1.0);  // F R2
+  op_set(op, 2, MUL_REAL, -1, -1, TAB_C2, 1.0);  // F (tr phi)^2
+  if (fr) {
+    op_set(op, 3, MUL_REAL, -1, -1, TAB_C5, 1.0);  // F R5
+    op_set(op, 4, MUL_REAL, -1, -1, TAB_C4, 1.0);  // F chi^2
+  }
+  CHK(xp(c, "x_fwd_mg", c.slot(5), c.slot(10), op));
+  return LPT2_OK;
+}
+
+// slots 0..10
+lpt2_status backward_one(Ctx& c, const Tables* t, const void* noise, const void* g1, const void* g2, void* gw) {
+  lpt2_plan_t p = c.p;
+  hipStream_t s = c.s;
+  Grid& g = c.g;
+  const double fb = (double)c.field();
+  // S_bar = F^-1[ sum_i conj(-i m_i PSI2) F psi2_bar_i ]
+  CHK(fwd_zy(c, "z_r2c_gpsi2", "y_fwd_gpsi2", g2, 3 * c.field(), c.slot(1), 3));
+  XOp o1 = op_blank(3, 1, 1);
+  op_tables(o1, g, t);
+  for (int i = 0; i < 3; ++i) op_set(o1, i, MUL_PI, i, -1, TAB_PSI2, 1.0);
+  CHK(xp(c, "x_adj_psi2", c.slot(1), c.slot(10), o1));
+  CHK(inv_y(c, "y_inv_sbar", c.slot(10), 1));
+  CHK(z_c2r(c, "z_c2r_sbar", c.slot(10), c.slot(10), c.cap(c.slot(10)), 1));
+  // phi_,ij recomputed from the noise
+  CHK(fwd_zy(c, "z_r2c_noise", "y_fwd_noise", noise, c.field(), c.slot(0), 1));
+  XOp o2 = op_blank(1, 6, 1);
+  op_tables(o2, g, t);
+  for (int q = 0; q < 6; ++q) op_set(o2, q, MUL_REAL, PI_[q], PJ_[q], TAB_PHI, -1.0);
+  CHK(xp(c, "x_fused_phi", c.slot(0), c.slot(1), o2));
+  CHK(inv_y(c, "y_inv_phi", c.slot(1), 6));
+  RUN("z_adj_prodrule", fb * 14.0,
+      launch_zprodrule(p->prec, g.n, c.slot(1), c.cap(c.slot(1)), g.nnm, c.slot(10), c.cap(c.slot(10)), c.slot(1),
+                       c.cap(c.slot(1)), g.nnm, (long)g.n * g.n, g.tw, s));
+  RUN("z_r2c_gpsi1", 2.0 * fb * 3,
+      launch_zr2c(p->prec, g.n, g1, 3 * c.field(), c.slot(7), c.cap(c.slot(7)), 3L * g.n * g.n, g.tw, s));
+  CHK(fwd_y(c, "y_fwd_adj", c.slot(1), 9));
+  XOp o3 = op_blank(9, 1, 1);
+  op_tables(o3, g, t);
+  for (int q = 0; q < 6; ++q) op_set(o3, q, MUL_REAL, PI_[q], PJ_[q], TAB_PHI, -1.0);
+  for (int i = 0; i < 3; ++i) op_set(o3, 6 + i, MUL_MI, i, -1, TAB_PSI1, 1.0);
+  CHK(xp(c, "x_adj_noise", c.slot(1), c.slot(0), o3));
+  CHK(inv_y(c, "y_inv_gnoise", c.slot(0), 1));
+  CHK(z_c2r(c, "z_c2r_gnoise", c.slot(0), gw, c.field(), 1));
+  return LPT2_OK;
+}
+
+lpt2_status check_a(lpt2_plan_t p, double a) {
+  if (!(a > 0.0) || !std::isfinite(a)) return fail(p, LPT2_EINVAL, "scale factor a must be > 0");
+  return LPT2_OK;
+}
+
+}  // namespace
+
+// =============================================================================
+// C ABI
+// =============================================================================
+extern "C" {
+
+void lpt2_config_default(lpt2_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->n = 32;
+  c->box = 128.0;
+  c->omega_m = 0.3;
+  c->h = 0.7;
+  c->n_s = 0.96;
+  c->sigma8 = 0.8;
+  c->gravity = LPT2_GRAV_GR;
+  c->fr0_abs = 1e-5;
+  c->hs_n = 1;
+  c->mu_const = 1.0;
+  c->factorisation = LPT2_D2_EDS;
+  c->tri_ratio = 1.0;
+  c->tri_theta_deg = 90.0;
+  c->nk_growth = 256;
+  c->kmin = 1e-3;
+  c->kmax = 10.0;
+  c->a_init = 1e-3;
+  c->ode_steps = 4096;
+  c->precision = LPT2_FP64;
+}
+
+const char* lpt2_strerror(lpt2_status s) {
+  switch (s) {
+    case LPT2_OK: return "ok";
+    case LPT2_EINVAL: return "invalid argument";
+    case LPT2_EUNSUPPORTED: return "unsupported";
+    case LPT2_ENOMEM: return "out of memory";
+    case LPT2_EDEVICE: return "device error";
+    case LPT2_ESTATE: return "plan busy or in the wrong state";
+  }
+  return "unknown status";
+}
+
+const char* lpt2_last_error(lpt2_plan_t p) { return p ? p->err.c_str() : g_err.c_str(); }
+
+lpt2_status lpt2_plan(const lpt2_config* cfgs, int n_cfgs, const int* counts, lpt2_plan_t* out) {
+  if (!out) return fail(nullptr, LPT2_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfgs || n_cfgs < 1) return fail(nullptr, LPT2_EINVAL, "need at least one configuration");
+  int prec = cfgs[0].precision;
+  for (int i = 0; i < n_cfgs; ++i) {
+    std::string why;
+    lpt2_status st = validate(cfgs[i], why);
+    if (st != LPT2_OK) return fail(nullptr, st, "config " + std::to_string(i) + ": " + why);
+    if (cfgs[i].precision != prec) return fail(nullptr, LPT2_EUNSUPPORTED, "all configurations must share a precision");
+    if (counts && counts[i] < 1) return fail(nullptr, LPT2_EINVAL, "counts must be >= 1");
+  }
+  lpt2_plan_s* p = new lpt2_plan_s();
+  p->prec = prec == LPT2_FP32 ? PREC_F32 : PREC_F64;
+  p->es = p->prec == PREC_F32 ? 4 : 8;
+  size_t maxf = 0;
+  for (int i = 0; i < n_cfgs; ++i) {
+    Grid g;
+    g.cfg = cfgs[i];
+    g.count = counts ? counts[i] : 1;
+    g.n = cfgs[i].n;
+    g.m = g.n / 2;
+    g.nnm = (long)g.n * g.n * g.m;
+    g.n3 = (long)g.n * g.n * g.n;
+    g.n2cnt = 3L * g.m * g.m + 1;
+    g.c.om = cfgs[i].omega_m;
+    g.c.ol = 1.0 - cfgs[i].omega_m;
+    g.c.h = cfgs[i].h;
+    g.c.ns = cfgs[i].n_s;
+    g.c.gravity = cfgs[i].gravity == LPT2_GRAV_FR_HS ? GRAV_FR : (cfgs[i].gravity == LPT2_GRAV_MU_CONST ? GRAV_MUC : GRAV_GR);
+    g.c.fr0 = cfgs[i].fr0_abs;
+    g.c.mu0 = cfgs[i].mu_const;
+    g.amp = sigma8_amplitude(g.c, cfgs[i].sigma8);
+    g.lkmin = std::log(cfgs[i].kmin);
+    g.lkmax = std::log(cfgs[i].kmax);
+    // twiddles exp(-2 pi i m / n), m < n, from long double, rounded once
+    std::vector<double> tw64(2 * g.n);
+    std::vector<float> tw32(2 * g.n);
+    for (int m = 0; m < g.n; ++m) {
+      const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)g.n;
+      tw64[2 * m] = (double)cosl(ang);
+      tw64[2 * m + 1] = (double)sinl(ang);
+      tw32[2 * m] = (float)cosl(ang);
+      tw32[2 * m + 1] = (float)sinl(ang);
+    }
+    const size_t twb = (size_t)2 * g.n * p->es;
+    hipError_t e = hipMalloc(&g.tw, twb);
+    if (e != hipSuccess) {
+      p->grids.push_back(g);
+      lpt2_destroy(p);
+      return fail(nullptr, LPT2_ENOMEM, "twiddle allocation failed");
+    }
+    e = hipMemcpy(g.tw, p->prec == PREC_F32 ? (const void*)tw32.data() : (const void*)tw64.data(), twb,
+                  hipMemcpyHostToDevice);
+    p->grids.push_back(g);
+    if (e != hipSuccess) {
+      lpt2_destroy(p);
+      return fail(nullptr, LPT2_EDEVICE, std::string("twiddle upload: ") + hipGetErrorString(e));
+    }
+    for (int r = 0; r < p->grids.back().count; ++r) p->rgrid.push_back(i);
+    const size_t fbytes = (size_t)g.n3 * p->es;
+    if (fbytes > maxf) maxf = fbytes;
+  }
+  p->ws_bytes = maxf * WS_FIELDS;
+  hipError_t e = hipMalloc((void**)&p->ws, p->ws_bytes);
+  if (e != hipSuccess) {
+    p->ws = nullptr;
+    lpt2_destroy(p);
+    return fail(nullptr, LPT2_ENOMEM, "workspace allocation failed");
+  }
+  e = hipMalloc((void**)&p->bin_partial, sizeof(double) * (BIN_BLOCKS * (size_t)BIN_MAXBINS * 4 + 4 * BIN_MAXBINS));
+  if (e != hipSuccess) {
+    p->bin_partial = nullptr;
+    lpt2_destroy(p);
+    return fail(nullptr, LPT2_ENOMEM, "binner allocation failed");
+  }
+  p->bin_out = p->bin_partial + (size_t)BIN_BLOCKS * BIN_MAXBINS * 4;
+  *out = p;
+  return LPT2_OK;
+}
+
+lpt2_status lpt2_destroy(lpt2_plan_t p) {
+  if (!p) return LPT2_OK;
+  (void)hipDeviceSynchronize();
+  for (auto& g : p->grids) {
+    if (g.tw) (void)hipFree(g.tw);
+    for (auto& t : g.tables) {
+      (void)hipFree(t.d1n);
+      if (t.radial) (void)hipFree(t.radial);
+    }
+    for (auto& t : g.gr_tables) (void)hipFree(t.d1n);
+  }
+  if (p->ws) (void)hipFree(p->ws);
+  if (p->bin_partial) (void)hipFree(p->bin_partial);
+  prof_flush(p);
+  for (auto e : p->pool) (void)hipEventDestroy(e);
+  delete p;
+  return LPT2_OK;
+}
+
+int lpt2_realisations(lpt2_plan_t p) { return p ? (int)p->rgrid.size() : 0; }
+
+lpt2_status lpt2_realisation_info(lpt2_plan_t p, int r, int* n, int* precision) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  if (r < 0 || r >= (int)p->rgrid.size()) return fail(p, LPT2_EINVAL, "realisation index out of range");
+  if (n) *n = p->grids[p->rgrid[r]].n;
+  if (precision) *precision = p->prec == PREC_F32 ? LPT2_FP32 : LPT2_FP64;
+  return LPT2_OK;
+}
+
+long long lpt2_workspace_bytes(lpt2_plan_t p) { return p ? (long long)p->ws_bytes : 0; }
+
+lpt2_status lpt2_displace(lpt2_plan_t p, double a, const void* const* noise, void* const* psi1, void* const* psi2,
+                          void* stream) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  CHK(check_a(p, a));
+  if (!noise || !psi1 || !psi2) return fail(p, LPT2_EINVAL, "null pointer array");
+  const int nr = (int)p->rgrid.size();
+  for (int r = 0; r < nr; ++r)
+    if (!noise[r] || !psi1[r] || !psi2[r]) return fail(p, LPT2_EINVAL, "null field pointer for realisation " + std::to_string(r));
+  hipStream_t s = (hipStream_t)stream;
+  for (int r = 0; r < nr; ++r) {
+    Grid& g = p->grids[p->rgrid[r]];
+    Tables* t = nullptr;
+    CHK(get_tables(p, g, a, false, s, &t));
+    Ctx c{p, g, s, 2 * p->es};
+    CHK(displace_one(c, t, noise[r], psi1[r], psi2[r]));
+  }
+  return LPT2_OK;
+}
+
+lpt2_status lpt2_source_spectrum(lpt2_plan_t p, double a, const void* noise, int nbins, int quantity, double* k_mean,
+                                 double* count, double* mean, double* std_dev, void* stream) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  CHK(check_a(p, a));
+  if (!noise || !k_mean || !count || !mean || !std_dev) return fail(p, LPT2_EINVAL, "null pointer");
+  if (nbins < 1 || nbins > BIN_MAXBINS) return fail(p, LPT2_EINVAL, "nbins must be in 1..512");
+  if (quantity != LPT2_SPEC_POWER && quantity != LPT2_SPEC_RATIO) return fail(p, LPT2_EINVAL, "unknown quantity");
+  hipStream_t s = (hipStream_t)stream;
+  Grid& g = p->grids[p->rgrid[0]];
+  Tables* t = nullptr;
+  CHK(get_tables(p, g, a, false, s, &t));
+  Ctx c{p, g, s, 2 * p->es};
+  const double kf = 2.0 * kPi / g.cfg.box;
+  if (quantity == LPT2_SPEC_POWER) {
+    CHK(source_k(c, t, noise, 11, 1.0));
+    const double n3 = (double)g.n3;
+    const double qs = g.cfg.box * g.cfg.box * g.cfg.box / (n3 * n3);
+    RUN("shell_bin", 0.0,
+        launch_bin(p->prec, g.n, c.slot(11), c.cap(c.slot(11)), nullptr, 0, 0, qs, nbins, kf, p->bin_partial,
+                   p->bin_out, s));
+  } else {
+    Tables* tg = nullptr;
+    CHK(get_tables(p, g, a, true, s, &tg));
+    double d1gr = 0.0;
+    hipError_t e = hipMemcpyAsync(&d1gr, tg->d1n, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(p, e, "D1_GR readback");
+    const double G = four_pi_g_rho(g.c, a);
+    CHK(source_k(c, t, noise, 11, -G * d1gr * d1gr));
+    CHK(mg_source_k(c, t, noise));
+    RUN("shell_bin", 0.0,
+        launch_bin(p->prec, g.n, c.slot(10), c.cap(c.slot(10)), c.slot(11), c.cap(c.slot(11)), 1, 1.0, nbins, kf,
+                   p->bin_partial, p->bin_out, s));
+  }
+  std::vector<double> h(4 * (size_t)nbins);
+  hipError_t e = hipMemcpyAsync(h.data(), p->bin_out, sizeof(double) * 4 * nbins, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(p, e, "spectrum readback");
+  for (int i = 0; i < nbins; ++i) {
+    k_mean[i] = h[i];
+    count[i] = h[nbins + i];
+    mean[i] = h[2 * nbins + i];
+    std_dev[i] = h[3 * nbins + i];
+  }
+  return LPT2_OK;
+}
+
+lpt2_status lpt2_triangle_ratio(lpt2_plan_t p, double a, double ratio, double theta_deg, int winther, const double* k,
+                                int nk, double* out) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  CHK(check_a(p, a));
+  if (!k || !out || nk < 0) return fail(p, LPT2_EINVAL, "null pointer");
+  if (!(ratio > 0.0) || !(theta_deg > 0.0 && theta_deg < 180.0)) return fail(p, LPT2_EINVAL, "bad triangle");
+  Grid& g = p->grids[p->rgrid[0]];
+  hipStream_t s = nullptr;
+  Tables *t = nullptr, *tg = nullptr;
+  CHK(get_tables(p, g, a, false, s, &t));
+  CHK(get_tables(p, g, a, true, s, &tg));
+  const int n = g.cfg.nk_growth;
+  std::vector<double> d1(n), d1g(1);
+  hipError_t e = hipMemcpy(d1.data(), t->d1n, sizeof(double) * n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(d1g.data(), tg->d1n, sizeof(double), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(p, e, "growth readback");
+  const double cs = cos_deg(theta_deg);
+  for (int i = 0; i < nk; ++i) {
+    double k1, k2;
+    triangle(k[i], ratio, cs, k1, k2);
+    const double dd = winther ? std::pow(interp_lnk(d1.data(), n, g.lkmin, g.lkmax, k[i]), 2)
+                              : interp_lnk(d1.data(), n, g.lkmin, g.lkmax, k1) * interp_lnk(d1.data(), n, g.lkmin, g.lkmax, k2);
+    out[i] = dd * brace(g.c, k[i], k1, k2, cs, a) / (d1g[0] * d1g[0] * (1.0 - cs * cs));
+  }
+  return LPT2_OK;
+}
+
+lpt2_status lpt2_backward(lpt2_plan_t p, double a, const void* const* noise, const void* const* g_psi1,
+                          const void* const* g_psi2, void* const* g_noise, void* stream) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  CHK(check_a(p, a));
+  if (!noise || !g_psi1 || !g_psi2 || !g_noise) return fail(p, LPT2_EINVAL, "null pointer array");
+  const int nr = (int)p->rgrid.size();
+  for (int r = 0; r < nr; ++r)
+    if (!noise[r] || !g_psi1[r] || !g_psi2[r] || !g_noise[r])
+      return fail(p, LPT2_EINVAL, "null field pointer for realisation " + std::to_string(r));
+  hipStream_t s = (hipStream_t)stream;
+  for (int r = 0; r < nr; ++r) {
+    Grid& g = p->grids[p->rgrid[r]];
+    Tables* t = nullptr;
+    CHK(get_tables(p, g, a, false, s, &t));
+    Ctx c{p, g, s, 2 * p->es};
+    CHK(backward_one(c, t, noise[r], g_psi1[r], g_psi2[r], g_noise[r]));
+  }
+  return LPT2_OK;
+}
+
+lpt2_status lpt2_paint_cic(lpt2_plan_t p, const void* psi1, const void* psi2, void* delta, void* stream) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  if (!psi1 || !psi2 || !delta) return fail(p, LPT2_EINVAL, "null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  Grid& g = p->grids[p->rgrid[0]];
+  RUN("cic_paint", 0.0, launch_cic(p->prec, g.n, g.cfg.box, psi1, psi2, delta, s));
+  return LPT2_OK;
+}
+
+lpt2_status lpt2_paint_cic_backward(lpt2_plan_t p, const void* psi1, const void* psi2, const void* g_delta, void* g_psi,
+                                    void* stream) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  if (!psi1 || !psi2 || !g_delta || !g_psi) return fail(p, LPT2_EINVAL, "null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  Grid& g = p->grids[p->rgrid[0]];
+  RUN("cic_backward", 0.0, launch_cic_back(p->prec, g.n, g.cfg.box, psi1, psi2, g_delta, g_psi, s));
+  return LPT2_OK;
+}
+
+lpt2_status lpt2_growth_table(lpt2_plan_t p, double a, double* k, double* d1, double* d2) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  CHK(check_a(p, a));
+  if (!k || !d1 || !d2) return fail(p, LPT2_EINVAL, "null pointer");
+  Grid& g = p->grids[p->rgrid[0]];
+  Tables* t = nullptr;
+  CHK(get_tables(p, g, a, false, nullptr, &t));
+  const int n = g.cfg.nk_growth;
+  hipError_t e = hipMemcpy(d1, t->d1n, sizeof(double) * n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(d2, t->d2n, sizeof(double) * n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(p, e, "growth readback");
+  for (int i = 0; i < n; ++i) k[i] = std::exp(g.lkmin + (g.lkmax - g.lkmin) * (double)i / (double)(n - 1));
+  return LPT2_OK;
+}
+
+lpt2_status lpt2_fft3d(lpt2_plan_t p, int direction, const void* in, void* out, void* stream) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  if (!in || !out) return fail(p, LPT2_EINVAL, "null pointer");
+  if (direction != -1 && direction != 1) return fail(p, LPT2_EINVAL, "direction must be -1 or +1");
+  hipStream_t s = (hipStream_t)stream;
+  Grid& g = p->grids[p->rgrid[0]];
+  Ctx c{p, g, s, 2 * p->es};
+  const double fb = (double)g.n3 * p->es;
+  if (direction < 0) {
+    RUN("z_r2c", 2.0 * fb, launch_zr2c(p->prec, g.n, in, c.field(), out, c.field(), (long)g.n * g.n, g.tw, s));
+    RUN("y_fwd", 2.0 * fb,
+        launch_colfft(p->prec, g.n, -1, out, c.field(), g.n, g.n * g.m, (int)g.m, g.m, g.tw, s));
+    RUN("x_fwd", 2.0 * fb,
+        launch_colfft(p->prec, g.n, -1, out, c.field(), 1, 0, (int)(g.n * g.m), g.n * g.m, g.tw, s));
+  } else {
+    hipError_t e = hipMemcpyAsync(c.slot(0), in, c.field(), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(p, e, "copy");
+    RUN("x_inv", 2.0 * fb,
+        launch_colfft(p->prec, g.n, +1, c.slot(0), c.cap(c.slot(0)), 1, 0, (int)(g.n * g.m), g.n * g.m, g.tw, s));
+    CHK(inv_y(c, "y_inv", c.slot(0), 1));
+    CHK(z_c2r(c, "z_c2r", c.slot(0), out, c.field(), 1));
+  }
+  return LPT2_OK;
+}
+
+lpt2_status lpt2_profile_enable(lpt2_plan_t p, int enable) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  prof_flush(p);
+  p->prof = enable != 0;
+  return LPT2_OK;
+}
+lpt2_status lpt2_profile_reset(lpt2_plan_t p) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  prof_flush(p);
+  p->prof_tab.clear();
+  return LPT2_OK;
+}
+int lpt2_profile_count(lpt2_plan_t p) {
+  if (!p) return 0;
+  prof_flush(p);
+  return (int)p->prof_tab.size();
+}
+lpt2_status lpt2_profile_get(lpt2_plan_t p, int i, const char** name, long long* launches, double* total_ms,
+                             double* bytes_per_launch) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  prof_flush(p);
+  if (i < 0 || i >= (int)p->prof_tab.size()) return fail(p, LPT2_EINVAL, "profile index out of range");
+  const ProfEntry& e = p->prof_tab[i];
+  if (name) *name = e.name;
+  if (launches) *launches = e.launches;
+  if (total_ms) *total_ms = e.ms;
+  if (bytes_per_launch) *bytes_per_launch = e.bytes;
+  return LPT2_OK;
+}
+
+}  // extern "C"

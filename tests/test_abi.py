@@ -1,0 +1,97 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared
+symbol, and rejects bad arguments on the host before any device work."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lpt2.h")
+
+
+def _lib():
+    from paper_1909_06282_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        pytest.skip("liblpt2.so not built")
+    return _abi, _abi.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lpt2_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_paper_entry_points():
+    names = declared_functions()
+    for must in ("lpt2_plan", "lpt2_displace", "lpt2_source_spectrum", "lpt2_backward"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    _, L = _lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    abi, _ = _lib()
+    assert sorted(abi.EXPORTS) == declared_functions()
+
+
+def test_config_struct_layout_matches_default():
+    abi, L = _lib()
+    c = abi.Config()
+    L.lpt2_config_default(C.byref(c))
+    assert (c.n, c.box, c.omega_m, c.h, c.n_s, c.sigma8) == (32, 128.0, 0.3, 0.7, 0.96, 0.8)
+    assert (c.hs_n, c.nk_growth, c.kmin, c.kmax, c.a_init, c.ode_steps) == (1, 256, 1e-3, 10.0, 1e-3, 4096)
+    assert c.precision == abi.FP64 and c.factorisation == abi.D2_EDS
+
+
+def _plan_status(abi, L, **kw):
+    c = abi.Config()
+    L.lpt2_config_default(C.byref(c))
+    for k, v in kw.items():
+        setattr(c, k, v)
+    h = C.c_void_p(123)
+    st = L.lpt2_plan(C.byref(c), 1, None, C.byref(h))
+    return st, h, L.lpt2_last_error(None).decode()
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=48), -2), (dict(n=4), -2), (dict(n=1024), -2), (dict(precision=7), -2),
+    (dict(box=0.0), -1), (dict(box=-3.0), -1), (dict(gravity=1, fr0_abs=0.0), -1),
+    (dict(gravity=1, hs_n=2), -2), (dict(gravity=9), -1), (dict(factorisation=8), -1),
+    (dict(nk_growth=1), -1), (dict(kmin=0.0), -1), (dict(kmax=1e-4), -1), (dict(a_init=0.0), -1),
+    (dict(ode_steps=0), -1), (dict(factorisation=2, tri_theta_deg=180.0), -1),
+    (dict(gravity=2, mu_const=0.0), -1), (dict(omega_m=0.0), -1),
+])
+def test_plan_rejects_bad_configs_on_host(kw, status):
+    abi, L = _lib()
+    st, h, msg = _plan_status(abi, L, **kw)
+    assert st == status
+    assert h.value is None
+    assert msg
+
+
+def test_null_arguments():
+    abi, L = _lib()
+    assert L.lpt2_plan(None, 1, None, None) == abi.EINVAL
+    h = C.c_void_p()
+    assert L.lpt2_plan(None, 1, None, C.byref(h)) == abi.EINVAL
+    c = abi.Config()
+    L.lpt2_config_default(C.byref(c))
+    cnt = (C.c_int * 1)(0)
+    assert L.lpt2_plan(C.byref(c), 1, cnt, C.byref(h)) == abi.EINVAL
+    assert L.lpt2_displace(None, 1.0, None, None, None, None) == abi.EINVAL
+    assert L.lpt2_backward(None, 1.0, None, None, None, None, None) == abi.EINVAL
+    assert L.lpt2_source_spectrum(None, 1.0, None, 8, 0, None, None, None, None, None) == abi.EINVAL
+    assert L.lpt2_destroy(None) == abi.OK
+    assert L.lpt2_realisations(None) == 0
+
+
+def test_strerror():
+    _, L = _lib()
+    assert L.lpt2_strerror(0) == b"ok"
+    assert L.lpt2_strerror(-2) == b"unsupported"

@@ -1,0 +1,268 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: FP64 path <= 1e-12 normwise (max |gpu - oracle| / max |oracle|),
+FP32 path <= 1e-5 normwise, integer bin counts exact, binner bitwise
+reproducible.  Sizes 8^3..128^3 cover several tiles and the ragged tails of
+the small grids (partial blocks of lines and columns).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import adjoint, cic, fields, growth, mgsource, spectrum
+from seeded_inputs import white_noise
+from tests._util import gpu_config, normwise, oracle_model, to_dev
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+F32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1909_06282_amd import load_library
+    load_library()
+
+
+def _plan(**kw):
+    from paper_1909_06282_amd import Plan
+    cfg = gpu_config(**kw)
+    return Plan(cfg), cfg
+
+
+_TAB_CACHE = {}
+
+
+def _tables(model, a):
+    key = (model, a)
+    if key not in _TAB_CACHE:
+        _TAB_CACHE[key] = growth.tables(model, a)
+    return _TAB_CACHE[key]
+
+
+# ---------------------------------------------------------------- FFT
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128])
+def test_fft3d_forward_matches_dft(n, prec):
+    print(f"fft3d forward n={n} {prec}", flush=True)
+    plan, cfg = _plan(precision=prec, n=n, box=2.0 * n)
+    x = white_noise(n, 5)
+    got = plan.fft3d(-1, to_dev(x, cfg.dtype)).cpu().to(torch.complex128)
+    ref = torch.fft.rfftn(torch.from_numpy(x))[:, :, : n // 2]
+    err = float((got - ref).abs().max() / ref.abs().max())
+    assert err < (1e-14 if prec == "fp64" else 1e-6), err
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128])
+def test_fft3d_inverse_matches_dft(n, prec):
+    print(f"fft3d inverse n={n} {prec}", flush=True)
+    plan, cfg = _plan(precision=prec, n=n, box=2.0 * n)
+    x = white_noise(n, 6)
+    half = torch.fft.rfftn(torch.from_numpy(x))
+    half[:, :, n // 2] = 0
+    ref = torch.fft.irfftn(half, s=(n, n, n)) * n ** 3
+    inp = torch.view_as_real(half[:, :, : n // 2].contiguous()).to(cfg.dtype).cuda().contiguous()
+    got = plan.fft3d(+1, inp).cpu()
+    assert normwise(got, ref) < (1e-14 if prec == "fp64" else 1e-6)
+
+
+# ---------------------------------------------------------------- growth
+@pytest.mark.parametrize("kw", [
+    dict(gravity="gr", factorisation="eds"),
+    dict(gravity="gr", factorisation="t1"),
+    dict(gravity="fr_hs", fr0_abs=1e-5, factorisation="t1"),
+    dict(gravity="fr_hs", fr0_abs=1e-4, factorisation="winther"),
+    dict(gravity="fr_hs", fr0_abs=1e-6, factorisation="triangle", tri_ratio=2.0, tri_theta_deg=70.0),
+    dict(gravity="fr_hs", fr0_abs=1e-5, factorisation="bouchet"),
+    dict(gravity="mu_const", mu_const=4.0 / 3.0, omega_m=1.0, factorisation="t1"),
+])
+@pytest.mark.parametrize("a", [1.0, 0.5])
+def test_growth_table_matches_oracle(kw, a):
+    print(f"growth {kw} a={a}", flush=True)
+    plan, cfg = _plan(n=8, box=16.0, nk_growth=64, **kw)
+    k, d1, d2 = plan.growth_table(a)
+    kn, o1, o2 = _tables(oracle_model(cfg), a)
+    assert np.max(np.abs(k / kn - 1)) < 1e-14
+    assert np.max(np.abs(d1 / o1 - 1)) < 1e-12
+    assert np.max(np.abs(d2 / o2 - 1)) < 1e-12
+
+
+# ---------------------------------------------------------------- displacements
+def _check_displace(prec, a, tol, seed=1, **kw):
+    plan, cfg = _plan(precision=prec, **kw)
+    model = oracle_model(cfg)
+    w = white_noise(cfg.n, seed)
+    p1, p2 = plan.displace(a, to_dev(w, cfg.dtype))
+    torch.cuda.synchronize()
+    r1, r2 = fields.displace(w, model, a, _tables(model, a))
+    e1, e2 = normwise(p1, r1), normwise(p2, r2)
+    tot = normwise(p1.double() + p2.double(), r1 + r2)
+    print(f"  psi1 {e1:.3e} psi2 {e2:.3e} total {tot:.3e}", flush=True)
+    assert e1 < tol and e2 < tol and tot < tol
+    return plan, cfg, p1, p2
+
+
+def test_displace_c1_gr_fp64():
+    print("displace C1 GR fp64", flush=True)
+    _check_displace("fp64", 1.0, F64_TOL, n=32, box=128.0, gravity="gr", factorisation="eds")
+
+
+@pytest.mark.parametrize("n", [8, 16, 32, 64])
+@pytest.mark.parametrize("a", [1.0, 0.5])
+def test_displace_fr_t1_fp64(n, a):
+    print(f"displace f(R) T1 fp64 n={n} a={a}", flush=True)
+    _check_displace("fp64", a, F64_TOL, n=n, box=2.0 * n, gravity="fr_hs", fr0_abs=1e-5,
+                    factorisation="t1", nk_growth=64)
+
+
+@pytest.mark.parametrize("n", [8, 32, 128])
+def test_displace_fr_t1_fp32(n):
+    print(f"displace f(R) T1 fp32 n={n}", flush=True)
+    _check_displace("fp32", 1.0, F32_TOL, n=n, box=2.0 * n, gravity="fr_hs", fr0_abs=1e-5,
+                    factorisation="t1", nk_growth=64)
+
+
+def test_displace_batched_plan_matches_single():
+    print("displace two-grid plan", flush=True)
+    from paper_1909_06282_amd import Plan
+    c1 = gpu_config(n=32, box=64.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=64)
+    c2 = gpu_config(n=16, box=32.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=64)
+    plan = Plan([c1, c2], counts=[2, 1])
+    ws = [white_noise(32, 100), white_noise(32, 101), white_noise(16, 102)]
+    p1, p2 = plan.displace(1.0, [to_dev(w, torch.float64) for w in ws])
+    for w, q1, q2, cfg in zip(ws, p1, p2, (c1, c1, c2)):
+        m = oracle_model(cfg)
+        r1, r2 = fields.displace(w, m, 1.0, _tables(m, 1.0))
+        assert normwise(q1, r1) < F64_TOL and normwise(q2, r2) < F64_TOL
+
+
+def test_single_plane_wave_gives_no_psi2():
+    print("plane wave", flush=True)
+    plan, cfg = _plan(n=16, box=32.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=64)
+    # white noise equal to one plane wave: its shaped delta is one Fourier mode
+    c = np.arange(16)
+    X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
+    w = np.cos(2 * np.pi * (X + 2 * Y - Z) / 16)
+    p1, p2 = plan.displace(1.0, to_dev(w, torch.float64))
+    assert float(p2.abs().max()) < 1e-13 * float(p1.abs().max())
+
+
+# ---------------------------------------------------------------- source spectrum
+@pytest.mark.parametrize("n,nbins", [(16, 8), (32, 16), (64, 32)])
+def test_source_power_spectrum_matches_oracle(n, nbins):
+    print(f"source power n={n}", flush=True)
+    plan, cfg = _plan(n=n, box=2.0 * n, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=64)
+    w = white_noise(n, 3)
+    got = plan.source_spectrum(1.0, to_dev(w, torch.float64), nbins, "power")
+    m = oracle_model(cfg)
+    sk = fields.source_k(fields.source(fields.delta_k(w, m), m), m)
+    km, cnt, mean, std = spectrum.source_power(sk, m, nbins)
+    assert np.array_equal(got["count"], cnt)
+    nz = cnt > 0
+    assert np.max(np.abs(got["k_mean"][nz] / km[nz] - 1)) < 1e-13
+    assert np.max(np.abs(got["mean"][nz] / mean[nz] - 1)) < 1e-11
+    assert np.max(np.abs(got["std"][nz] / std[nz] - 1)) < 1e-9
+
+
+def test_source_spectrum_is_bitwise_reproducible():
+    print("binner determinism", flush=True)
+    plan, cfg = _plan(precision="fp32", n=64, box=128.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1",
+                      nk_growth=64)
+    w = to_dev(white_noise(64, 9), torch.float32)
+    a = plan.source_spectrum(1.0, w, 32, "power")
+    b = plan.source_spectrum(1.0, w, 32, "power")
+    for k in a:
+        assert np.array_equal(a[k], b[k])
+
+
+@pytest.mark.parametrize("gravity", ["gr", "fr_hs"])
+def test_source_ratio_matches_oracle(gravity):
+    print(f"source ratio {gravity}", flush=True)
+    n, nb = 32, 16
+    plan, cfg = _plan(n=n, box=128.0, gravity=gravity, fr0_abs=1e-4, factorisation="t1", nk_growth=64)
+    w = white_noise(n, 3)
+    got = plan.source_spectrum(1.0, to_dev(w, torch.float64), nb, "ratio")
+    m = oracle_model(cfg)
+    km, cnt, mean, std = mgsource.source_ratio(w, m, 1.0, nb, _tables(m, 1.0))
+    assert np.array_equal(got["count"], cnt)
+    nz = cnt > 0
+    assert np.max(np.abs(got["mean"][nz] - mean[nz])) < 1e-10
+    assert np.max(np.abs(got["std"][nz] - std[nz])) < 1e-7
+    if gravity == "gr":
+        assert np.max(np.abs(got["mean"][nz] - 1)) < 1e-12
+
+
+def test_triangle_ratio_matches_oracle():
+    plan, cfg = _plan(n=8, box=16.0, gravity="fr_hs", fr0_abs=1e-4, factorisation="t1", nk_growth=64)
+    m = oracle_model(cfg)
+    k = np.geomspace(0.01, 1.0, 9)
+    tab = growth.tables(m.with_(factorisation="eds"), 0.8)
+    for _, r, th, win in mgsource.CANDIDATES:
+        got = plan.triangle_ratio(0.8, r, th, k, win)
+        ref = mgsource.triangle_ratio(k, m, 0.8, r, th, win, tab)
+        assert np.max(np.abs(got / ref - 1)) < 1e-12, (r, th, win)
+
+
+# ---------------------------------------------------------------- adjoint and CIC
+@pytest.mark.parametrize("n", [8, 16])
+def test_backward_matches_oracle_autograd(n):
+    print(f"backward fp64 n={n}", flush=True)
+    plan, cfg = _plan(n=n, box=2.0 * n, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=64)
+    m = oracle_model(cfg)
+    w = white_noise(n, 4)
+    rng = np.random.default_rng(5)
+    g1, g2 = rng.standard_normal((3, n, n, n)), rng.standard_normal((3, n, n, n))
+    got = plan.backward(1.0, to_dev(w, torch.float64), to_dev(g1, torch.float64), to_dev(g2, torch.float64))
+    ref = adjoint.vjp_displace(w, g1, g2, m, 1.0, _tables(m, 1.0))
+    assert normwise(got, ref) < 1e-11
+
+
+def test_backward_fp32_matches_fp64_gpu():
+    print("backward fp32", flush=True)
+    n = 32
+    kw = dict(n=n, box=64.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=64)
+    p64, _ = _plan(precision="fp64", **kw)
+    p32, _ = _plan(precision="fp32", **kw)
+    w = white_noise(n, 4)
+    rng = np.random.default_rng(6)
+    g1, g2 = rng.standard_normal((3, n, n, n)), rng.standard_normal((3, n, n, n))
+    a = p64.backward(1.0, to_dev(w, torch.float64), to_dev(g1, torch.float64), to_dev(g2, torch.float64))
+    b = p32.backward(1.0, to_dev(w, torch.float32), to_dev(g1, torch.float32), to_dev(g2, torch.float32))
+    assert normwise(b, a) < F32_TOL
+
+
+def test_cic_paint_and_transpose_match_oracle():
+    print("cic", flush=True)
+    n = 16
+    plan, cfg = _plan(n=n, box=32.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=64)
+    m = oracle_model(cfg)
+    w = white_noise(n, 7)
+    p1, p2 = plan.displace(1.0, to_dev(w, torch.float64))
+    d = plan.paint_cic(p1, p2)
+    ref = cic.paint(p1.cpu() + p2.cpu(), m)
+    assert float((d.cpu() - ref).abs().max()) < 1e-12
+    gd = np.random.default_rng(8).standard_normal((n, n, n))
+    g = plan.paint_cic_backward(p1, p2, to_dev(gd, torch.float64))
+    gref = adjoint.vjp_paint(p1.cpu() + p2.cpu(), gd, m)
+    assert normwise(g, gref) < 1e-12
+
+
+def test_invalid_arguments_raise():
+    from paper_1909_06282_amd import LPT2Error
+    plan, cfg = _plan(n=8, box=16.0)
+    w = to_dev(white_noise(8, 1), torch.float64)
+    with pytest.raises(LPT2Error):
+        plan.displace(0.0, w)
+    with pytest.raises(LPT2Error):
+        plan.displace(-1.0, w)
+    with pytest.raises(ValueError):
+        plan.displace(1.0, w.float())
+    with pytest.raises(ValueError):
+        plan.displace(1.0, to_dev(white_noise(16, 1), torch.float64))
