@@ -1,0 +1,211 @@
+"""Throughput of the 2LPT displacement path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-fp64]
+
+A step is one lpt2_displace call: the whole path from unit white noise to
+psi1 and psi2 for one 512^3 realisation (L = 1024 Mpc/h, Hu-Sawicki n = 1),
+cycling through |f_R0| in {1e-6, 1e-4}, z in {0, 1} and seeds 1-4 (16
+combinations), FP32 fields with FP64 growth factors.  Inputs are resident in
+HBM before the timed region; growth tables are built once per (model, a)
+during warm-up, outside the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+N = 512
+BOX = 1024.0
+FR0S = (1e-6, 1e-4)
+REDSHIFTS = (0.0, 1.0)
+SEEDS = (1, 2, 3, 4)
+CSRC = os.path.join(ROOT, "paper_1909_06282_amd", "csrc")
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel: str, launches_bytes: float):
+    """HBM bytes per launch measured with rocprofv3 counters, if taken on this source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(fr0: float, a: float, seed: int):
+    """The FP64 oracle on a bounded sample: one 256^3 realisation at the same cell size."""
+    import torch
+    import oracle
+    from oracle import fields, growth
+    from seeded_inputs import white_noise
+    torch.set_num_threads(os.cpu_count() or 1)
+    n = 256
+    m = oracle.Model(n=n, box=BOX * n / N, gravity="fr_hs", fr0_abs=fr0, factorisation="t1")
+    tab = growth.tables(m, a)                         # excluded, as on the GPU side
+    w = white_noise(n, seed)
+    amp = oracle.cosmology.sigma8_amplitude(m)
+    t0 = time.perf_counter()
+    p1, p2 = fields.displace(w, m, a, tab, amp)
+    dt = time.perf_counter() - t0
+    return {"value": n ** 3 / dt, "unit": "grid-cells/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"one {n}^3 realisation (L={BOX * n / N:.0f} Mpc/h, same 2 Mpc/h cells), "
+                      f"|f_R0|={fr0:g}, a={a}, seed {seed}; growth tables excluded; {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=32)
+    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 companion measurement")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1909_06282_amd import LPT2Config, Plan
+    from seeded_inputs import white_noise
+
+    dev = torch.device("cuda:0")
+    combos = [(f, z, s) for f in FR0S for z in REDSHIFTS for s in SEEDS]
+
+    def make_plans(prec):
+        return {f: Plan(LPT2Config(n=N, box=BOX, gravity="fr_hs", fr0_abs=f, factorisation="t1",
+                                   precision=prec)) for f in FR0S}
+
+    # ---------------- FP32 headline ----------------
+    plans = make_plans("fp32")
+    noise = {s: torch.from_numpy(white_noise(N, s, np.float32)).to(dev) for s in SEEDS}
+    psi1 = torch.empty((3, N, N, N), dtype=torch.float32, device=dev)
+    psi2 = torch.empty_like(psi1)
+    stream = torch.cuda.current_stream()
+
+    def step(i):
+        f, z, s = combos[i % len(combos)]
+        plans[f].displace(1.0 / (1.0 + z), noise[s], psi1, psi2, stream=stream)
+
+    for i in range(max(args.warmup, len(combos))):    # builds every (model, a) table once
+        step(i)
+    torch.cuda.synchronize()
+    for p in plans.values():
+        p.profile_reset()
+        p.profile_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.steps):
+        step(i)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    kernels = {}
+    for p in plans.values():
+        for name, launches, ms, by in p.profile():
+            k = kernels.setdefault(name, [0, 0.0, by])
+            k[0] += launches
+            k[1] += ms
+        p.profile_enable(False)
+    ms_per_step = wall * 1e3 / args.steps
+    cells = float(N) ** 3
+    value = cells * args.steps / wall
+    dom = max(kernels.items(), key=lambda kv: kv[1][1])
+    dname, (dl, dms, dbytes) = dom
+    davg_s = dms / dl / 1e3
+    achieved = dbytes / davg_s / 1e9
+    breakdown = {k: {"launches": v[0], "avg_ms": round(v[1] / v[0], 4), "GB_per_launch": round(v[2] / 1e9, 4),
+                     "GBps": round(v[2] / (v[1] / v[0] / 1e3) / 1e9, 1) if v[1] > 0 else None,
+                     "share": round(v[1] / sum(x[1] for x in kernels.values()), 3)}
+                 for k, v in sorted(kernels.items(), key=lambda kv: -kv[1][1])}
+
+    # FP32 error against the FP64 GPU path (itself parity-tested against the oracle)
+    extra = {}
+    if not args.no_fp64:
+        f, z, s = combos[0]
+        plans[f].displace(1.0 / (1.0 + z), noise[s], psi1, psi2, stream=stream)
+        torch.cuda.synchronize()
+        ref32 = (psi1.clone(), psi2.clone())
+        del plans, noise, psi1, psi2
+        torch.cuda.empty_cache()
+        p64 = make_plans("fp64")
+        w64 = torch.from_numpy(white_noise(N, s)).to(dev)
+        q1 = torch.empty((3, N, N, N), dtype=torch.float64, device=dev)
+        q2 = torch.empty_like(q1)
+        a = 1.0 / (1.0 + z)
+        for _ in range(2):
+            p64[f].displace(a, w64, q1, q2)
+        torch.cuda.synchronize()
+        k64 = max(4, args.steps // 4)
+        t0 = time.perf_counter()
+        for _ in range(k64):
+            p64[f].displace(a, w64, q1, q2)
+        torch.cuda.synchronize()
+        w64t = time.perf_counter() - t0
+        tot = (q1 + q2).abs().max().item()
+        err = max((ref32[0].double() - q1).abs().max().item(), (ref32[1].double() - q2).abs().max().item())
+        errt = ((ref32[0].double() + ref32[1].double()) - (q1 + q2)).abs().max().item()
+        extra["fp64"] = {"value": cells * k64 / w64t, "ms_per_step": round(w64t * 1e3 / k64, 3), "steps": k64,
+                         "config": f"|f_R0|={f:g}, z={z:g}, seed {s}"}
+        extra["fp32_error_vs_fp64"] = {"max_abs_psi_component": err, "max_abs_total": errt,
+                                       "normwise_total": errt / tot}
+        del p64, q1, q2, w64
+        torch.cuda.empty_cache()
+
+    out = {
+        "metric": "2LPT grid-cells/s at 512^3 f(R), FP32 vs FP64 at stated error; % HBM peak",
+        "value": value,
+        "unit": "grid-cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "gpu_ms_per_step": round(gpu_ms / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "512^3 grid, L=1024 Mpc/h, Hu-Sawicki n=1 |f_R0| in {1e-6,1e-4}, z in {0,1}, "
+                               "seeds 1-4 (16 combinations cycled), T1 D2(k,a), FP32 fields, FP64 growth tables",
+                   "grid": N, "box_mpc_h": BOX, "global_batch": 1, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dname, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic_for(dname, dbytes), "bytes_per_launch": dbytes,
+                     "avg_launch_ms": round(davg_s * 1e3, 4)},
+        "kernels": breakdown,
+        "algorithmic_GBps_whole_step": round(sum(v[2] * v[0] for v in kernels.values()) / args.steps
+                                             / (gpu_ms / args.steps / 1e3) / 1e9, 1),
+        "source_hash": source_hash(),
+    }
+    out.update(extra)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(*combos[0][:1], 1.0, 1)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,170 @@
+"""Parity at the workload sizes, in the launch configuration bench.py times.
+
+  * C2: 256^3, L = 512, |f_R0| = 1e-5, z = 0: FP64 <= 1e-12 and FP32 <= 1e-5
+    against the full FP64 oracle; the 128-bin source spectrum;
+  * C3: 512^3, L = 1024, FP32 against the full FP64 oracle (one seed per
+    (|f_R0|, z) corner is too slow for the oracle; seed 1 at F6 z = 0 and F4
+    z = 1 are checked);
+  * C4: the 128^3 and 64^3 members of the batched mix, FP32;
+  * C5: the adjoint at 128^3: FP32 gradient against the FP64 oracle's
+    autograd gradient, and the FP64 GPU gradient against central finite
+    differences (eps = 1e-3) on 64 cells.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import adjoint, cic, fields, growth, spectrum
+from seeded_inputs import cell_sample, white_noise
+from tests._util import gpu_config, normwise, oracle_model, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.set_num_threads(min(16, torch.get_num_threads()))
+
+
+def _plan(**kw):
+    from paper_1909_06282_amd import Plan
+    cfg = gpu_config(**kw)
+    return Plan(cfg), cfg
+
+
+def _parity(prec, a, seed, tol, **kw):
+    plan, cfg = _plan(precision=prec, **kw)
+    m = oracle_model(cfg)
+    w = white_noise(cfg.n, seed)
+    p1, p2 = plan.displace(a, to_dev(w, cfg.dtype))
+    torch.cuda.synchronize()
+    g1, g2 = p1.cpu().double(), p2.cpu().double()
+    del p1, p2
+    plan.close()
+    r1, r2 = fields.displace(w, m, a, growth.tables(m, a))
+    e1, e2, et = normwise(g1, r1), normwise(g2, r2), normwise(g1 + g2, r1 + r2)
+    print(f"  {prec} n={cfg.n} a={a}: psi1 {e1:.3e} psi2 {e2:.3e} total {et:.3e}", flush=True)
+    assert e1 < tol and e2 < tol and et < tol
+
+
+C2 = dict(n=256, box=512.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1")
+C3 = dict(n=512, box=1024.0, gravity="fr_hs", factorisation="t1")
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_c2_displacements(prec, tol):
+    print(f"C2 {prec}", flush=True)
+    _parity(prec, 1.0, 1, tol, **C2)
+
+
+def test_c2_source_spectrum_128_bins():
+    print("C2 spectrum", flush=True)
+    plan, cfg = _plan(precision="fp64", **C2)
+    w = white_noise(cfg.n, 1)
+    got = plan.source_spectrum(1.0, to_dev(w, torch.float64), 128, "power")
+    m = oracle_model(cfg)
+    sk = fields.source_k(fields.source(fields.delta_k(w, m), m), m)
+    km, cnt, mean, std = spectrum.source_power(sk, m, 128)
+    assert np.array_equal(got["count"], cnt)
+    nz = cnt > 0
+    assert np.max(np.abs(got["mean"][nz] / mean[nz] - 1)) < 1e-10
+    assert np.max(np.abs(got["std"][nz] / std[nz] - 1)) < 1e-8
+    plan.close()
+
+
+@pytest.mark.parametrize("fr0,z", [(1e-6, 0.0), (1e-4, 1.0)])
+def test_c3_fp32_displacements(fr0, z):
+    print(f"C3 fp32 fr0={fr0} z={z}", flush=True)
+    _parity("fp32", 1.0 / (1.0 + z), 1, 1e-5, fr0_abs=fr0, **C3)
+
+
+@pytest.mark.parametrize("n,box,seed", [(128, 256.0, 100), (64, 128.0, 164)])
+def test_c4_members_fp32(n, box, seed):
+    print(f"C4 member n={n}", flush=True)
+    _parity("fp32", 1.0, seed, 1e-5, n=n, box=box, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1")
+
+
+def _c5_loss_pieces(prec):
+    from paper_1909_06282_amd import Displace, PaintCIC
+    plan, cfg = _plan(precision=prec, n=128, box=256.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1")
+    with torch.no_grad():
+        t1, t2 = plan.displace(1.0, to_dev(white_noise(128, 7), cfg.dtype))
+        target = plan.paint_cic(t1, t2).clone()
+
+    def loss(wt):
+        p1, p2 = Displace.apply(wt, plan, 1.0)
+        d = PaintCIC.apply(p1, p2, plan)
+        return ((d - target) ** 2).sum()
+    return plan, cfg, loss, target
+
+
+def test_c5_adjoint_fp64_vs_oracle_autograd():
+    # FP64 on both sides: particle positions agree to ~1e-15 cells, so no
+    # particle lands on a different side of a CIC cell face and the two
+    # gradients must agree to rounding.
+    print("C5 adjoint fp64 vs oracle", flush=True)
+    plan, cfg, loss, target = _c5_loss_pieces("fp64")
+    w = white_noise(128, 1)
+    wt = to_dev(w, torch.float64).requires_grad_(True)
+    loss(wt).backward()
+    m = oracle_model(cfg)
+    _, gref = adjoint.loss_and_grad(w, target.cpu(), m, 1.0, growth.tables(m, 1.0))
+    err = normwise(wt.grad, gref)
+    print(f"  gradient normwise error {err:.3e}", flush=True)
+    assert err < 1e-9
+
+
+def test_c5_adjoint_fp32_vs_fp64_gpu():
+    # The FP32 gradient differs from the FP64 one where an FP32 particle
+    # position falls on the other side of a CIC cell face (the CIC weight
+    # slope jumps there).  With position errors ~1e-6 cells about
+    # 3 n^3 1e-6 ~ a few particles flip; each moves the gradient by an O(1)
+    # share of one particle's contribution, i.e. a relative L2 change of order
+    # sqrt(flips / n^3) ~ 1e-3.  Tolerance: relative L2 <= 2e-3, loss <= 1e-5.
+    print("C5 adjoint fp32 vs fp64", flush=True)
+    w = white_noise(128, 1)
+    out = {}
+    for prec in ("fp64", "fp32"):
+        plan, cfg, loss, target = _c5_loss_pieces(prec)
+        wt = to_dev(w, cfg.dtype).requires_grad_(True)
+        L = loss(wt)
+        L.backward()
+        out[prec] = (float(L), wt.grad.double().cpu())
+        plan.close()
+    l64, g64 = out["fp64"]
+    l32, g32 = out["fp32"]
+    l2 = float((g32 - g64).norm() / g64.norm())
+    print(f"  loss rel {abs(l32 / l64 - 1):.3e} gradient relative L2 {l2:.3e} normwise {normwise(g32, g64):.3e}",
+          flush=True)
+    assert abs(l32 / l64 - 1) < 1e-5
+    assert l2 < 2e-3
+
+
+def test_c5_adjoint_fp64_vs_finite_differences():
+    print("C5 adjoint fp64 vs FD", flush=True)
+    plan, cfg, loss, _ = _c5_loss_pieces("fp64")
+    w = to_dev(white_noise(128, 1), torch.float64)
+    wt = w.clone().requires_grad_(True)
+    loss(wt).backward()
+    g = wt.grad.reshape(-1)
+    cells = cell_sample(128, 64, seed=0)
+
+    def fd(c, eps):
+        with torch.no_grad():
+            wp = w.clone().reshape(-1); wp[c] += eps
+            wm = w.clone().reshape(-1); wm[c] -= eps
+            return (loss(wp.reshape(w.shape)) - loss(wm.reshape(w.shape))).item() / (2 * eps)
+
+    mis = np.array([abs(fd(c, 1e-3) - g[c].item()) / max(1.0, abs(g[c].item())) for c in cells])
+    order = np.argsort(mis)[::-1]
+    print(f"  FD mismatch quantiles 50% {np.median(mis):.2e} 90% {np.quantile(mis, 0.9):.2e} max {mis.max():.2e}",
+          flush=True)
+    for i in order[:4]:
+        c = cells[i]
+        print(f"  cell {c}: grad {g[c].item():.6e} fd(1e-3) {fd(c, 1e-3):.6e} fd(3e-4) {fd(c, 3e-4):.6e} "
+              f"fd(1e-4) {fd(c, 1e-4):.6e}", flush=True)
+    assert np.median(mis) < 1e-3
+    assert mis.max() < 5e-2
