@@ -142,10 +142,10 @@ __device__ __forceinline__ void exchange(Cx<T>* v, int t, Cx<T>* lb) {
 // ---- full transform -----------------------------------------------------------
 // In: slots in the first-stage pattern of the direction's plan.
 // Out: slots in the last-stage pattern.  D = -1 forward, +1 inverse.
-template <typename T, int L, int D, int ES>
+template <typename T, int L, int D, int ES, int E = elems_per_thread(L)>
 __device__ __forceinline__ void fft(Cx<T>* v, int t, const Cx<T>* __restrict__ tw, int tws, Cx<T>* lb) {
   constexpr bool INV = D > 0;
-  constexpr int E = elems_per_thread(L);
+  static_assert(E % plan_radix(L, 0, INV) == 0 && L % E == 0, "E must be a multiple of every radix");
   constexpr int NST = plan_stages(L);
   constexpr int R0 = plan_radix(L, 0, INV);
   constexpr int R1 = plan_radix(L, 1, INV);

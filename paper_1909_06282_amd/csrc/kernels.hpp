@@ -31,21 +31,43 @@ struct XOp {
   const double* tables[16];
 };
 
+// Per-field power of m_z applied to a half-spectrum line before the inverse
+// z transform: field f = line / lines_per_field is multiplied by m_z^r[f]
+// (r in {0, 1, 2}).
+constexpr int ZPOW_MAX = 16;
+struct ZPow {
+  long lines_per_field;
+  int r[ZPOW_MAX];
+};
+ZPow zpow_none(long lines_per_field);
+
+// Fused inverse y pass: output o = F^-1_y[ m_y^pw[o] * input src[o] ]
+// (outputs grouped by source field).
+constexpr int YOP_MAX = 16;
+struct YOp {
+  int nin, nout;
+  int src[YOP_MAX], pw[YOP_MAX];
+};
+
 // z axis (contiguous): nlines lines of n reals <-> n/2 complex
 hipError_t launch_zr2c(int prec, int n, const void* in, size_t in_cap, void* out, size_t out_cap, long nlines,
                        const void* tw, hipStream_t s);
 hipError_t launch_zc2r(int prec, int n, const void* in, size_t in_cap, void* out, size_t out_cap, long nlines,
-                       const void* tw, hipStream_t s);
+                       const ZPow& zp, const void* tw, hipStream_t s);
 // strided complex column FFT in place: nplanes planes of ncols columns,
 // element (row, col) of plane p at data + p*plane_stride + row*rowstride + col
 hipError_t launch_colfft(int prec, int n, int dir, void* data, size_t cap, long nplanes, long plane_stride,
                          int ncols, long rowstride, const void* tw, hipStream_t s);
+// fused inverse y pass over the n planes x n/2 columns of each field
+hipError_t launch_ycombo(int prec, int n, const void* in, size_t in_cap, long in_fstride, void* out, size_t out_cap,
+                         long out_fstride, const YOp& op, const void* tw, hipStream_t s);
 // fused x pass over the n*(n/2) columns of each field
 hipError_t launch_xpass(int prec, int n, const void* in, size_t in_cap, long in_fstride, void* out, size_t out_cap,
                         long out_fstride, const XOp& op, long n2cnt, const void* tw, hipStream_t s);
 // z pass: 6 phi_,ij half-spectrum lines (xx,yy,zz,xy,xz,yz at fstride) -> S(k) line
-hipError_t launch_zsource(int prec, int n, const void* phi, size_t phi_cap, long fstride, void* sk, size_t sk_cap,
-                          long nlines, const void* tw, hipStream_t s);
+// (field f of the six multiplied by m_z^zp.r[f] first)
+hipError_t launch_zsource(int prec, int n, const void* phi, size_t phi_cap, long fstride, const ZPow& zp, void* sk,
+                          size_t sk_cap, long nlines, const void* tw, hipStream_t s);
 // z pass of the adjoint: 6 phi lines + real S_bar line -> 6 phi_bar half-spectrum lines
 hipError_t launch_zprodrule(int prec, int n, const void* phi, size_t phi_cap, long fstride, const void* sbar,
                             size_t sbar_cap, void* out, size_t out_cap, long out_fstride, long nlines, const void* tw,

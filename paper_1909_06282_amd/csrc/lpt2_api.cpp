@@ -67,7 +67,7 @@ struct lpt2_plan_s {
 
 namespace {
 
-constexpr int WS_FIELDS = 12;  // half-spectrum-sized slots in the workspace
+constexpr int WS_FIELDS = 16;  // half-spectrum-sized slots in the workspace
 
 lpt2_status fail(lpt2_plan_t p, lpt2_status st, const std::string& msg) {
   if (p)
@@ -370,21 +370,48 @@ lpt2_status xp(Ctx& c, const char* name, const void* in, void* out, const XOp& o
       launch_xpass(p->prec, g.n, in, c.cap(in), fst, out, c.cap(out), fst, op, g.n2cnt, g.tw, s));
   return LPT2_OK;
 }
-lpt2_status z_c2r(Ctx& c, const char* name, const void* in, void* out, size_t out_cap, int nf) {
+lpt2_status z_c2r(Ctx& c, const char* name, const void* in, void* out, size_t out_cap, int nf,
+                  const int* rpow = nullptr) {
   lpt2_plan_t p = c.p;
   hipStream_t s = c.s;
   Grid& g = c.g;
   const double fb = (double)c.field();
-  RUN(name, 2.0 * fb * nf, launch_zc2r(p->prec, g.n, in, c.cap(in), out, out_cap, (long)nf * g.n * g.n, g.tw, s));
+  ZPow zp = zpow_none((long)g.n * g.n);
+  if (rpow)
+    for (int f = 0; f < nf && f < ZPOW_MAX; ++f) zp.r[f] = rpow[f];
+  RUN(name, 2.0 * fb * nf,
+      launch_zc2r(p->prec, g.n, in, c.cap(in), out, out_cap, (long)nf * g.n * g.n, zp, g.tw, s));
   return LPT2_OK;
 }
-lpt2_status z_source(Ctx& c, const void* phi, void* sk) {
+lpt2_status z_source(Ctx& c, const void* phi, void* sk, const int* rpow = nullptr) {
   lpt2_plan_t p = c.p;
   hipStream_t s = c.s;
   Grid& g = c.g;
+  ZPow zp = zpow_none((long)g.n * g.n);
+  if (rpow)
+    for (int f = 0; f < 6; ++f) zp.r[f] = rpow[f];
   RUN("z_fused_source", (double)c.field() * 7.0,
-      launch_zsource(p->prec, g.n, phi, c.cap(phi), g.nnm, sk, c.cap(sk), (long)g.n * g.n, g.tw, s));
+      launch_zsource(p->prec, g.n, phi, c.cap(phi), g.nnm, zp, sk, c.cap(sk), (long)g.n * g.n, g.tw, s));
   return LPT2_OK;
+}
+lpt2_status ycombo(Ctx& c, const char* name, const void* in, void* out, const YOp& op) {
+  lpt2_plan_t p = c.p;
+  hipStream_t s = c.s;
+  Grid& g = c.g;
+  RUN(name, (double)c.field() * (op.nin + op.nout),
+      launch_ycombo(p->prec, g.n, in, c.cap(in), g.nnm, out, c.cap(out), g.nnm, op, g.tw, s));
+  return LPT2_OK;
+}
+YOp yop(int nin, int nout, const int* src, const int* pw) {
+  YOp op;
+  std::memset(&op, 0, sizeof(op));
+  op.nin = nin;
+  op.nout = nout;
+  for (int o = 0; o < nout; ++o) {
+    op.src[o] = src[o];
+    op.pw[o] = pw[o];
+  }
+  return op;
 }
 #define CHK(x)                      \
   do {                              \
@@ -392,25 +419,42 @@ lpt2_status z_source(Ctx& c, const void* phi, void* sk) {
     if (st_ != LPT2_OK) return st_; \
   } while (0)
 
-// psi1, psi2 of one realisation (see lpt2_displace); slots 0..10
+// psi1, psi2 of one realisation (see lpt2_displace).  The k-space factors
+// are split by axis: the radial part (and k_x) is applied in the x pass,
+// k_y in the y pass and k_z in the z pass, so five x-transforms carry the
+// nine fields:  U_p = F_x^-1[-k_x^p A/k^2 X] (p = 0,1,2),
+// V_p = F_x^-1[i k_x^p A D1/k^2 X] (p = 0,1), and e.g.
+// phi_yz = F_z^-1[k_z F_y^-1[k_y U_0]] (integer mode numbers throughout;
+// the (2 pi/L) factors sit in the radial tables).  Slots 0..14.
 lpt2_status displace_one(Ctx& c, const Tables* t, const void* noise, void* psi1, void* psi2) {
   Grid& g = c.g;
   CHK(fwd_zy(c, "z_r2c_noise", "y_fwd_noise", noise, c.field(), c.slot(0), 1));
-  XOp op = op_blank(1, 9, 1);
+  XOp op = op_blank(1, 5, 1);
   op_tables(op, g, t);
-  for (int i = 0; i < 3; ++i) op_set(op, i, MUL_PI, i, -1, TAB_PSI1, 1.0);
-  for (int q = 0; q < 6; ++q) op_set(op, 3 + q, MUL_REAL, PI_[q], PJ_[q], TAB_PHI, -1.0);
+  op_set(op, 0, MUL_REAL, -1, -1, TAB_PHI, -1.0);  // U0
+  op_set(op, 1, MUL_REAL, 0, -1, TAB_PHI, -1.0);   // U1
+  op_set(op, 2, MUL_REAL, 0, 0, TAB_PHI, -1.0);    // U2
+  op_set(op, 3, MUL_PI, -1, -1, TAB_PSI1, 1.0);    // V0
+  op_set(op, 4, MUL_PI, 0, -1, TAB_PSI1, 1.0);     // V1
   CHK(xp(c, "x_fused_psi1_phi", c.slot(0), c.slot(1), op));
-  CHK(inv_y(c, "y_inv_psi1_phi", c.slot(1), 9));
-  CHK(z_c2r(c, "z_c2r_psi1", c.slot(1), psi1, 3 * c.field(), 3));
-  CHK(z_source(c, c.slot(4), c.slot(10)));
-  CHK(fwd_y(c, "y_fwd_source", c.slot(10), 1));
-  XOp o2 = op_blank(1, 3, 1);
+  // outputs: psi1 x,y,z then phi xx,yy,zz,xy,xz,yz (inputs U0,U1,U2,V0,V1 = 0..4)
+  const int src9[9] = {4, 3, 3, 2, 0, 0, 1, 1, 0};
+  const int pw9[9] = {0, 1, 0, 0, 2, 0, 1, 0, 1};
+  CHK(ycombo(c, "y_inv_psi1_phi", c.slot(1), c.slot(6), yop(5, 9, src9, pw9)));
+  const int rz1[3] = {0, 0, 1};
+  CHK(z_c2r(c, "z_c2r_psi1", c.slot(6), psi1, 3 * c.field(), 3, rz1));
+  const int rzs[6] = {0, 0, 2, 0, 1, 1};
+  CHK(z_source(c, c.slot(9), c.slot(0), rzs));
+  CHK(fwd_y(c, "y_fwd_source", c.slot(0), 1));
+  XOp o2 = op_blank(1, 2, 1);
   op_tables(o2, g, t);
-  for (int i = 0; i < 3; ++i) op_set(o2, i, MUL_MI, i, -1, TAB_PSI2, 1.0);
-  CHK(xp(c, "x_fused_psi2", c.slot(10), c.slot(1), o2));
-  CHK(inv_y(c, "y_inv_psi2", c.slot(1), 3));
-  CHK(z_c2r(c, "z_c2r_psi2", c.slot(1), psi2, 3 * c.field(), 3));
+  op_set(o2, 0, MUL_MI, -1, -1, TAB_PSI2, 1.0);  // Q0
+  op_set(o2, 1, MUL_MI, 0, -1, TAB_PSI2, 1.0);   // Q1
+  CHK(xp(c, "x_fused_psi2", c.slot(0), c.slot(1), o2));
+  const int src3[3] = {1, 0, 0};
+  const int pw3[3] = {0, 1, 0};
+  CHK(ycombo(c, "y_inv_psi2", c.slot(1), c.slot(3), yop(2, 3, src3, pw3)));
+  CHK(z_c2r(c, "z_c2r_psi2", c.slot(3), psi2, 3 * c.field(), 3, rz1));
   return LPT2_OK;
 }
 
