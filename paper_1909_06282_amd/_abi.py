@@ -5,7 +5,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblpt2.so")
+# LPT2_LIBRARY selects another build of the same ABI (e.g. a tuning variant)
+LIB_PATH = os.environ.get("LPT2_LIBRARY") or os.path.join(HERE, "liblpt2.so")
 
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
 FP64, FP32 = 0, 1

@@ -113,6 +113,9 @@ __global__ void k_radial(RadialSetup r, const double* __restrict__ d1n, const do
     }
   }
   for (int i = 0; i < TAB_COUNT; ++i) tabs[i * n2cnt + n2] = v[i];
+  double* pair = tabs + (long)TAB_COUNT * n2cnt;
+  pair[2 * n2] = v[TAB_PHI];
+  pair[2 * n2 + 1] = v[TAB_PSI1];
 }
 
 hipError_t launch_radial(const RadialSetup& r, const double* d1n, const double* d2n, double* tabs, long n2cnt,

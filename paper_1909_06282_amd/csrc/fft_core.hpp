@@ -118,45 +118,89 @@ __device__ __forceinline__ void stage(Cx<T>* v, int t, const Cx<T>* __restrict__
 
 // ---- LDS exchange between stages ------------------------------------------------
 // lb points at element 0 of this thread's transform; element e lives at
-// lb[e * ES].  The leading barrier protects LDS still being read by the
-// previous phase of the kernel.
-template <typename T, int L, int E, int ROUT, int NSOUT, int RIN, int ES>
-__device__ __forceinline__ void exchange(Cx<T>* v, int t, Cx<T>* lb) {
+// lb[lds_index<PAD>(e) * ES].  PAD inserts one spare slot after every 8
+// elements, which makes the stride-8 write of a first radix-8 stage
+// bank-conflict free when one transform's threads sit in adjacent lanes.
+//
+// Synchronisation (SY):
+//   SY_BLOCK: a transform spans several wavefronts; a workgroup barrier
+//             before the writes (protects the previous reads) and after them;
+//   SY_WAVE:  a transform lies inside one wavefront; LDS operations of a
+//             wavefront complete in order, so only the compiler must be kept
+//             from moving loads and stores across the exchange;
+//   SY_PING:  as SY_BLOCK but alternating between two LDS buffers (`phase`
+//             counts exchanges), so the barrier before the writes is not needed.
+enum { SY_BLOCK = 0, SY_WAVE = 1, SY_PING = 2 };
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int SY>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (SY == SY_WAVE)
+    wave_sync();
+  else
+    __syncthreads();
+}
+
+template <bool PAD>
+__device__ __forceinline__ int lds_index(int e) {
+  return PAD ? e + (e >> 3) : e;
+}
+// LDS slots needed by one transform of length L
+template <bool PAD>
+constexpr int lds_span(int L) { return PAD ? L + L / 8 : L; }
+
+template <typename T, int L, int E, int ROUT, int NSOUT, int RIN, int ES, int SY, bool PAD>
+__device__ __forceinline__ void exchange(Cx<T>* v, int t, Cx<T>* lb, int pingstride, int& phase) {
   constexpr int TP = L / E;
-  __syncthreads();
+  if constexpr (SY == SY_PING) {
+    lb += (phase & 1) * pingstride;
+    ++phase;
+  } else {
+    lds_sync<SY>();
+  }
 #pragma unroll
   for (int u = 0; u < E / ROUT; ++u) {
     const int b = t + u * TP;
     const int k = b & (NSOUT - 1);
     const int base = (b - k) * ROUT + k;
 #pragma unroll
-    for (int q = 0; q < ROUT; ++q) lb[(base + q * NSOUT) * ES] = v[u * ROUT + q];
+    for (int q = 0; q < ROUT; ++q) lb[lds_index<PAD>(base + q * NSOUT) * ES] = v[u * ROUT + q];
   }
-  __syncthreads();
+  lds_sync<SY>();
 #pragma unroll
   for (int u = 0; u < E / RIN; ++u)
 #pragma unroll
-    for (int j = 0; j < RIN; ++j) v[u * RIN + j] = lb[(t + u * TP + j * (L / RIN)) * ES];
+    for (int j = 0; j < RIN; ++j) v[u * RIN + j] = lb[lds_index<PAD>(t + u * TP + j * (L / RIN)) * ES];
 }
 
 // ---- full transform -----------------------------------------------------------
 // In: slots in the first-stage pattern of the direction's plan.
 // Out: slots in the last-stage pattern.  D = -1 forward, +1 inverse.
-template <typename T, int L, int D, int ES, int E = elems_per_thread(L)>
-__device__ __forceinline__ void fft(Cx<T>* v, int t, const Cx<T>* __restrict__ tw, int tws, Cx<T>* lb) {
+// For SY_PING, lb + pingstride is the second buffer and `phase` persists
+// across the transforms of a kernel.
+template <typename T, int L, int D, int ES, int SY = SY_BLOCK, bool PAD = false, int E = elems_per_thread(L)>
+__device__ __forceinline__ void fft(Cx<T>* v, int t, const Cx<T>* __restrict__ tw, int tws, Cx<T>* lb,
+                                    int pingstride = 0, int* phase = nullptr) {
   constexpr bool INV = D > 0;
   static_assert(E % plan_radix(L, 0, INV) == 0 && L % E == 0, "E must be a multiple of every radix");
   constexpr int NST = plan_stages(L);
   constexpr int R0 = plan_radix(L, 0, INV);
   constexpr int R1 = plan_radix(L, 1, INV);
   constexpr int R2 = plan_radix(L, 2, INV);
+  int dummy = 0;
+  int& ph = phase ? *phase : dummy;
   stage<T, L, E, R0, 1, D>(v, t, tw, tws);
   if constexpr (NST > 1) {
-    exchange<T, L, E, R0, 1, R1, ES>(v, t, lb);
+    exchange<T, L, E, R0, 1, R1, ES, SY, PAD>(v, t, lb, pingstride, ph);
     stage<T, L, E, R1, R0, D>(v, t, tw, tws);
   }
   if constexpr (NST > 2) {
-    exchange<T, L, E, R1, R0, R2, ES>(v, t, lb);
+    exchange<T, L, E, R1, R0, R2, ES, SY, PAD>(v, t, lb, pingstride, ph);
     stage<T, L, E, R2, R0 * R1, D>(v, t, tw, tws);
   }
 }

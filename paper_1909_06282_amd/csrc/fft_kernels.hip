@@ -34,6 +34,8 @@ struct LineCfg {
   static constexpr int R0I = plan_first(L, true);       // inverse first radix
   static constexpr int RLI = plan_last(L, true);        // inverse last radix (== R0F)
   static_assert(RLI == R0F, "inverse plan must end with the forward first radix");
+  static_assert(TPL <= 64 && 64 % TPL == 0, "a line must lie inside one wavefront");
+  static constexpr int SPAN = lds_span<true>(L);       // LDS slots per line (padded)
 };
 
 template <typename T, int N>
@@ -63,15 +65,15 @@ __device__ __forceinline__ void load_real_line(const T* src, Cx<T>* v, int t, bo
 template <typename T, int N>
 __device__ __forceinline__ void r2c_finish(Cx<T>* v, int t, Cx<T>* lb, const Cx<T>* stw, Cx<T>* dst, bool act) {
   using C = LineCfg<N>;
-  __syncthreads();
+  wave_sync();
 #pragma unroll
-  for (int sl = 0; sl < C::E; ++sl) lb[slot_elem<C::L, C::E, C::RLF>(t, sl)] = v[sl];
-  __syncthreads();
+  for (int sl = 0; sl < C::E; ++sl) lb[lds_index<true>(slot_elem<C::L, C::E, C::RLF>(t, sl))] = v[sl];
+  wave_sync();
 #pragma unroll
   for (int s = 0; s < C::E; ++s) {
     const int k = t + s * C::TPL;
-    const Cx<T> z = lb[k];
-    const Cx<T> zc = conj(lb[(C::L - k) & (C::L - 1)]);
+    const Cx<T> z = lb[lds_index<true>(k)];
+    const Cx<T> zc = conj(lb[lds_index<true>((C::L - k) & (C::L - 1))]);
     const Cx<T> a = scale(z + zc, T(0.5));
     const Cx<T> wb = stw[k] * scale(z - zc, T(0.5));
     if (act) dst[k] = mk(a.x + wb.y, a.y - wb.x);
@@ -87,23 +89,23 @@ template <typename T, int N>
 __device__ __forceinline__ void c2r_prepare(const Cx<T>* src, int r, Cx<T>* v, int t, Cx<T>* lb, const Cx<T>* stw,
                                             bool act) {
   using C = LineCfg<N>;
-  __syncthreads();
+  wave_sync();
 #pragma unroll
   for (int s = 0; s < C::E; ++s) {
     const int k = t + s * C::TPL;
-    lb[k] = act ? scale(src[k], mpow<T>(k, r)) : zero<T>();
+    lb[lds_index<true>(k)] = act ? scale(src[k], mpow<T>(k, r)) : zero<T>();
   }
-  __syncthreads();
+  wave_sync();
 #pragma unroll
   for (int sl = 0; sl < C::E; ++sl) {
     const int e = slot_elem<C::L, C::E, C::R0I>(t, sl);
-    Cx<T> x = lb[e];
+    Cx<T> x = lb[lds_index<true>(e)];
     Cx<T> xc;
     if (e == 0) {
       x.y = T(0);
       xc = zero<T>();
     } else {
-      xc = conj(lb[C::L - e]);
+      xc = conj(lb[lds_index<true>(C::L - e)]);
     }
     const Cx<T> ek = x + xc;
     const Cx<T> ok = (x - xc) * conj(stw[e]);
@@ -114,17 +116,17 @@ __device__ __forceinline__ void c2r_prepare(const Cx<T>* src, int r, Cx<T>* v, i
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_zr2c(const T* in, Cx<T>* out, long nlines, const Cx<T>* __restrict__ tw) {
   using C = LineCfg<N>;
-  __shared__ Cx<T> lds[C::G * C::L];
+  __shared__ Cx<T> lds[C::G * C::SPAN];
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
   const int t = threadIdx.x % C::TPL, g = threadIdx.x / C::TPL;
   const long line = (long)blockIdx.x * C::G + g;
   const bool act = line < nlines;
   const long lsafe = act ? line : 0;
-  Cx<T>* lb = lds + g * C::L;
+  Cx<T>* lb = lds + g * C::SPAN;
   Cx<T> v[C::E];
   load_real_line<T, N>(in + lsafe * N, v, t, act);
-  fft<T, C::L, -1, 1>(v, t, stw, 2, lb);
+  fft<T, C::L, -1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
   r2c_finish<T, N>(v, t, lb, stw, out + lsafe * C::L, act);
 }
 
@@ -133,7 +135,7 @@ template <typename T, int N>
 __global__ __launch_bounds__(256) void k_zc2r(const Cx<T>* in, T* out, long nlines, ZPow zp,
                                               const Cx<T>* __restrict__ tw) {
   using C = LineCfg<N>;
-  __shared__ Cx<T> lds[C::G * C::L];
+  __shared__ Cx<T> lds[C::G * C::SPAN];
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
   const int t = threadIdx.x % C::TPL, g = threadIdx.x / C::TPL;
@@ -142,10 +144,10 @@ __global__ __launch_bounds__(256) void k_zc2r(const Cx<T>* in, T* out, long nlin
   const long lsafe = act ? line : 0;
   const int f = (int)(lsafe / zp.lines_per_field);
   const int r = f < ZPOW_MAX ? zp.r[f] : 0;
-  Cx<T>* lb = lds + g * C::L;
+  Cx<T>* lb = lds + g * C::SPAN;
   Cx<T> v[C::E];
   c2r_prepare<T, N>(in + lsafe * C::L, r, v, t, lb, stw, act);
-  fft<T, C::L, +1, 1>(v, t, stw, 2, lb);
+  fft<T, C::L, +1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
   Cx<T>* d2 = reinterpret_cast<Cx<T>*>(out + lsafe * N);
   if (act) {
 #pragma unroll
@@ -160,39 +162,39 @@ template <typename T, int N>
 __global__ __launch_bounds__(256) void k_zsource(const Cx<T>* __restrict__ phi, long fstride, ZPow zp,
                                                  Cx<T>* __restrict__ sk, long nlines, const Cx<T>* __restrict__ tw) {
   using C = LineCfg<N>;
-  __shared__ Cx<T> lds[C::G * C::L];
+  __shared__ Cx<T> lds[C::G * C::SPAN];
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
   const int t = threadIdx.x % C::TPL, g = threadIdx.x / C::TPL;
   const long line = (long)blockIdx.x * C::G + g;
   const bool act = line < nlines;
   const long lsafe = act ? line : 0;
-  Cx<T>* lb = lds + g * C::L;
+  Cx<T>* lb = lds + g * C::SPAN;
   Cx<T> a[C::E], s[C::E], v[C::E];
   const Cx<T>* src = phi + lsafe * C::L;
   c2r_prepare<T, N>(src, zp.r[0], v, t, lb, stw, act);
-  fft<T, C::L, +1, 1>(v, t, stw, 2, lb);
+  fft<T, C::L, +1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
 #pragma unroll
   for (int i = 0; i < C::E; ++i) a[i] = v[i];
   c2r_prepare<T, N>(src + fstride, zp.r[1], v, t, lb, stw, act);
-  fft<T, C::L, +1, 1>(v, t, stw, 2, lb);
+  fft<T, C::L, +1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
 #pragma unroll
   for (int i = 0; i < C::E; ++i) {
     s[i] = mk(a[i].x * v[i].x, a[i].y * v[i].y);
     a[i] = a[i] + v[i];
   }
   c2r_prepare<T, N>(src + 2 * fstride, zp.r[2], v, t, lb, stw, act);
-  fft<T, C::L, +1, 1>(v, t, stw, 2, lb);
+  fft<T, C::L, +1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
 #pragma unroll
   for (int i = 0; i < C::E; ++i) s[i] = mk(s[i].x + a[i].x * v[i].x, s[i].y + a[i].y * v[i].y);
 #pragma unroll 1
   for (int f = 3; f < 6; ++f) {
     c2r_prepare<T, N>(src + f * fstride, zp.r[f], v, t, lb, stw, act);
-    fft<T, C::L, +1, 1>(v, t, stw, 2, lb);
+    fft<T, C::L, +1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
 #pragma unroll
     for (int i = 0; i < C::E; ++i) s[i] = mk(s[i].x - v[i].x * v[i].x, s[i].y - v[i].y * v[i].y);
   }
-  fft<T, C::L, -1, 1>(s, t, stw, 2, lb);
+  fft<T, C::L, -1, 1, SY_WAVE, true>(s, t, stw, 2, lb);
   r2c_finish<T, N>(s, t, lb, stw, sk + lsafe * C::L, act);
 }
 
@@ -204,43 +206,43 @@ __global__ __launch_bounds__(256) void k_zprodrule(const Cx<T>* phi, long fstrid
                                                    Cx<T>* out, long ofstride, long nlines,
                                                    const Cx<T>* __restrict__ tw) {
   using C = LineCfg<N>;
-  __shared__ Cx<T> lds[C::G * C::L];
+  __shared__ Cx<T> lds[C::G * C::SPAN];
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
   const int t = threadIdx.x % C::TPL, g = threadIdx.x / C::TPL;
   const long line = (long)blockIdx.x * C::G + g;
   const bool act = line < nlines;
   const long lsafe = act ? line : 0;
-  Cx<T>* lb = lds + g * C::L;
+  Cx<T>* lb = lds + g * C::SPAN;
   Cx<T> sb[C::E], d0[C::E], d1[C::E], d2[C::E], v[C::E];
   load_real_line<T, N>(sbar + lsafe * N, sb, t, act);
   const Cx<T>* src = phi + lsafe * C::L;
   c2r_prepare<T, N>(src, 0, d0, t, lb, stw, act);
-  fft<T, C::L, +1, 1>(d0, t, stw, 2, lb);
+  fft<T, C::L, +1, 1, SY_WAVE, true>(d0, t, stw, 2, lb);
   c2r_prepare<T, N>(src + fstride, 0, d1, t, lb, stw, act);
-  fft<T, C::L, +1, 1>(d1, t, stw, 2, lb);
+  fft<T, C::L, +1, 1, SY_WAVE, true>(d1, t, stw, 2, lb);
   c2r_prepare<T, N>(src + 2 * fstride, 0, d2, t, lb, stw, act);
-  fft<T, C::L, +1, 1>(d2, t, stw, 2, lb);
+  fft<T, C::L, +1, 1, SY_WAVE, true>(d2, t, stw, 2, lb);
   Cx<T>* dst = out + lsafe * C::L;
 #pragma unroll
   for (int i = 0; i < C::E; ++i) v[i] = mk(sb[i].x * (d1[i].x + d2[i].x), sb[i].y * (d1[i].y + d2[i].y));
-  fft<T, C::L, -1, 1>(v, t, stw, 2, lb);
+  fft<T, C::L, -1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
   r2c_finish<T, N>(v, t, lb, stw, dst, act);
 #pragma unroll
   for (int i = 0; i < C::E; ++i) v[i] = mk(sb[i].x * (d0[i].x + d2[i].x), sb[i].y * (d0[i].y + d2[i].y));
-  fft<T, C::L, -1, 1>(v, t, stw, 2, lb);
+  fft<T, C::L, -1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
   r2c_finish<T, N>(v, t, lb, stw, dst + ofstride, act);
 #pragma unroll
   for (int i = 0; i < C::E; ++i) v[i] = mk(sb[i].x * (d0[i].x + d1[i].x), sb[i].y * (d0[i].y + d1[i].y));
-  fft<T, C::L, -1, 1>(v, t, stw, 2, lb);
+  fft<T, C::L, -1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
   r2c_finish<T, N>(v, t, lb, stw, dst + 2 * ofstride, act);
 #pragma unroll 1
   for (int f = 3; f < 6; ++f) {
     c2r_prepare<T, N>(src + f * fstride, 0, v, t, lb, stw, act);
-    fft<T, C::L, +1, 1>(v, t, stw, 2, lb);
+    fft<T, C::L, +1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
 #pragma unroll
     for (int i = 0; i < C::E; ++i) v[i] = mk(T(-2) * sb[i].x * v[i].x, T(-2) * sb[i].y * v[i].y);
-    fft<T, C::L, -1, 1>(v, t, stw, 2, lb);
+    fft<T, C::L, -1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
     r2c_finish<T, N>(v, t, lb, stw, dst + f * ofstride, act);
   }
 }
@@ -249,29 +251,45 @@ __global__ __launch_bounds__(256) void k_zprodrule(const Cx<T>* phi, long fstrid
 // strided column kernels: a block takes W adjacent columns of one plane
 // (lane = column fastest), so every row access is W contiguous complex.
 // ---------------------------------------------------------------------------
-// EPT: complex values per thread (8, or 16 for the multi-transform kernels
-// so that their blocks are half as large and two fit on a CU).
-template <typename T, int N, int EPT = elems_per_thread(N)>
+// WW: columns per block; a block is WW * (N/8) threads.  Each (precision,
+// grid size) offers three widths for the tile tuner: half, one and two
+// times the width that gives 128-byte row runs, clamped to blocks of 64..1024
+// threads and to double-buffered tiles that fit the 160 KB LDS.
+constexpr int col_tpc(int N) { return N / elems_per_thread(N); }
+constexpr int pow2_floor(int x) { return x >= 1024 ? 1024 : x >= 512 ? 512 : x >= 256 ? 256 : x >= 128 ? 128 : x >= 64 ? 64 : x >= 32 ? 32 : x >= 16 ? 16 : x >= 8 ? 8 : x >= 4 ? 4 : x >= 2 ? 2 : 1; }
+template <typename T>
+constexpr int col_wlo(int N) { return 64 / col_tpc(N) > 1 ? 64 / col_tpc(N) : 1; }
+template <typename T>
+constexpr int col_whi(int N) {
+  const int byblock = 1024 / col_tpc(N);
+  const int bylds = pow2_floor((150 * 1024) / (2 * N * (int)sizeof(Cx<T>)));
+  return byblock < bylds ? byblock : bylds;
+}
+template <typename T>
+constexpr int clampw(int N, int w) { return w < col_wlo<T>(N) ? col_wlo<T>(N) : (w > col_whi<T>(N) ? col_whi<T>(N) : w); }
+template <typename T>
+constexpr int col_w(int N, int i) {
+  return clampw<T>(N, i == 0 ? 64 / (int)sizeof(Cx<T>) : (i == 1 ? 128 / (int)sizeof(Cx<T>) : 256 / (int)sizeof(Cx<T>)));
+}
+
+template <typename T, int N, int WW>
 struct ColCfg {
   static constexpr int L = N;
-  static constexpr int E = (EPT < L) ? EPT : L;
+  static constexpr int E = elems_per_thread(L);
   static constexpr int TPC = L / E;                     // threads per column
-  static constexpr int WMIN = sizeof(T) == 4 ? 16 : 8;  // 128-byte rows
-  static constexpr int W = (256 / TPC > WMIN) ? 256 / TPC : WMIN;
+  static constexpr int W = WW;
   static constexpr int BLOCK = W * TPC;
+  static_assert(BLOCK >= 64 && BLOCK <= 1024, "block size");
   static constexpr int R0F = plan_first(L, false), RLF = plan_last(L, false);
   static constexpr int R0I = plan_first(L, true), RLI = plan_last(L, true);
   static_assert(RLF == R0I && RLI == R0F, "reversed plans");
 };
-// elements per thread of the fused x and y passes
-template <int N>
-constexpr int multi_ept() { return elems_per_thread(N); }
 
-template <typename T, int N, int D>
-__global__ __launch_bounds__((ColCfg<T, N>::BLOCK)) void k_colfft(Cx<T>* __restrict__ data, int ncols, int bpp,
+template <typename T, int N, int WW, int D>
+__global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_colfft(Cx<T>* __restrict__ data, int ncols, int bpp,
                                                                   long plane_stride, long rowstride,
                                                                   const Cx<T>* __restrict__ tw) {
-  using C = ColCfg<T, N>;
+  using C = ColCfg<T, N, WW>;
   __shared__ Cx<T> lds[C::L * C::W];
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
@@ -295,16 +313,17 @@ __global__ __launch_bounds__((ColCfg<T, N>::BLOCK)) void k_colfft(Cx<T>* __restr
 // Fused y pass of the inverse chain: output o is the inverse y-FFT of input
 // field src[o] multiplied by m_y^pw[o] (outputs grouped by source, so each
 // input column tile is read once).
-template <typename T, int N>
-__global__ __launch_bounds__((ColCfg<T, N, multi_ept<N>()>::BLOCK)) void k_ycombo(const Cx<T>* __restrict__ in, long fsi,
+template <typename T, int N, int WW>
+__global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T>* __restrict__ in, long fsi,
                                                                   Cx<T>* __restrict__ out, long fso, YOp op,
                                                                   const Cx<T>* __restrict__ tw) {
-  using C = ColCfg<T, N, multi_ept<N>()>;
+  using C = ColCfg<T, N, WW>;
   constexpr int M = N / 2;
   constexpr int BPP = (M + C::W - 1) / C::W;
-  __shared__ Cx<T> lds[C::L * C::W];
+  __shared__ Cx<T> lds[2 * C::L * C::W];  // two exchange buffers
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
+  int phase = 0;
   const int c = threadIdx.x % C::W, t = threadIdx.x / C::W;
   const long plane = blockIdx.x / BPP;                    // x index
   const int col = (blockIdx.x % BPP) * C::W + c;          // z index
@@ -326,11 +345,82 @@ __global__ __launch_bounds__((ColCfg<T, N, multi_ept<N>()>::BLOCK)) void k_ycomb
       const int iy = slot_elem<C::L, C::E, C::R0I>(t, sl);
       y[sl] = scale(v[sl], mpow<T>(iy < N / 2 ? iy : iy - N, pw));
     }
-    fft<T, C::L, +1, C::W, C::E>(y, t, stw, 1, lds + c);
+    fft<T, C::L, +1, C::W, SY_PING>(y, t, stw, 1, lds + c, C::L * C::W, &phase);
     if (act) {
       Cx<T>* d = out + o * fso + off;
 #pragma unroll
       for (int sl = 0; sl < C::E; ++sl) d[slot_elem<C::L, C::E, C::RLI>(t, sl) * M] = y[sl];
+    }
+  }
+}
+
+// Displacement x pass (the hot path's two x passes).  One input column X
+// (z and y already forward-transformed), forward x-FFT, then one gather per
+// mode of the FP64 radial table(s), rounded once to T, then the outputs
+// with their k_x powers (integer mode numbers, exact in T):
+//   MODE 0: tab = interleaved (PHI, PSI1) per |m|^2;
+//           out 0..2: U_p = F_x^-1[-m_x^p PHI X], out 3..4: V_p = F_x^-1[i m_x^p PSI1 X]
+//   MODE 1: tab = PSI2;  out 0..1: Q_p = F_x^-1[-i m_x^p PSI2 X]
+// DC and Nyquist planes are zero in every output.
+template <typename T, int N, int WW, int MODE>
+__global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>* __restrict__ in,
+                                                                 Cx<T>* __restrict__ out, long fso,
+                                                                 const double* __restrict__ tab,
+                                                                 const Cx<T>* __restrict__ tw) {
+  using C = ColCfg<T, N, WW>;
+  constexpr int M = N / 2;
+  constexpr long NCOL = (long)N * M;
+  __shared__ Cx<T> lds[2 * C::L * C::W];  // two exchange buffers
+  __shared__ Cx<T> stw[N];
+  stage_twiddles<T, N>(stw, tw);
+  int phase = 0;
+  const int c = threadIdx.x % C::W, t = threadIdx.x / C::W;
+  const long col = (long)blockIdx.x * C::W + c;
+  const bool act = col < NCOL;
+  const long cs = act ? col : 0;
+  const int iy = (int)(cs / M), iz = (int)(cs % M);
+  const int my = iy < N / 2 ? iy : iy - N;
+  const bool keep_y = iy != N / 2;
+  const int n2yz = my * my + iz * iz;
+  Cx<T> va[C::E], vb[C::E], y[C::E];
+#pragma unroll
+  for (int sl = 0; sl < C::E; ++sl) va[sl] = act ? in[cs + slot_elem<C::L, C::E, C::R0F>(t, sl) * NCOL] : zero<T>();
+  fft<T, C::L, -1, C::W, SY_PING>(va, t, stw, 1, lds + c, C::L * C::W, &phase);
+#pragma unroll
+  for (int sl = 0; sl < C::E; ++sl) {
+    const int ix = slot_elem<C::L, C::E, C::RLF>(t, sl);
+    const int mx = ix < N / 2 ? ix : ix - N;
+    const int n2 = mx * mx + n2yz;
+    const bool keep = keep_y && ix != N / 2 && n2 != 0;
+    if (MODE == 0) {
+      double2 r = keep ? reinterpret_cast<const double2*>(tab)[n2] : make_double2(0.0, 0.0);
+      vb[sl] = scale(va[sl], T(r.y));
+      va[sl] = scale(va[sl], T(r.x));
+    } else {
+      va[sl] = scale(va[sl], keep ? T(tab[n2]) : T(0));
+    }
+  }
+  constexpr int NOUT = MODE == 0 ? 5 : 2;
+#pragma unroll 1
+  for (int o = 0; o < NOUT; ++o) {
+    // MODE 0: o < 3 -> -m_x^o * va ; o = 3, 4 -> i m_x^(o-3) * vb.  MODE 1: -i m_x^o * va
+    const bool second = MODE == 0 && o >= 3;
+    const int p = second ? o - 3 : o;
+#pragma unroll
+    for (int sl = 0; sl < C::E; ++sl) {
+      const int ix = slot_elem<C::L, C::E, C::RLF>(t, sl);
+      const T f = mpow<T>(ix < N / 2 ? ix : ix - N, p);
+      const Cx<T> a = second ? vb[sl] : va[sl];
+      if (MODE == 0)
+        y[sl] = second ? mk(-a.y * f, a.x * f) : mk(-a.x * f, -a.y * f);
+      else
+        y[sl] = mk(a.y * f, -a.x * f);
+    }
+    fft<T, C::L, +1, C::W, SY_PING>(y, t, stw, 1, lds + c, C::L * C::W, &phase);
+    if (act) {
+      Cx<T>* dst = out + o * fso + cs;
+#pragma unroll
+      for (int sl = 0; sl < C::E; ++sl) dst[slot_elem<C::L, C::E, C::RLI>(t, sl) * NCOL] = y[sl];
     }
   }
 }
@@ -350,11 +440,11 @@ __device__ __forceinline__ Cx<T> xop_mul(const XOp& op, int c, int mx, int my, i
   return kd == MUL_REAL ? mk(T(val), T(0)) : (kd == MUL_PI ? mk(T(0), T(val)) : mk(T(0), T(-val)));
 }
 
-template <typename T, int N>
-__global__ __launch_bounds__((ColCfg<T, N, multi_ept<N>()>::BLOCK)) void k_xpass(const Cx<T>* __restrict__ in, long fsi,
+template <typename T, int N, int WW>
+__global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xpass(const Cx<T>* __restrict__ in, long fsi,
                                                                  Cx<T>* __restrict__ out, long fso, XOp op,
                                                                  const Cx<T>* __restrict__ tw) {
-  using C = ColCfg<T, N, multi_ept<N>()>;
+  using C = ColCfg<T, N, WW>;
   constexpr int M = N / 2;
   constexpr long NCOL = (long)N * M;
   __shared__ Cx<T> lds[C::L * C::W];
@@ -372,7 +462,7 @@ __global__ __launch_bounds__((ColCfg<T, N, multi_ept<N>()>::BLOCK)) void k_xpass
   if (op.nin == 1) {
 #pragma unroll
     for (int sl = 0; sl < C::E; ++sl) v[sl] = act ? in[cs + slot_elem<C::L, C::E, C::R0F>(t, sl) * NCOL] : zero<T>();
-    fft<T, C::L, -1, C::W, C::E>(v, t, stw, 1, lds + c);
+    fft<T, C::L, -1, C::W>(v, t, stw, 1, lds + c);
 #pragma unroll 1
     for (int o = 0; o < op.nout; ++o) {
 #pragma unroll
@@ -384,7 +474,7 @@ __global__ __launch_bounds__((ColCfg<T, N, multi_ept<N>()>::BLOCK)) void k_xpass
       }
       Cx<T>* dst = out + o * fso + cs;
       if (op.inverse) {
-        fft<T, C::L, +1, C::W, C::E>(y, t, stw, 1, lds + c);
+        fft<T, C::L, +1, C::W>(y, t, stw, 1, lds + c);
         if (act) {
 #pragma unroll
           for (int sl = 0; sl < C::E; ++sl) dst[slot_elem<C::L, C::E, C::RLI>(t, sl) * NCOL] = y[sl];
@@ -402,7 +492,7 @@ __global__ __launch_bounds__((ColCfg<T, N, multi_ept<N>()>::BLOCK)) void k_xpass
       const Cx<T>* src = in + f * fsi + cs;
 #pragma unroll
       for (int sl = 0; sl < C::E; ++sl) v[sl] = act ? src[slot_elem<C::L, C::E, C::R0F>(t, sl) * NCOL] : zero<T>();
-      fft<T, C::L, -1, C::W, C::E>(v, t, stw, 1, lds + c);
+      fft<T, C::L, -1, C::W>(v, t, stw, 1, lds + c);
 #pragma unroll
       for (int sl = 0; sl < C::E; ++sl) {
         const int ix = slot_elem<C::L, C::E, C::RLF>(t, sl);
@@ -413,7 +503,7 @@ __global__ __launch_bounds__((ColCfg<T, N, multi_ept<N>()>::BLOCK)) void k_xpass
     }
     Cx<T>* dst = out + cs;
     if (op.inverse) {
-      fft<T, C::L, +1, C::W, C::E>(y, t, stw, 1, lds + c);
+      fft<T, C::L, +1, C::W>(y, t, stw, 1, lds + c);
       if (act) {
 #pragma unroll
         for (int sl = 0; sl < C::E; ++sl) dst[slot_elem<C::L, C::E, C::RLI>(t, sl) * NCOL] = y[sl];
@@ -439,6 +529,27 @@ __global__ __launch_bounds__((ColCfg<T, N, multi_ept<N>()>::BLOCK)) void k_xpass
     case 512: CALL(512); break;    \
     default: return hipErrorInvalidValue; \
   }
+
+int col_width(int prec, int n, int i) {
+#define W_(NN) return prec == PREC_F32 ? col_w<float>(NN, i) : col_w<double>(NN, i)
+  switch (n) {
+    case 8: W_(8);
+    case 16: W_(16);
+    case 32: W_(32);
+    case 64: W_(64);
+    case 128: W_(128);
+    case 256: W_(256);
+    case 512: W_(512);
+  }
+#undef W_
+  return 0;
+}
+// 128-byte row runs (measured on MI355X: narrower tiles lose more to the
+// access granularity than they gain from extra blocks per CU)
+int default_width(int prec, int n, int kind) {
+  (void)kind;
+  return col_width(prec, n, 1);
+}
 
 static inline size_t esize(int prec) { return prec == PREC_F32 ? 4 : 8; }
 static inline bool pow2n(int n) { return n >= 8 && n <= 512 && (n & (n - 1)) == 0; }
@@ -543,46 +654,64 @@ hipError_t launch_zprodrule(int prec, int n, const void* phi, size_t phi_cap, lo
   return hipErrorInvalidValue;
 }
 
-template <typename T, int N>
-static hipError_t colfft_t(int dir, void* data, long nplanes, long plane_stride, int ncols, long rowstride,
+template <typename T, int N, int WW>
+static hipError_t colfft_w(int dir, void* data, long nplanes, long plane_stride, int ncols, long rowstride,
                            const void* tw, hipStream_t s) {
-  using C = ColCfg<T, N>;
+  using C = ColCfg<T, N, WW>;
   const int bpp = (ncols + C::W - 1) / C::W;
   const long blocks = nplanes * bpp;
   if (blocks > 0x7fffffffL) return hipErrorInvalidValue;
   if (dir < 0)
-    hipLaunchKernelGGL((k_colfft<T, N, -1>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (Cx<T>*)data, ncols, bpp,
-                       plane_stride, rowstride, (const Cx<T>*)tw);
+    hipLaunchKernelGGL((k_colfft<T, N, WW, -1>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (Cx<T>*)data, ncols,
+                       bpp, plane_stride, rowstride, (const Cx<T>*)tw);
   else
-    hipLaunchKernelGGL((k_colfft<T, N, +1>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (Cx<T>*)data, ncols, bpp,
-                       plane_stride, rowstride, (const Cx<T>*)tw);
+    hipLaunchKernelGGL((k_colfft<T, N, WW, +1>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (Cx<T>*)data, ncols,
+                       bpp, plane_stride, rowstride, (const Cx<T>*)tw);
   return hipGetLastError();
 }
+template <typename T, int N>
+static hipError_t colfft_t(int w, int dir, void* data, long nplanes, long plane_stride, int ncols, long rowstride,
+                           const void* tw, hipStream_t s) {
+  if (w == col_w<T>(N, 0)) return colfft_w<T, N, col_w<T>(N, 0)>(dir, data, nplanes, plane_stride, ncols, rowstride, tw, s);
+  if (w == col_w<T>(N, 1)) return colfft_w<T, N, col_w<T>(N, 1)>(dir, data, nplanes, plane_stride, ncols, rowstride, tw, s);
+  if (w == col_w<T>(N, 2)) return colfft_w<T, N, col_w<T>(N, 2)>(dir, data, nplanes, plane_stride, ncols, rowstride, tw, s);
+  return hipErrorInvalidValue;
+}
 hipError_t launch_colfft(int prec, int n, int dir, void* data, size_t cap, long nplanes, long plane_stride,
-                         int ncols, long rowstride, const void* tw, hipStream_t s) {
+                         int ncols, long rowstride, const void* tw, hipStream_t s, int w) {
+  if (w == 0) w = default_width(prec, n, KIND_COL);
   if (nplanes <= 0 || ncols <= 0) return hipSuccess;
   if (!pow2n(n) || !data || !tw || plane_stride < 0 || rowstride < ncols) return hipErrorInvalidValue;
   // one past the last element touched
   const size_t end = (size_t)(nplanes - 1) * plane_stride + (size_t)(n - 1) * rowstride + (size_t)ncols;
   if (end * 2 * esize(prec) > cap) return hipErrorInvalidValue;
-#define CALL(NN) return prec == PREC_F32 ? colfft_t<float, NN>(dir, data, nplanes, plane_stride, ncols, rowstride, tw, s) : colfft_t<double, NN>(dir, data, nplanes, plane_stride, ncols, rowstride, tw, s)
+#define CALL(NN) return prec == PREC_F32 ? colfft_t<float, NN>(w, dir, data, nplanes, plane_stride, ncols, rowstride, tw, s) : colfft_t<double, NN>(w, dir, data, nplanes, plane_stride, ncols, rowstride, tw, s)
   LPT2_SWITCH_N(n, CALL)
 #undef CALL
   return hipErrorInvalidValue;
 }
 
-template <typename T, int N>
-static hipError_t ycombo_t(const void* in, long fsi, void* out, long fso, const YOp& op, const void* tw,
+template <typename T, int N, int WW>
+static hipError_t ycombo_w(const void* in, long fsi, void* out, long fso, const YOp& op, const void* tw,
                            hipStream_t s) {
-  using C = ColCfg<T, N, multi_ept<N>()>;
+  using C = ColCfg<T, N, WW>;
   constexpr int M = N / 2;
   const long blocks = (long)N * ((M + C::W - 1) / C::W);
-  hipLaunchKernelGGL((k_ycombo<T, N>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in, fsi,
+  hipLaunchKernelGGL((k_ycombo<T, N, WW>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in, fsi,
                      (Cx<T>*)out, fso, op, (const Cx<T>*)tw);
   return hipGetLastError();
 }
+template <typename T, int N>
+static hipError_t ycombo_t(int w, const void* in, long fsi, void* out, long fso, const YOp& op, const void* tw,
+                           hipStream_t s) {
+  if (w == col_w<T>(N, 0)) return ycombo_w<T, N, col_w<T>(N, 0)>(in, fsi, out, fso, op, tw, s);
+  if (w == col_w<T>(N, 1)) return ycombo_w<T, N, col_w<T>(N, 1)>(in, fsi, out, fso, op, tw, s);
+  if (w == col_w<T>(N, 2)) return ycombo_w<T, N, col_w<T>(N, 2)>(in, fsi, out, fso, op, tw, s);
+  return hipErrorInvalidValue;
+}
 hipError_t launch_ycombo(int prec, int n, const void* in, size_t in_cap, long in_fstride, void* out, size_t out_cap,
-                         long out_fstride, const YOp& op, const void* tw, hipStream_t s) {
+                         long out_fstride, const YOp& op, const void* tw, hipStream_t s, int w) {
+  if (w == 0) w = default_width(prec, n, KIND_MULTI);
   if (op.nin < 1 || op.nout < 1 || op.nin > YOP_MAX || op.nout > YOP_MAX) return hipErrorInvalidValue;
   if (!pow2n(n) || !in || !out || !tw || in_fstride < 0 || out_fstride < 0) return hipErrorInvalidValue;
   for (int o = 0; o < op.nout; ++o)
@@ -590,7 +719,45 @@ hipError_t launch_ycombo(int prec, int n, const void* in, size_t in_cap, long in
   const size_t cb = 2 * esize(prec), field = (size_t)n * n * (n / 2);
   if (((size_t)(op.nin - 1) * in_fstride + field) * cb > in_cap) return hipErrorInvalidValue;
   if (((size_t)(op.nout - 1) * out_fstride + field) * cb > out_cap) return hipErrorInvalidValue;
-#define CALL(NN) return prec == PREC_F32 ? ycombo_t<float, NN>(in, in_fstride, out, out_fstride, op, tw, s) : ycombo_t<double, NN>(in, in_fstride, out, out_fstride, op, tw, s)
+#define CALL(NN) return prec == PREC_F32 ? ycombo_t<float, NN>(w, in, in_fstride, out, out_fstride, op, tw, s) : ycombo_t<double, NN>(w, in, in_fstride, out, out_fstride, op, tw, s)
+  LPT2_SWITCH_N(n, CALL)
+#undef CALL
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int N, int WW>
+static hipError_t xdisp_w(int mode, const void* in, void* out, long fso, const double* tab, const void* tw,
+                          hipStream_t s) {
+  using C = ColCfg<T, N, WW>;
+  const long ncol = (long)N * (N / 2);
+  const long blocks = (ncol + C::W - 1) / C::W;
+  if (mode == 0)
+    hipLaunchKernelGGL((k_xdisp<T, N, WW, 0>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in,
+                       (Cx<T>*)out, fso, tab, (const Cx<T>*)tw);
+  else
+    hipLaunchKernelGGL((k_xdisp<T, N, WW, 1>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in,
+                       (Cx<T>*)out, fso, tab, (const Cx<T>*)tw);
+  return hipGetLastError();
+}
+template <typename T, int N>
+static hipError_t xdisp_t(int w, int mode, const void* in, void* out, long fso, const double* tab, const void* tw,
+                          hipStream_t s) {
+  if (w == col_w<T>(N, 0)) return xdisp_w<T, N, col_w<T>(N, 0)>(mode, in, out, fso, tab, tw, s);
+  if (w == col_w<T>(N, 1)) return xdisp_w<T, N, col_w<T>(N, 1)>(mode, in, out, fso, tab, tw, s);
+  if (w == col_w<T>(N, 2)) return xdisp_w<T, N, col_w<T>(N, 2)>(mode, in, out, fso, tab, tw, s);
+  return hipErrorInvalidValue;
+}
+hipError_t launch_xdisp(int prec, int n, int mode, const void* in, size_t in_cap, void* out, size_t out_cap,
+                        long out_fstride, const double* tab, size_t tab_cap, const void* tw, hipStream_t s, int w) {
+  if (w == 0) w = default_width(prec, n, KIND_MULTI);
+  if (!pow2n(n) || !in || !out || !tab || !tw || out_fstride < 0 || (mode != 0 && mode != 1))
+    return hipErrorInvalidValue;
+  const size_t cb = 2 * esize(prec), field = (size_t)n * n * (n / 2);
+  const int nout = mode == 0 ? 5 : 2;
+  if (field * cb > in_cap || ((size_t)(nout - 1) * out_fstride + field) * cb > out_cap) return hipErrorInvalidValue;
+  const size_t n2cnt = 3 * (size_t)(n / 2) * (n / 2) + 1;
+  if (n2cnt * (mode == 0 ? 16 : 8) > tab_cap) return hipErrorInvalidValue;
+#define CALL(NN) return prec == PREC_F32 ? xdisp_t<float, NN>(w, mode, in, out, out_fstride, tab, tw, s) : xdisp_t<double, NN>(w, mode, in, out, out_fstride, tab, tw, s)
   LPT2_SWITCH_N(n, CALL)
 #undef CALL
   return hipErrorInvalidValue;
@@ -599,10 +766,11 @@ hipError_t launch_ycombo(int prec, int n, const void* in, size_t in_cap, long in
 template <typename T, int N>
 static hipError_t xpass_t(const void* in, long fsi, void* out, long fso, const XOp& op, const void* tw,
                           hipStream_t s) {
-  using C = ColCfg<T, N, multi_ept<N>()>;
+  constexpr int WW = col_w<T>(N, 1);
+  using C = ColCfg<T, N, WW>;
   const long ncol = (long)N * (N / 2);
   const long blocks = (ncol + C::W - 1) / C::W;
-  hipLaunchKernelGGL((k_xpass<T, N>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in, fsi,
+  hipLaunchKernelGGL((k_xpass<T, N, WW>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in, fsi,
                      (Cx<T>*)out, fso, op, (const Cx<T>*)tw);
   return hipGetLastError();
 }

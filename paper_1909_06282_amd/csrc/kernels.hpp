@@ -56,11 +56,19 @@ hipError_t launch_zc2r(int prec, int n, const void* in, size_t in_cap, void* out
                        const ZPow& zp, const void* tw, hipStream_t s);
 // strided complex column FFT in place: nplanes planes of ncols columns,
 // element (row, col) of plane p at data + p*plane_stride + row*rowstride + col
+// w: columns per block, one of col_width(n, 0..2); 0 picks default_width
 hipError_t launch_colfft(int prec, int n, int dir, void* data, size_t cap, long nplanes, long plane_stride,
-                         int ncols, long rowstride, const void* tw, hipStream_t s);
+                         int ncols, long rowstride, const void* tw, hipStream_t s, int w = 0);
+enum { KIND_COL = 0, KIND_MULTI = 1 };
+int col_width(int prec, int n, int i);       // the three tile widths offered for (precision, grid size)
+int default_width(int prec, int n, int kind);
 // fused inverse y pass over the n planes x n/2 columns of each field
 hipError_t launch_ycombo(int prec, int n, const void* in, size_t in_cap, long in_fstride, void* out, size_t out_cap,
-                         long out_fstride, const YOp& op, const void* tw, hipStream_t s);
+                         long out_fstride, const YOp& op, const void* tw, hipStream_t s, int w = 0);
+// displacement x pass: mode 0 (tab = interleaved PHI, PSI1 per |m|^2; five
+// outputs U0,U1,U2,V0,V1) or mode 1 (tab = PSI2; outputs Q0,Q1); tab_cap in bytes
+hipError_t launch_xdisp(int prec, int n, int mode, const void* in, size_t in_cap, void* out, size_t out_cap,
+                        long out_fstride, const double* tab, size_t tab_cap, const void* tw, hipStream_t s, int w = 0);
 // fused x pass over the n*(n/2) columns of each field
 hipError_t launch_xpass(int prec, int n, const void* in, size_t in_cap, long in_fstride, void* out, size_t out_cap,
                         long out_fstride, const XOp& op, long n2cnt, const void* tw, hipStream_t s);
@@ -90,6 +98,8 @@ enum {
   TAB_PSI1 = 0, TAB_PHI, TAB_PSI2, TAB_A, TAB_R1, TAB_R2, TAB_R3, TAB_R4, TAB_R5, TAB_R6,
   TAB_C2, TAB_C4, TAB_C5, TAB_COUNT
 };
+// after the TAB_COUNT rows: the interleaved (PHI, PSI1) pair table, 2 rows
+constexpr int TAB_ROWS = TAB_COUNT + 2;
 struct RadialSetup {
   Cosmo c;
   int n;
@@ -97,7 +107,8 @@ struct RadialSetup {
   int nk;
   double lkmin, lkmax;
 };
-// per-|m|^2 FP64 tables, TAB_COUNT arrays of n2max + 1 = 3 (n/2)^2 + 1 entries
+// per-|m|^2 FP64 tables: TAB_COUNT arrays of n2max + 1 = 3 (n/2)^2 + 1 entries,
+// then the interleaved pair table (PHI, PSI1) of 2 (n2max + 1) entries
 hipError_t launch_radial(const RadialSetup& r, const double* d1n, const double* d2n, double* tabs, long n2cnt,
                          hipStream_t s);
 

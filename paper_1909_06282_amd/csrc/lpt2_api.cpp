@@ -6,11 +6,12 @@
 #include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
 
-#include "../../include/lpt2.h"
+#include "lpt2.h"
 #include "kernels.hpp"
 
 using namespace lpt2;
@@ -34,6 +35,7 @@ struct Grid {
   Cosmo c;
   double amp = 0.0, lkmin = 0.0, lkmax = 0.0;
   void* tw = nullptr;
+  int tiles[3] = {0, 0, 0};  // columns per block: y/x single passes, fused y pass, fused x pass (0 = default)
   std::vector<Tables> tables;
   std::vector<Tables> gr_tables;  // GR growth at a (for S_GR and the triangle ratios)
 };
@@ -239,7 +241,7 @@ lpt2_status build_tables(lpt2_plan_t p, Grid& g, double a, bool gr, hipStream_t 
     return st;
   }
   if (!gr) {
-    e = hipMalloc((void**)&t.radial, sizeof(double) * TAB_COUNT * g.n2cnt);
+    e = hipMalloc((void**)&t.radial, sizeof(double) * TAB_ROWS * g.n2cnt);
     if (e != hipSuccess) {
       (void)hipFree(t.d1n);
       return fail(p, LPT2_ENOMEM, "radial table allocation failed");
@@ -339,7 +341,8 @@ lpt2_status fwd_zy(Ctx& c, const char* nz, const char* ny, const void* in, size_
   const double fb = (double)c.field();
   RUN(nz, 2.0 * fb * nf, launch_zr2c(p->prec, g.n, in, in_cap, out, c.cap(out), (long)nf * g.n * g.n, g.tw, s));
   RUN(ny, 2.0 * fb * nf,
-      launch_colfft(p->prec, g.n, -1, out, c.cap(out), (long)nf * g.n, g.n * g.m, (int)g.m, g.m, g.tw, s));
+      launch_colfft(p->prec, g.n, -1, out, c.cap(out), (long)nf * g.n, g.n * g.m, (int)g.m, g.m, g.tw, s,
+                    g.tiles[0]));
   return LPT2_OK;
 }
 lpt2_status inv_y(Ctx& c, const char* ny, void* data, int nf) {
@@ -348,7 +351,8 @@ lpt2_status inv_y(Ctx& c, const char* ny, void* data, int nf) {
   Grid& g = c.g;
   const double fb = (double)c.field();
   RUN(ny, 2.0 * fb * nf,
-      launch_colfft(p->prec, g.n, +1, data, c.cap(data), (long)nf * g.n, g.n * g.m, (int)g.m, g.m, g.tw, s));
+      launch_colfft(p->prec, g.n, +1, data, c.cap(data), (long)nf * g.n, g.n * g.m, (int)g.m, g.m, g.tw, s,
+                    g.tiles[0]));
   return LPT2_OK;
 }
 lpt2_status fwd_y(Ctx& c, const char* ny, void* data, int nf) {
@@ -357,7 +361,8 @@ lpt2_status fwd_y(Ctx& c, const char* ny, void* data, int nf) {
   Grid& g = c.g;
   const double fb = (double)c.field();
   RUN(ny, 2.0 * fb * nf,
-      launch_colfft(p->prec, g.n, -1, data, c.cap(data), (long)nf * g.n, g.n * g.m, (int)g.m, g.m, g.tw, s));
+      launch_colfft(p->prec, g.n, -1, data, c.cap(data), (long)nf * g.n, g.n * g.m, (int)g.m, g.m, g.tw, s,
+                    g.tiles[0]));
   return LPT2_OK;
 }
 lpt2_status xp(Ctx& c, const char* name, const void* in, void* out, const XOp& op) {
@@ -368,6 +373,14 @@ lpt2_status xp(Ctx& c, const char* name, const void* in, void* out, const XOp& o
   const long fst = g.nnm;
   RUN(name, fb * (op.nin + op.nout),
       launch_xpass(p->prec, g.n, in, c.cap(in), fst, out, c.cap(out), fst, op, g.n2cnt, g.tw, s));
+  return LPT2_OK;
+}
+lpt2_status xdisp(Ctx& c, const char* name, int mode, const void* in, void* out, const double* tab, size_t tab_cap) {
+  lpt2_plan_t p = c.p;
+  hipStream_t s = c.s;
+  Grid& g = c.g;
+  RUN(name, (double)c.field() * (mode == 0 ? 6 : 3),
+      launch_xdisp(p->prec, g.n, mode, in, c.cap(in), out, c.cap(out), g.nnm, tab, tab_cap, g.tw, s, g.tiles[2]));
   return LPT2_OK;
 }
 lpt2_status z_c2r(Ctx& c, const char* name, const void* in, void* out, size_t out_cap, int nf,
@@ -399,7 +412,7 @@ lpt2_status ycombo(Ctx& c, const char* name, const void* in, void* out, const YO
   hipStream_t s = c.s;
   Grid& g = c.g;
   RUN(name, (double)c.field() * (op.nin + op.nout),
-      launch_ycombo(p->prec, g.n, in, c.cap(in), g.nnm, out, c.cap(out), g.nnm, op, g.tw, s));
+      launch_ycombo(p->prec, g.n, in, c.cap(in), g.nnm, out, c.cap(out), g.nnm, op, g.tw, s, g.tiles[1]));
   return LPT2_OK;
 }
 YOp yop(int nin, int nout, const int* src, const int* pw) {
@@ -429,14 +442,8 @@ YOp yop(int nin, int nout, const int* src, const int* pw) {
 lpt2_status displace_one(Ctx& c, const Tables* t, const void* noise, void* psi1, void* psi2) {
   Grid& g = c.g;
   CHK(fwd_zy(c, "z_r2c_noise", "y_fwd_noise", noise, c.field(), c.slot(0), 1));
-  XOp op = op_blank(1, 5, 1);
-  op_tables(op, g, t);
-  op_set(op, 0, MUL_REAL, -1, -1, TAB_PHI, -1.0);  // U0
-  op_set(op, 1, MUL_REAL, 0, -1, TAB_PHI, -1.0);   // U1
-  op_set(op, 2, MUL_REAL, 0, 0, TAB_PHI, -1.0);    // U2
-  op_set(op, 3, MUL_PI, -1, -1, TAB_PSI1, 1.0);    // V0
-  op_set(op, 4, MUL_PI, 0, -1, TAB_PSI1, 1.0);     // V1
-  CHK(xp(c, "x_fused_psi1_phi", c.slot(0), c.slot(1), op));
+  CHK(xdisp(c, "x_fused_psi1_phi", 0, c.slot(0), c.slot(1), t->radial + (size_t)TAB_COUNT * g.n2cnt,
+            sizeof(double) * 2 * g.n2cnt));
   // outputs: psi1 x,y,z then phi xx,yy,zz,xy,xz,yz (inputs U0,U1,U2,V0,V1 = 0..4)
   const int src9[9] = {4, 3, 3, 2, 0, 0, 1, 1, 0};
   const int pw9[9] = {0, 1, 0, 0, 2, 0, 1, 0, 1};
@@ -446,11 +453,8 @@ lpt2_status displace_one(Ctx& c, const Tables* t, const void* noise, void* psi1,
   const int rzs[6] = {0, 0, 2, 0, 1, 1};
   CHK(z_source(c, c.slot(9), c.slot(0), rzs));
   CHK(fwd_y(c, "y_fwd_source", c.slot(0), 1));
-  XOp o2 = op_blank(1, 2, 1);
-  op_tables(o2, g, t);
-  op_set(o2, 0, MUL_MI, -1, -1, TAB_PSI2, 1.0);  // Q0
-  op_set(o2, 1, MUL_MI, 0, -1, TAB_PSI2, 1.0);   // Q1
-  CHK(xp(c, "x_fused_psi2", c.slot(0), c.slot(1), o2));
+  CHK(xdisp(c, "x_fused_psi2", 1, c.slot(0), c.slot(1), t->radial + (size_t)TAB_PSI2 * g.n2cnt,
+            sizeof(double) * g.n2cnt));
   const int src3[3] = {1, 0, 0};
   const int pw3[3] = {0, 1, 0};
   CHK(ycombo(c, "y_inv_psi2", c.slot(1), c.slot(3), yop(2, 3, src3, pw3)));
@@ -683,6 +687,16 @@ lpt2_status lpt2_plan(const lpt2_config* cfgs, int n_cfgs, const int* counts, lp
     if (e != hipSuccess) {
       lpt2_destroy(p);
       return fail(nullptr, LPT2_EDEVICE, std::string("twiddle upload: ") + hipGetErrorString(e));
+    }
+    if (const char* ev = std::getenv("LPT2_TILES")) {  // "col,y,x" widths, for tuning experiments
+      int a = 0, b = 0, cc = 0;
+      if (std::sscanf(ev, "%d,%d,%d", &a, &b, &cc) == 3) {
+        Grid& gb = p->grids.back();
+        const int want[3] = {a, b, cc};
+        for (int k = 0; k < 3; ++k)
+          for (int j = 0; j < 3; ++j)
+            if (col_width(p->prec, gb.n, j) == want[k]) gb.tiles[k] = want[k];
+      }
     }
     for (int r = 0; r < p->grids.back().count; ++r) p->rgrid.push_back(i);
     const size_t fbytes = (size_t)g.n3 * p->es;
