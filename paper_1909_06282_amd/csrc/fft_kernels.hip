@@ -35,7 +35,7 @@ struct LineCfg {
   static constexpr int RLI = plan_last(L, true);        // inverse last radix (== R0F)
   static_assert(RLI == R0F, "inverse plan must end with the forward first radix");
   static_assert(TPL <= 64 && 64 % TPL == 0, "a line must lie inside one wavefront");
-  static constexpr int SPAN = lds_span<true>(L);       // LDS slots per line (padded)
+  static constexpr int SPAN = lds_span<true>(L);       // LDS slots per line (room for padding)
 };
 
 template <typename T, int N>
@@ -62,18 +62,18 @@ __device__ __forceinline__ void load_real_line(const T* src, Cx<T>* v, int t, bo
 // After a forward FFT of the packed line: split Z into the real line's modes
 // X_k = (Z_k + Z*_{L-k})/2 - i W^k (Z_k - Z*_{L-k})/2, W = exp(-2 pi i/n),
 // for k = 0..n/2-1 (the Nyquist mode is not kept), and store them.
-template <typename T, int N>
+template <typename T, int N, bool PAD = true>
 __device__ __forceinline__ void r2c_finish(Cx<T>* v, int t, Cx<T>* lb, const Cx<T>* stw, Cx<T>* dst, bool act) {
   using C = LineCfg<N>;
   wave_sync();
 #pragma unroll
-  for (int sl = 0; sl < C::E; ++sl) lb[lds_index<true>(slot_elem<C::L, C::E, C::RLF>(t, sl))] = v[sl];
+  for (int sl = 0; sl < C::E; ++sl) lb[lds_index<PAD>(slot_elem<C::L, C::E, C::RLF>(t, sl))] = v[sl];
   wave_sync();
 #pragma unroll
   for (int s = 0; s < C::E; ++s) {
     const int k = t + s * C::TPL;
-    const Cx<T> z = lb[lds_index<true>(k)];
-    const Cx<T> zc = conj(lb[lds_index<true>((C::L - k) & (C::L - 1))]);
+    const Cx<T> z = lb[lds_index<PAD>(k)];
+    const Cx<T> zc = conj(lb[lds_index<PAD>((C::L - k) & (C::L - 1))]);
     const Cx<T> a = scale(z + zc, T(0.5));
     const Cx<T> wb = stw[k] * scale(z - zc, T(0.5));
     if (act) dst[k] = mk(a.x + wb.y, a.y - wb.x);
@@ -85,7 +85,7 @@ __device__ __forceinline__ void r2c_finish(Cx<T>* v, int t, Cx<T>* lb, const Cx<
 // O_k = (X_k - X*_{L-k}) conj(W^k), with X_{n/2} = 0 and Im X_0 ignored, in
 // the inverse first-stage slots.  The unnormalised inverse FFT of Z then
 // gives n x_{2j} + i n x_{2j+1}.
-template <typename T, int N>
+template <typename T, int N, bool PAD = true>
 __device__ __forceinline__ void c2r_prepare(const Cx<T>* src, int r, Cx<T>* v, int t, Cx<T>* lb, const Cx<T>* stw,
                                             bool act) {
   using C = LineCfg<N>;
@@ -93,19 +93,19 @@ __device__ __forceinline__ void c2r_prepare(const Cx<T>* src, int r, Cx<T>* v, i
 #pragma unroll
   for (int s = 0; s < C::E; ++s) {
     const int k = t + s * C::TPL;
-    lb[lds_index<true>(k)] = act ? scale(src[k], mpow<T>(k, r)) : zero<T>();
+    lb[lds_index<PAD>(k)] = act ? scale(src[k], mpow<T>(k, r)) : zero<T>();
   }
   wave_sync();
 #pragma unroll
   for (int sl = 0; sl < C::E; ++sl) {
     const int e = slot_elem<C::L, C::E, C::R0I>(t, sl);
-    Cx<T> x = lb[lds_index<true>(e)];
+    Cx<T> x = lb[lds_index<PAD>(e)];
     Cx<T> xc;
     if (e == 0) {
       x.y = T(0);
       xc = zero<T>();
     } else {
-      xc = conj(lb[lds_index<true>(C::L - e)]);
+      xc = conj(lb[lds_index<PAD>(C::L - e)]);
     }
     const Cx<T> ek = x + xc;
     const Cx<T> ok = (x - xc) * conj(stw[e]);
@@ -126,8 +126,8 @@ __global__ __launch_bounds__(256) void k_zr2c(const T* in, Cx<T>* out, long nlin
   Cx<T>* lb = lds + g * C::SPAN;
   Cx<T> v[C::E];
   load_real_line<T, N>(in + lsafe * N, v, t, act);
-  fft<T, C::L, -1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
-  r2c_finish<T, N>(v, t, lb, stw, out + lsafe * C::L, act);
+  fft<T, C::L, -1, 1, SY_WAVE, false>(v, t, stw, 2, lb);
+  r2c_finish<T, N, false>(v, t, lb, stw, out + lsafe * C::L, act);
 }
 
 // lines of field f = line / lines_per_field are multiplied by m_z^rpow[f]
@@ -146,8 +146,8 @@ __global__ __launch_bounds__(256) void k_zc2r(const Cx<T>* in, T* out, long nlin
   const int r = f < ZPOW_MAX ? zp.r[f] : 0;
   Cx<T>* lb = lds + g * C::SPAN;
   Cx<T> v[C::E];
-  c2r_prepare<T, N>(in + lsafe * C::L, r, v, t, lb, stw, act);
-  fft<T, C::L, +1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
+  c2r_prepare<T, N, false>(in + lsafe * C::L, r, v, t, lb, stw, act);
+  fft<T, C::L, +1, 1, SY_WAVE, false>(v, t, stw, 2, lb);
   Cx<T>* d2 = reinterpret_cast<Cx<T>*>(out + lsafe * N);
   if (act) {
 #pragma unroll
@@ -155,9 +155,38 @@ __global__ __launch_bounds__(256) void k_zc2r(const Cx<T>* in, T* out, long nlin
   }
 }
 
+// c2r_prepare for a line already held in registers (raw[s] = X_{t + s*TPL}).
+template <typename T, int N, bool PAD = true>
+__device__ __forceinline__ void c2r_prepare_regs(const Cx<T>* raw, int r, Cx<T>* v, int t, Cx<T>* lb,
+                                                 const Cx<T>* stw) {
+  using C = LineCfg<N>;
+  wave_sync();
+#pragma unroll
+  for (int s = 0; s < C::E; ++s) {
+    const int k = t + s * C::TPL;
+    lb[lds_index<PAD>(k)] = scale(raw[s], mpow<T>(k, r));
+  }
+  wave_sync();
+#pragma unroll
+  for (int sl = 0; sl < C::E; ++sl) {
+    const int e = slot_elem<C::L, C::E, C::R0I>(t, sl);
+    Cx<T> x = lb[lds_index<PAD>(e)];
+    Cx<T> xc;
+    if (e == 0) {
+      x.y = T(0);
+      xc = zero<T>();
+    } else {
+      xc = conj(lb[lds_index<PAD>(C::L - e)]);
+    }
+    const Cx<T> ek = x + xc;
+    const Cx<T> ok = (x - xc) * conj(stw[e]);
+    v[sl] = mk(ek.x - ok.y, ek.y + ok.x);
+  }
+}
 // S = phi_xx phi_yy + (phi_xx + phi_yy) phi_zz - phi_xy^2 - phi_xz^2 - phi_yz^2
 // per real value (field f of the six multiplied by m_z^rpow[f] first), then
-// the forward R2C of the S line.
+// the forward R2C of the S line.  The line of field f+1 is loaded while
+// field f is transformed, so the load latency hides behind the transform.
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_zsource(const Cx<T>* __restrict__ phi, long fstride, ZPow zp,
                                                  Cx<T>* __restrict__ sk, long nlines, const Cx<T>* __restrict__ tw) {
@@ -170,29 +199,36 @@ __global__ __launch_bounds__(256) void k_zsource(const Cx<T>* __restrict__ phi, 
   const bool act = line < nlines;
   const long lsafe = act ? line : 0;
   Cx<T>* lb = lds + g * C::SPAN;
-  Cx<T> a[C::E], s[C::E], v[C::E];
+  Cx<T> a[C::E], s[C::E], v[C::E], raw[C::E], nxt[C::E];
   const Cx<T>* src = phi + lsafe * C::L;
-  c2r_prepare<T, N>(src, zp.r[0], v, t, lb, stw, act);
-  fft<T, C::L, +1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
 #pragma unroll
-  for (int i = 0; i < C::E; ++i) a[i] = v[i];
-  c2r_prepare<T, N>(src + fstride, zp.r[1], v, t, lb, stw, act);
-  fft<T, C::L, +1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
+  for (int q = 0; q < C::E; ++q) raw[q] = act ? src[t + q * C::TPL] : zero<T>();
 #pragma unroll
-  for (int i = 0; i < C::E; ++i) {
-    s[i] = mk(a[i].x * v[i].x, a[i].y * v[i].y);
-    a[i] = a[i] + v[i];
-  }
-  c2r_prepare<T, N>(src + 2 * fstride, zp.r[2], v, t, lb, stw, act);
-  fft<T, C::L, +1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
+  for (int f = 0; f < 6; ++f) {
+    if (f < 5) {
 #pragma unroll
-  for (int i = 0; i < C::E; ++i) s[i] = mk(s[i].x + a[i].x * v[i].x, s[i].y + a[i].y * v[i].y);
-#pragma unroll 1
-  for (int f = 3; f < 6; ++f) {
-    c2r_prepare<T, N>(src + f * fstride, zp.r[f], v, t, lb, stw, act);
+      for (int q = 0; q < C::E; ++q) nxt[q] = act ? src[(f + 1) * fstride + t + q * C::TPL] : zero<T>();
+    }
+    c2r_prepare_regs<T, N>(raw, zp.r[f], v, t, lb, stw);
     fft<T, C::L, +1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
+    if (f == 0) {
 #pragma unroll
-    for (int i = 0; i < C::E; ++i) s[i] = mk(s[i].x - v[i].x * v[i].x, s[i].y - v[i].y * v[i].y);
+      for (int i = 0; i < C::E; ++i) a[i] = v[i];
+    } else if (f == 1) {
+#pragma unroll
+      for (int i = 0; i < C::E; ++i) {
+        s[i] = mk(a[i].x * v[i].x, a[i].y * v[i].y);
+        a[i] = a[i] + v[i];
+      }
+    } else if (f == 2) {
+#pragma unroll
+      for (int i = 0; i < C::E; ++i) s[i] = mk(s[i].x + a[i].x * v[i].x, s[i].y + a[i].y * v[i].y);
+    } else {
+#pragma unroll
+      for (int i = 0; i < C::E; ++i) s[i] = mk(s[i].x - v[i].x * v[i].x, s[i].y - v[i].y * v[i].y);
+    }
+#pragma unroll
+    for (int q = 0; q < C::E; ++q) raw[q] = nxt[q];
   }
   fft<T, C::L, -1, 1, SY_WAVE, true>(s, t, stw, 2, lb);
   r2c_finish<T, N>(s, t, lb, stw, sk + lsafe * C::L, act);
@@ -311,8 +347,9 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_colfft(Cx<T>* __r
 }
 
 // Fused y pass of the inverse chain: output o is the inverse y-FFT of input
-// field src[o] multiplied by m_y^pw[o] (outputs grouped by source, so each
-// input column tile is read once).
+// field src[o] multiplied by m_y^pw[o].  Persistent over column tiles (the
+// grid holds the resident blocks): the column of the next source, or of the
+// next tile's first source, is loaded while the current outputs transform.
 template <typename T, int N, int WW>
 __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T>* __restrict__ in, long fsi,
                                                                   Cx<T>* __restrict__ out, long fso, YOp op,
@@ -320,36 +357,57 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
   using C = ColCfg<T, N, WW>;
   constexpr int M = N / 2;
   constexpr int BPP = (M + C::W - 1) / C::W;
+  constexpr long NTILES = (long)N * BPP;
   __shared__ Cx<T> lds[2 * C::L * C::W];  // two exchange buffers
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
   int phase = 0;
   const int c = threadIdx.x % C::W, t = threadIdx.x / C::W;
-  const long plane = blockIdx.x / BPP;                    // x index
-  const int col = (blockIdx.x % BPP) * C::W + c;          // z index
-  const bool act = col < M;
-  const long off = plane * (long)N * M + (act ? col : 0);
-  Cx<T> v[C::E], y[C::E];
-  int cur = -1;
+  // tile -> (x plane, z column); returns the element offset, act = column exists
+  auto tile_off = [&](long tile, bool& act) -> long {
+    const long plane = tile / BPP;
+    const int col = (int)(tile % BPP) * C::W + c;
+    act = col < M;
+    return plane * (long)N * M + (act ? col : 0);
+  };
+  Cx<T> v[C::E], y[C::E], pf[C::E];
+  auto load = [&](long tile, int src) {
+    bool a;
+    const long off = tile_off(tile, a);
+    const Cx<T>* b = in + src * fsi + off;
+#pragma unroll
+    for (int sl = 0; sl < C::E; ++sl) pf[sl] = a ? b[slot_elem<C::L, C::E, C::R0I>(t, sl) * M] : zero<T>();
+  };
+  long tile = blockIdx.x;
+  if (tile < NTILES) load(tile, op.src[0]);
 #pragma unroll 1
-  for (int o = 0; o < op.nout; ++o) {
-    if (op.src[o] != cur) {
-      cur = op.src[o];
-      const Cx<T>* b = in + cur * fsi + off;
+  for (; tile < NTILES; tile += gridDim.x) {
+    bool act;
+    const long off = tile_off(tile, act);
+#pragma unroll 1
+    for (int o = 0; o < op.nout; ++o) {
+      if (o == 0 || op.src[o] != op.src[o - 1]) {
 #pragma unroll
-      for (int sl = 0; sl < C::E; ++sl) v[sl] = act ? b[slot_elem<C::L, C::E, C::R0I>(t, sl) * M] : zero<T>();
-    }
-    const int pw = op.pw[o];
+        for (int sl = 0; sl < C::E; ++sl) v[sl] = pf[sl];
+        int on = o + 1;
+        while (on < op.nout && op.src[on] == op.src[o]) ++on;
+        if (on < op.nout)
+          load(tile, op.src[on]);
+        else if (tile + gridDim.x < NTILES)
+          load(tile + gridDim.x, op.src[0]);
+      }
+      const int pw = op.pw[o];
 #pragma unroll
-    for (int sl = 0; sl < C::E; ++sl) {
-      const int iy = slot_elem<C::L, C::E, C::R0I>(t, sl);
-      y[sl] = scale(v[sl], mpow<T>(iy < N / 2 ? iy : iy - N, pw));
-    }
-    fft<T, C::L, +1, C::W, SY_PING>(y, t, stw, 1, lds + c, C::L * C::W, &phase);
-    if (act) {
-      Cx<T>* d = out + o * fso + off;
+      for (int sl = 0; sl < C::E; ++sl) {
+        const int iy = slot_elem<C::L, C::E, C::R0I>(t, sl);
+        y[sl] = scale(v[sl], mpow<T>(iy < N / 2 ? iy : iy - N, pw));
+      }
+      fft<T, C::L, +1, C::W, SY_PING>(y, t, stw, 1, lds + c, C::L * C::W, &phase);
+      if (act) {
+        Cx<T>* d = out + o * fso + off;
 #pragma unroll
-      for (int sl = 0; sl < C::E; ++sl) d[slot_elem<C::L, C::E, C::RLI>(t, sl) * M] = y[sl];
+        for (int sl = 0; sl < C::E; ++sl) d[slot_elem<C::L, C::E, C::RLI>(t, sl) * M] = y[sl];
+      }
     }
   }
 }
@@ -357,7 +415,8 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
 // Displacement x pass (the hot path's two x passes).  One input column X
 // (z and y already forward-transformed), forward x-FFT, then one gather per
 // mode of the FP64 radial table(s), rounded once to T, then the outputs
-// with their k_x powers (integer mode numbers, exact in T):
+// with their k_x powers (integer mode numbers, exact in T).  Persistent over
+// column tiles; the next tile's input column loads while this one transforms.
 //   MODE 0: tab = interleaved (PHI, PSI1) per |m|^2;
 //           out 0..2: U_p = F_x^-1[-m_x^p PHI X], out 3..4: V_p = F_x^-1[i m_x^p PSI1 X]
 //   MODE 1: tab = PSI2;  out 0..1: Q_p = F_x^-1[-i m_x^p PSI2 X]
@@ -375,52 +434,66 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
   stage_twiddles<T, N>(stw, tw);
   int phase = 0;
   const int c = threadIdx.x % C::W, t = threadIdx.x / C::W;
-  const long col = (long)blockIdx.x * C::W + c;
-  const bool act = col < NCOL;
-  const long cs = act ? col : 0;
-  const int iy = (int)(cs / M), iz = (int)(cs % M);
-  const int my = iy < N / 2 ? iy : iy - N;
-  const bool keep_y = iy != N / 2;
-  const int n2yz = my * my + iz * iz;
-  Cx<T> va[C::E], vb[C::E], y[C::E];
+  constexpr long NTILES = (NCOL + C::W - 1) / C::W;
+  Cx<T> va[C::E], vb[C::E], y[C::E], pf[C::E];
+  auto load = [&](long tile) {
+    const long col = tile * C::W + c;
+    const bool a = col < NCOL;
+    const long cs = a ? col : 0;
 #pragma unroll
-  for (int sl = 0; sl < C::E; ++sl) va[sl] = act ? in[cs + slot_elem<C::L, C::E, C::R0F>(t, sl) * NCOL] : zero<T>();
-  fft<T, C::L, -1, C::W, SY_PING>(va, t, stw, 1, lds + c, C::L * C::W, &phase);
-#pragma unroll
-  for (int sl = 0; sl < C::E; ++sl) {
-    const int ix = slot_elem<C::L, C::E, C::RLF>(t, sl);
-    const int mx = ix < N / 2 ? ix : ix - N;
-    const int n2 = mx * mx + n2yz;
-    const bool keep = keep_y && ix != N / 2 && n2 != 0;
-    if (MODE == 0) {
-      double2 r = keep ? reinterpret_cast<const double2*>(tab)[n2] : make_double2(0.0, 0.0);
-      vb[sl] = scale(va[sl], T(r.y));
-      va[sl] = scale(va[sl], T(r.x));
-    } else {
-      va[sl] = scale(va[sl], keep ? T(tab[n2]) : T(0));
-    }
-  }
-  constexpr int NOUT = MODE == 0 ? 5 : 2;
+    for (int sl = 0; sl < C::E; ++sl) pf[sl] = a ? in[cs + slot_elem<C::L, C::E, C::R0F>(t, sl) * NCOL] : zero<T>();
+  };
+  long tile = blockIdx.x;
+  if (tile < NTILES) load(tile);
 #pragma unroll 1
-  for (int o = 0; o < NOUT; ++o) {
-    // MODE 0: o < 3 -> -m_x^o * va ; o = 3, 4 -> i m_x^(o-3) * vb.  MODE 1: -i m_x^o * va
-    const bool second = MODE == 0 && o >= 3;
-    const int p = second ? o - 3 : o;
-#pragma unroll
+  for (; tile < NTILES; tile += gridDim.x) {
+    const long col = tile * C::W + c;
+    const bool act = col < NCOL;
+    const long cs = act ? col : 0;
+    const int iy = (int)(cs / M), iz = (int)(cs % M);
+    const int my = iy < N / 2 ? iy : iy - N;
+    const bool keep_y = iy != N / 2;
+    const int n2yz = my * my + iz * iz;
+  #pragma unroll
+    for (int sl = 0; sl < C::E; ++sl) va[sl] = pf[sl];
+    if (tile + gridDim.x < NTILES) load(tile + gridDim.x);  // next tile's column, in flight meanwhile
+    fft<T, C::L, -1, C::W, SY_PING>(va, t, stw, 1, lds + c, C::L * C::W, &phase);
+  #pragma unroll
     for (int sl = 0; sl < C::E; ++sl) {
       const int ix = slot_elem<C::L, C::E, C::RLF>(t, sl);
-      const T f = mpow<T>(ix < N / 2 ? ix : ix - N, p);
-      const Cx<T> a = second ? vb[sl] : va[sl];
-      if (MODE == 0)
-        y[sl] = second ? mk(-a.y * f, a.x * f) : mk(-a.x * f, -a.y * f);
-      else
-        y[sl] = mk(a.y * f, -a.x * f);
+      const int mx = ix < N / 2 ? ix : ix - N;
+      const int n2 = mx * mx + n2yz;
+      const bool keep = keep_y && ix != N / 2 && n2 != 0;
+      if (MODE == 0) {
+        double2 r = keep ? reinterpret_cast<const double2*>(tab)[n2] : make_double2(0.0, 0.0);
+        vb[sl] = scale(va[sl], T(r.y));
+        va[sl] = scale(va[sl], T(r.x));
+      } else {
+        va[sl] = scale(va[sl], keep ? T(tab[n2]) : T(0));
+      }
     }
-    fft<T, C::L, +1, C::W, SY_PING>(y, t, stw, 1, lds + c, C::L * C::W, &phase);
-    if (act) {
-      Cx<T>* dst = out + o * fso + cs;
-#pragma unroll
-      for (int sl = 0; sl < C::E; ++sl) dst[slot_elem<C::L, C::E, C::RLI>(t, sl) * NCOL] = y[sl];
+    constexpr int NOUT = MODE == 0 ? 5 : 2;
+  #pragma unroll 1
+    for (int o = 0; o < NOUT; ++o) {
+      // MODE 0: o < 3 -> -m_x^o * va ; o = 3, 4 -> i m_x^(o-3) * vb.  MODE 1: -i m_x^o * va
+      const bool second = MODE == 0 && o >= 3;
+      const int p = second ? o - 3 : o;
+  #pragma unroll
+      for (int sl = 0; sl < C::E; ++sl) {
+        const int ix = slot_elem<C::L, C::E, C::RLF>(t, sl);
+        const T f = mpow<T>(ix < N / 2 ? ix : ix - N, p);
+        const Cx<T> a = second ? vb[sl] : va[sl];
+        if (MODE == 0)
+          y[sl] = second ? mk(-a.y * f, a.x * f) : mk(-a.x * f, -a.y * f);
+        else
+          y[sl] = mk(a.y * f, -a.x * f);
+      }
+      fft<T, C::L, +1, C::W, SY_PING>(y, t, stw, 1, lds + c, C::L * C::W, &phase);
+      if (act) {
+        Cx<T>* dst = out + o * fso + cs;
+  #pragma unroll
+        for (int sl = 0; sl < C::E; ++sl) dst[slot_elem<C::L, C::E, C::RLI>(t, sl) * NCOL] = y[sl];
+      }
     }
   }
 }
@@ -549,6 +622,17 @@ int col_width(int prec, int n, int i) {
 int default_width(int prec, int n, int kind) {
   (void)kind;
   return col_width(prec, n, 1);
+}
+
+// Grid for a persistent kernel: the blocks that can be resident at once
+// (occupancy of this kernel x compute units), at most one per tile.
+static long resident_grid(const void* kernel, int block, long ntiles) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return ntiles;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, 0) != hipSuccess || per < 1) per = 1;
+  const long g = (long)per * cus;
+  return g < ntiles ? g : ntiles;
 }
 
 static inline size_t esize(int prec) { return prec == PREC_F32 ? 4 : 8; }
@@ -696,7 +780,8 @@ static hipError_t ycombo_w(const void* in, long fsi, void* out, long fso, const 
                            hipStream_t s) {
   using C = ColCfg<T, N, WW>;
   constexpr int M = N / 2;
-  const long blocks = (long)N * ((M + C::W - 1) / C::W);
+  static const long blocks =
+      resident_grid(reinterpret_cast<const void*>(&k_ycombo<T, N, WW>), C::BLOCK, (long)N * ((M + C::W - 1) / C::W));
   hipLaunchKernelGGL((k_ycombo<T, N, WW>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in, fsi,
                      (Cx<T>*)out, fso, op, (const Cx<T>*)tw);
   return hipGetLastError();
@@ -729,8 +814,10 @@ template <typename T, int N, int WW>
 static hipError_t xdisp_w(int mode, const void* in, void* out, long fso, const double* tab, const void* tw,
                           hipStream_t s) {
   using C = ColCfg<T, N, WW>;
-  const long ncol = (long)N * (N / 2);
-  const long blocks = (ncol + C::W - 1) / C::W;
+  const long ntiles = ((long)N * (N / 2) + C::W - 1) / C::W;
+  static const long b0 = resident_grid(reinterpret_cast<const void*>(&k_xdisp<T, N, WW, 0>), C::BLOCK, ntiles);
+  static const long b1 = resident_grid(reinterpret_cast<const void*>(&k_xdisp<T, N, WW, 1>), C::BLOCK, ntiles);
+  const long blocks = mode == 0 ? b0 : b1;
   if (mode == 0)
     hipLaunchKernelGGL((k_xdisp<T, N, WW, 0>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in,
                        (Cx<T>*)out, fso, tab, (const Cx<T>*)tw);
