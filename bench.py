@@ -28,6 +28,7 @@ FR0S = (1e-6, 1e-4)
 REDSHIFTS = (0.0, 1.0)
 SEEDS = (1, 2, 3, 4)
 CSRC = os.path.join(ROOT, "paper_1909_06282_amd", "csrc")
+COPY_BYTES = 512 << 20
 
 
 def source_hash() -> str:
@@ -142,6 +143,20 @@ def main():
                      "share": round(v[1] / sum(x[1] for x in kernels.values()), 3)}
                  for k, v in sorted(kernels.items(), key=lambda kv: -kv[1][1])}
 
+    # plain device copy of known size: context bandwidth, and the scale for the
+    # FETCH_SIZE / WRITE_SIZE counters (512 MiB read + 512 MiB written)
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    for _ in range(10):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * COPY_BYTES * 10 / (time.perf_counter() - c0) / 1e9
+    del src, dst
+
     # FP32 error against the FP64 GPU path (itself parity-tested against the oracle)
     extra = {}
     if not args.no_fp64:
@@ -199,6 +214,7 @@ def main():
         "kernels": breakdown,
         "algorithmic_GBps_whole_step": round(sum(v[2] * v[0] for v in kernels.values()) / args.steps
                                              / (gpu_ms / args.steps / 1e3) / 1e9, 1),
+        "copy_GBps": round(copy_gbs, 1),
         "source_hash": source_hash(),
     }
     out.update(extra)
