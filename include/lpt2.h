@@ -139,7 +139,7 @@ lpt2_status lpt2_displace(lpt2_plan_t plan, double a, const void* const* noise,
  * isqrt(|m|^2 nbins^2 / (n/2)^2); weight 2 for 0 < m_z < n/2, else 1; DC and
  * modes beyond the last shell are left out.  Writes nbins values to each host
  * array: mean k, weighted count, mean q, population std of q (zeros for an
- * empty shell).  Synchronises `stream` before returning.  nbins in 1..4096. */
+ * empty shell).  Synchronises `stream` before returning.  nbins in 1..512. */
 lpt2_status lpt2_source_spectrum(lpt2_plan_t plan, double a, const void* noise, int nbins,
                                  int quantity, double* k_mean, double* count,
                                  double* mean, double* std_dev, void* stream);

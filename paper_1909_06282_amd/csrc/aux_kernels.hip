@@ -113,9 +113,14 @@ __global__ void k_radial(RadialSetup r, const double* __restrict__ d1n, const do
     }
   }
   for (int i = 0; i < TAB_COUNT; ++i) tabs[i * n2cnt + n2] = v[i];
-  double* pair = tabs + (long)TAB_COUNT * n2cnt;
+  double* pair = tabs + (long)TAB_PAIR64 * n2cnt;
   pair[2 * n2] = v[TAB_PHI];
   pair[2 * n2 + 1] = v[TAB_PSI1];
+  float* pair32 = reinterpret_cast<float*>(tabs + (long)TAB_PAIR32 * n2cnt);
+  pair32[2 * n2] = (float)v[TAB_PHI];
+  pair32[2 * n2 + 1] = (float)v[TAB_PSI1];
+  float* psi2_32 = reinterpret_cast<float*>(tabs + (long)TAB_PSI2_32 * n2cnt);
+  psi2_32[n2] = (float)v[TAB_PSI2];
 }
 
 hipError_t launch_radial(const RadialSetup& r, const double* d1n, const double* d2n, double* tabs, long n2cnt,

@@ -184,7 +184,8 @@ __device__ __forceinline__ void c2r_prepare_regs(const Cx<T>* raw, int r, Cx<T>*
   }
 }
 // S = phi_xx phi_yy + (phi_xx + phi_yy) phi_zz - phi_xy^2 - phi_xz^2 - phi_yz^2
-// per real value (field f of the six multiplied by m_z^rpow[f] first), then
+// per real value (logical field f of the six, stored at field zp.fmap[f],
+// multiplied by m_z^zp.r[f] first), then
 // the forward R2C of the S line.  The line of field f+1 is loaded while
 // field f is transformed, so the load latency hides behind the transform.
 template <typename T, int N>
@@ -202,12 +203,12 @@ __global__ __launch_bounds__(256) void k_zsource(const Cx<T>* __restrict__ phi, 
   Cx<T> a[C::E], s[C::E], v[C::E], raw[C::E], nxt[C::E];
   const Cx<T>* src = phi + lsafe * C::L;
 #pragma unroll
-  for (int q = 0; q < C::E; ++q) raw[q] = act ? src[t + q * C::TPL] : zero<T>();
+  for (int q = 0; q < C::E; ++q) raw[q] = act ? src[zp.fmap[0] * fstride + t + q * C::TPL] : zero<T>();
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     if (f < 5) {
 #pragma unroll
-      for (int q = 0; q < C::E; ++q) nxt[q] = act ? src[(f + 1) * fstride + t + q * C::TPL] : zero<T>();
+      for (int q = 0; q < C::E; ++q) nxt[q] = act ? src[zp.fmap[f + 1] * fstride + t + q * C::TPL] : zero<T>();
     }
     c2r_prepare_regs<T, N>(raw, zp.r[f], v, t, lb, stw);
     fft<T, C::L, +1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
@@ -414,7 +415,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
 
 // Displacement x pass (the hot path's two x passes).  One input column X
 // (z and y already forward-transformed), forward x-FFT, then one gather per
-// mode of the FP64 radial table(s), rounded once to T, then the outputs
+// mode of the radial table(s) (built in FP64, stored rounded once to T), then the outputs
 // with their k_x powers (integer mode numbers, exact in T).  Persistent over
 // column tiles; the next tile's input column loads while this one transforms.
 //   MODE 0: tab = interleaved (PHI, PSI1) per |m|^2;
@@ -424,7 +425,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
 template <typename T, int N, int WW, int MODE>
 __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>* __restrict__ in,
                                                                  Cx<T>* __restrict__ out, long fso,
-                                                                 const double* __restrict__ tab,
+                                                                 const T* __restrict__ tab,
                                                                  const Cx<T>* __restrict__ tw) {
   using C = ColCfg<T, N, WW>;
   constexpr int M = N / 2;
@@ -465,11 +466,11 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
       const int n2 = mx * mx + n2yz;
       const bool keep = keep_y && ix != N / 2 && n2 != 0;
       if (MODE == 0) {
-        double2 r = keep ? reinterpret_cast<const double2*>(tab)[n2] : make_double2(0.0, 0.0);
-        vb[sl] = scale(va[sl], T(r.y));
-        va[sl] = scale(va[sl], T(r.x));
+        const Cx<T> r = keep ? reinterpret_cast<const Cx<T>*>(tab)[n2] : zero<T>();
+        vb[sl] = scale(va[sl], r.y);
+        va[sl] = scale(va[sl], r.x);
       } else {
-        va[sl] = scale(va[sl], keep ? T(tab[n2]) : T(0));
+        va[sl] = scale(va[sl], keep ? tab[n2] : T(0));
       }
     }
     constexpr int NOUT = MODE == 0 ? 5 : 2;
@@ -661,13 +662,18 @@ hipError_t launch_zr2c(int prec, int n, const void* in, size_t in_cap, void* out
 ZPow zpow_none(long lines_per_field) {
   ZPow z;
   z.lines_per_field = lines_per_field > 0 ? lines_per_field : 1;
-  for (int i = 0; i < ZPOW_MAX; ++i) z.r[i] = 0;
+  for (int i = 0; i < ZPOW_MAX; ++i) {
+    z.r[i] = 0;
+    z.fmap[i] = i;
+  }
   return z;
 }
 static bool zpow_ok(const ZPow& zp) {
   if (zp.lines_per_field <= 0) return false;
   for (int i = 0; i < ZPOW_MAX; ++i)
     if (zp.r[i] < 0 || zp.r[i] > 2) return false;
+  for (int i = 0; i < 6; ++i)
+    if (zp.fmap[i] < 0 || zp.fmap[i] > 5) return false;
   return true;
 }
 
@@ -811,7 +817,7 @@ hipError_t launch_ycombo(int prec, int n, const void* in, size_t in_cap, long in
 }
 
 template <typename T, int N, int WW>
-static hipError_t xdisp_w(int mode, const void* in, void* out, long fso, const double* tab, const void* tw,
+static hipError_t xdisp_w(int mode, const void* in, void* out, long fso, const void* tab, const void* tw,
                           hipStream_t s) {
   using C = ColCfg<T, N, WW>;
   const long ntiles = ((long)N * (N / 2) + C::W - 1) / C::W;
@@ -820,14 +826,14 @@ static hipError_t xdisp_w(int mode, const void* in, void* out, long fso, const d
   const long blocks = mode == 0 ? b0 : b1;
   if (mode == 0)
     hipLaunchKernelGGL((k_xdisp<T, N, WW, 0>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in,
-                       (Cx<T>*)out, fso, tab, (const Cx<T>*)tw);
+                       (Cx<T>*)out, fso, (const T*)tab, (const Cx<T>*)tw);
   else
     hipLaunchKernelGGL((k_xdisp<T, N, WW, 1>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in,
-                       (Cx<T>*)out, fso, tab, (const Cx<T>*)tw);
+                       (Cx<T>*)out, fso, (const T*)tab, (const Cx<T>*)tw);
   return hipGetLastError();
 }
 template <typename T, int N>
-static hipError_t xdisp_t(int w, int mode, const void* in, void* out, long fso, const double* tab, const void* tw,
+static hipError_t xdisp_t(int w, int mode, const void* in, void* out, long fso, const void* tab, const void* tw,
                           hipStream_t s) {
   if (w == col_w<T>(N, 0)) return xdisp_w<T, N, col_w<T>(N, 0)>(mode, in, out, fso, tab, tw, s);
   if (w == col_w<T>(N, 1)) return xdisp_w<T, N, col_w<T>(N, 1)>(mode, in, out, fso, tab, tw, s);
@@ -835,7 +841,7 @@ static hipError_t xdisp_t(int w, int mode, const void* in, void* out, long fso, 
   return hipErrorInvalidValue;
 }
 hipError_t launch_xdisp(int prec, int n, int mode, const void* in, size_t in_cap, void* out, size_t out_cap,
-                        long out_fstride, const double* tab, size_t tab_cap, const void* tw, hipStream_t s, int w) {
+                        long out_fstride, const void* tab, size_t tab_cap, const void* tw, hipStream_t s, int w) {
   if (w == 0) w = default_width(prec, n, KIND_MULTI);
   if (!pow2n(n) || !in || !out || !tab || !tw || out_fstride < 0 || (mode != 0 && mode != 1))
     return hipErrorInvalidValue;
@@ -843,7 +849,7 @@ hipError_t launch_xdisp(int prec, int n, int mode, const void* in, size_t in_cap
   const int nout = mode == 0 ? 5 : 2;
   if (field * cb > in_cap || ((size_t)(nout - 1) * out_fstride + field) * cb > out_cap) return hipErrorInvalidValue;
   const size_t n2cnt = 3 * (size_t)(n / 2) * (n / 2) + 1;
-  if (n2cnt * (mode == 0 ? 16 : 8) > tab_cap) return hipErrorInvalidValue;
+  if (n2cnt * esize(prec) * (mode == 0 ? 2 : 1) > tab_cap) return hipErrorInvalidValue;
 #define CALL(NN) return prec == PREC_F32 ? xdisp_t<float, NN>(w, mode, in, out, out_fstride, tab, tw, s) : xdisp_t<double, NN>(w, mode, in, out, out_fstride, tab, tw, s)
   LPT2_SWITCH_N(n, CALL)
 #undef CALL

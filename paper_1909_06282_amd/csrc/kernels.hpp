@@ -38,6 +38,7 @@ constexpr int ZPOW_MAX = 16;
 struct ZPow {
   long lines_per_field;
   int r[ZPOW_MAX];
+  int fmap[ZPOW_MAX];   // source pass: logical field f is stored at field fmap[f]
 };
 ZPow zpow_none(long lines_per_field);
 
@@ -66,9 +67,10 @@ int default_width(int prec, int n, int kind);
 hipError_t launch_ycombo(int prec, int n, const void* in, size_t in_cap, long in_fstride, void* out, size_t out_cap,
                          long out_fstride, const YOp& op, const void* tw, hipStream_t s, int w = 0);
 // displacement x pass: mode 0 (tab = interleaved PHI, PSI1 per |m|^2; five
-// outputs U0,U1,U2,V0,V1) or mode 1 (tab = PSI2; outputs Q0,Q1); tab_cap in bytes
+// outputs U0,U1,U2,V0,V1) or mode 1 (tab = PSI2; outputs Q0,Q1).  The table
+// is in the working precision (pair: 2 values per |m|^2); tab_cap in bytes.
 hipError_t launch_xdisp(int prec, int n, int mode, const void* in, size_t in_cap, void* out, size_t out_cap,
-                        long out_fstride, const double* tab, size_t tab_cap, const void* tw, hipStream_t s, int w = 0);
+                        long out_fstride, const void* tab, size_t tab_cap, const void* tw, hipStream_t s, int w = 0);
 // fused x pass over the n*(n/2) columns of each field
 hipError_t launch_xpass(int prec, int n, const void* in, size_t in_cap, long in_fstride, void* out, size_t out_cap,
                         long out_fstride, const XOp& op, long n2cnt, const void* tw, hipStream_t s);
@@ -98,8 +100,11 @@ enum {
   TAB_PSI1 = 0, TAB_PHI, TAB_PSI2, TAB_A, TAB_R1, TAB_R2, TAB_R3, TAB_R4, TAB_R5, TAB_R6,
   TAB_C2, TAB_C4, TAB_C5, TAB_COUNT
 };
-// after the TAB_COUNT rows: the interleaved (PHI, PSI1) pair table, 2 rows
-constexpr int TAB_ROWS = TAB_COUNT + 2;
+// after the TAB_COUNT rows: the interleaved (PHI, PSI1) pair table (2 rows),
+// then FP32 copies of the pair table (float2, 1 row) and of PSI2 (float,
+// half a row): FP32 passes gather these (the same values rounded once).
+constexpr int TAB_PAIR64 = TAB_COUNT, TAB_PAIR32 = TAB_COUNT + 2, TAB_PSI2_32 = TAB_COUNT + 3;
+constexpr int TAB_ROWS = TAB_COUNT + 4;
 struct RadialSetup {
   Cosmo c;
   int n;

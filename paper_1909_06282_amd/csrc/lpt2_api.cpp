@@ -375,12 +375,16 @@ lpt2_status xp(Ctx& c, const char* name, const void* in, void* out, const XOp& o
       launch_xpass(p->prec, g.n, in, c.cap(in), fst, out, c.cap(out), fst, op, g.n2cnt, g.tw, s));
   return LPT2_OK;
 }
-lpt2_status xdisp(Ctx& c, const char* name, int mode, const void* in, void* out, const double* tab, size_t tab_cap) {
+lpt2_status xdisp(Ctx& c, const char* name, int mode, const void* in, void* out, const Tables* t) {
   lpt2_plan_t p = c.p;
   hipStream_t s = c.s;
   Grid& g = c.g;
+  const bool f32 = p->prec == PREC_F32;
+  const int row = mode == 0 ? (f32 ? TAB_PAIR32 : TAB_PAIR64) : (f32 ? TAB_PSI2_32 : TAB_PSI2);
+  const void* tab = t->radial + (size_t)row * g.n2cnt;
+  const size_t cap = sizeof(double) * (size_t)(TAB_ROWS - row) * g.n2cnt;
   RUN(name, (double)c.field() * (mode == 0 ? 6 : 3),
-      launch_xdisp(p->prec, g.n, mode, in, c.cap(in), out, c.cap(out), g.nnm, tab, tab_cap, g.tw, s, g.tiles[2]));
+      launch_xdisp(p->prec, g.n, mode, in, c.cap(in), out, c.cap(out), g.nnm, tab, cap, g.tw, s, g.tiles[2]));
   return LPT2_OK;
 }
 lpt2_status z_c2r(Ctx& c, const char* name, const void* in, void* out, size_t out_cap, int nf,
@@ -396,13 +400,15 @@ lpt2_status z_c2r(Ctx& c, const char* name, const void* in, void* out, size_t ou
       launch_zc2r(p->prec, g.n, in, c.cap(in), out, out_cap, (long)nf * g.n * g.n, zp, g.tw, s));
   return LPT2_OK;
 }
-lpt2_status z_source(Ctx& c, const void* phi, void* sk, const int* rpow = nullptr) {
+lpt2_status z_source(Ctx& c, const void* phi, void* sk, const int* rpow = nullptr, const int* fmap = nullptr) {
   lpt2_plan_t p = c.p;
   hipStream_t s = c.s;
   Grid& g = c.g;
   ZPow zp = zpow_none((long)g.n * g.n);
-  if (rpow)
-    for (int f = 0; f < 6; ++f) zp.r[f] = rpow[f];
+  for (int f = 0; f < 6; ++f) {
+    if (rpow) zp.r[f] = rpow[f];
+    if (fmap) zp.fmap[f] = fmap[f];
+  }
   RUN("z_fused_source", (double)c.field() * 7.0,
       launch_zsource(p->prec, g.n, phi, c.cap(phi), g.nnm, zp, sk, c.cap(sk), (long)g.n * g.n, g.tw, s));
   return LPT2_OK;
@@ -442,19 +448,20 @@ YOp yop(int nin, int nout, const int* src, const int* pw) {
 lpt2_status displace_one(Ctx& c, const Tables* t, const void* noise, void* psi1, void* psi2) {
   Grid& g = c.g;
   CHK(fwd_zy(c, "z_r2c_noise", "y_fwd_noise", noise, c.field(), c.slot(0), 1));
-  CHK(xdisp(c, "x_fused_psi1_phi", 0, c.slot(0), c.slot(1), t->radial + (size_t)TAB_COUNT * g.n2cnt,
-            sizeof(double) * 2 * g.n2cnt));
-  // outputs: psi1 x,y,z then phi xx,yy,zz,xy,xz,yz (inputs U0,U1,U2,V0,V1 = 0..4)
-  const int src9[9] = {4, 3, 3, 2, 0, 0, 1, 1, 0};
-  const int pw9[9] = {0, 1, 0, 0, 2, 0, 1, 0, 1};
+  CHK(xdisp(c, "x_fused_psi1_phi", 0, c.slot(0), c.slot(1), t));
+  // outputs (inputs U0,U1,U2,V0,V1 = 0..4, grouped so each is read once):
+  // psi1 x,y,z, then phi stored as xx,xy,xz,yy,zz,yz
+  const int src9[9] = {4, 3, 3, 2, 1, 1, 0, 0, 0};
+  const int pw9[9] = {0, 1, 0, 0, 1, 0, 2, 0, 1};
   CHK(ycombo(c, "y_inv_psi1_phi", c.slot(1), c.slot(6), yop(5, 9, src9, pw9)));
   const int rz1[3] = {0, 0, 1};
   CHK(z_c2r(c, "z_c2r_psi1", c.slot(6), psi1, 3 * c.field(), 3, rz1));
+  // source pass order xx,yy,zz,xy,xz,yz: m_z powers and storage positions
   const int rzs[6] = {0, 0, 2, 0, 1, 1};
-  CHK(z_source(c, c.slot(9), c.slot(0), rzs));
+  const int fms[6] = {0, 3, 4, 1, 2, 5};
+  CHK(z_source(c, c.slot(9), c.slot(0), rzs, fms));
   CHK(fwd_y(c, "y_fwd_source", c.slot(0), 1));
-  CHK(xdisp(c, "x_fused_psi2", 1, c.slot(0), c.slot(1), t->radial + (size_t)TAB_PSI2 * g.n2cnt,
-            sizeof(double) * g.n2cnt));
+  CHK(xdisp(c, "x_fused_psi2", 1, c.slot(0), c.slot(1), t));
   const int src3[3] = {1, 0, 0};
   const int pw3[3] = {0, 1, 0};
   CHK(ycombo(c, "y_inv_psi2", c.slot(1), c.slot(3), yop(2, 3, src3, pw3)));
