@@ -73,6 +73,59 @@ def cpu_baseline(fr0: float, a: float, seed: int):
                       f"|f_R0|={fr0:g}, a={a}, seed {seed}; growth tables excluded; {dt:.2f} s"}
 
 
+def batched(steps: int, warmup: int):
+    """The batched mix: 64 x 128^3 (L=256) + 32 x 64^3 (L=128), |f_R0| = 1e-5,
+    z = 0, seeds 100-195, FP32; tiles from the tuner, the whole batch one
+    captured graph per step."""
+    import numpy as np
+    import torch
+    from paper_1909_06282_amd import LPT2Config, Plan
+    from seeded_inputs import white_noise
+    dev = torch.device("cuda:0")
+    cfgs = [LPT2Config(n=128, box=256.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", precision="fp32"),
+            LPT2Config(n=64, box=128.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", precision="fp32")]
+    plan = Plan(cfgs, counts=[64, 32])
+    sizes = [128] * 64 + [64] * 32
+    noise = [torch.from_numpy(white_noise(n, s, np.float32)).to(dev) for n, s in zip(sizes, range(100, 196))]
+    p1 = [torch.empty((3, n, n, n), dtype=torch.float32, device=dev) for n in sizes]
+    p2 = [torch.empty_like(x) for x in p1]
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    tiles = plan.autotune(1.0, noise, p1, p2, stream=stream)
+    tune_s = time.perf_counter() - t0
+    cells = float(sum(n ** 3 for n in sizes))
+
+    def timed(k):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(k):
+            plan.displace(1.0, noise, p1, p2, stream=stream)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / k
+
+    for _ in range(warmup):
+        plan.displace(1.0, noise, p1, p2, stream=stream)
+    eager = timed(max(4, steps // 2))
+    plan.profile_reset()
+    plan.profile_enable(True)
+    plan.displace(1.0, noise, p1, p2, stream=stream)
+    torch.cuda.synchronize()
+    prof = {f"{name} [{by / 1e9:.3f} GB]": {"launches": launches, "avg_ms": round(ms / max(launches, 1), 4),
+                                            "GBps": round(by / (ms / launches / 1e3) / 1e9, 1) if ms > 0 else None}
+            for name, launches, ms, by in plan.profile()}
+    plan.profile_enable(False)
+    plan.set_graph(True)
+    for _ in range(warmup):                    # first call captures the graph
+        plan.displace(1.0, noise, p1, p2, stream=stream)
+    graph = timed(steps)
+    return {"workload": "64 x 128^3 (L=256) + 32 x 64^3 (L=128) realisations, Hu-Sawicki |f_R0|=1e-5, z=0, "
+                        "seeds 100-195, FP32, one hipGraph launch per batch",
+            "cells_per_batch": cells, "value": cells / graph, "unit": "grid-cells/s",
+            "ms_per_batch": round(graph * 1e3, 4), "eager_ms_per_batch": round(eager * 1e3, 4),
+            "steps": steps, "tiles": {"128": tiles[0], "64": tiles[1]}, "tune_s": round(tune_s, 2),
+            "kernels_eager": prof}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +133,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 companion measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-mix measurement")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -218,6 +272,9 @@ def main():
         "source_hash": source_hash(),
     }
     out.update(extra)
+    if not args.no_batch:
+        out["batched"] = batched(max(8, args.steps // 2), 3)
+        torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(*combos[0][:1], 1.0, 1)
     print(json.dumps(out), flush=True)

@@ -100,8 +100,11 @@ void lpt2_config_default(lpt2_config* cfg);
  * field on the host before any device work: n not a power of two in 8..512,
  * hs_n != 1 or an unknown precision -> LPT2_EUNSUPPORTED; box <= 0,
  * fr0_abs <= 0 for f(R), bad growth grid or null out -> LPT2_EINVAL.
- * Allocates the workspace for the largest grid and the FP64 twiddles on the
- * current device.  On failure *out is NULL. */
+ * Allocates, on the current device, the twiddles and a workspace of 16
+ * half-spectrum slots per realisation of a batch: the realisations of one
+ * configuration are transformed up to 64 at a time (fewer where 16 slots of
+ * that many fields would pass 16 GiB), and every configuration has a region
+ * of its own.  On failure *out is NULL. */
 lpt2_status lpt2_plan(const lpt2_config* cfgs, int n_cfgs, const int* counts, lpt2_plan_t* out);
 
 /* Release every device and host resource of the plan (NULL is a no-op). */
@@ -124,9 +127,49 @@ lpt2_status lpt2_realisation_info(lpt2_plan_t plan, int r, int* n, int* precisio
  * noise; psi1 and psi2 [3][n][n][n] outputs.  The first call for a new a
  * builds its growth tables on `stream` (FP64 RK4 on the GPU, then per-|m|^2
  * tables) and caches them; later calls with the same a allocate nothing and
- * never synchronise, so they can be captured in a hipGraph. */
+ * never synchronise.
+ * Batches: each kernel of the chain covers a whole batch of realisations of
+ * one configuration (one launch per pass, not per realisation).  With several
+ * configurations each runs on a stream of the plan's own, forked from and
+ * joined back into `stream`, so grids of different n overlap on the GPU.
+ * In graph mode (lpt2_set_graph) the whole sequence is captured once per
+ * (a, set of buffers) and later calls launch the graph on `stream`. */
 lpt2_status lpt2_displace(lpt2_plan_t plan, double a, const void* const* noise,
                           void* const* psi1, void* const* psi2, void* stream);
+
+/* Graph mode on (enable != 0) or off.  In graph mode lpt2_displace captures
+ * its launches (all grids and batches, with their fork and join) into a
+ * hipGraph on a stream of the plan, instantiates it, caches it under
+ * (a, noise/psi1/psi2 pointers) -- up to 8 graphs -- and launches it on the
+ * caller's stream; a call with the same a and pointers only launches.
+ * Turning graph mode off, changing tiles, or evicting growth tables
+ * destroys the cached graphs (after a device synchronisation). */
+lpt2_status lpt2_set_graph(lpt2_plan_t plan, int enable);
+
+/* Tile widths (columns per workgroup) of configuration `grid`'s strided
+ * passes: tiles[0] the single y (and x) FFT passes, tiles[1] the fused y
+ * pass, tiles[2] the fused x pass.  lpt2_tile_options writes the three
+ * widths offered for that grid's n and precision (64-, 128- and 256-byte row
+ * runs, clamped to the workgroup and LDS limits; entries may repeat).
+ * lpt2_set_tiles takes widths from that list, or 0 for the default
+ * (128-byte runs); anything else is LPT2_EINVAL.  Synchronises if the
+ * tiles change. */
+lpt2_status lpt2_get_tiles(lpt2_plan_t plan, int grid, int* tiles);
+lpt2_status lpt2_set_tiles(lpt2_plan_t plan, int grid, const int* tiles);
+lpt2_status lpt2_tile_options(lpt2_plan_t plan, int grid, int* widths);
+
+/* Tile tuner: for every configuration, runs its batches at a on the given
+ * buffers (same meaning as lpt2_displace; their contents are overwritten)
+ * under every combination of the offered tile widths, timing each with HIP
+ * events on `stream` (one warm run, minimum of three), and keeps the fastest.
+ * cache_path (may be NULL) names a text file: an entry for the same device
+ * architecture, precision, n and batch size is used without timing, and new
+ * results are appended as lines
+ *   lpt2-tiles <arch> <fp32|fp64> <n> <batch> <tile0> <tile1> <tile2>
+ * Synchronises. */
+lpt2_status lpt2_autotune(lpt2_plan_t plan, double a, const void* const* noise,
+                          void* const* psi1, void* const* psi2, const char* cache_path,
+                          void* stream);
 
 /* Shell-binned spectrum of the source for realisation 0 (Sec. 3: bin a
  * per-mode quantity in k, report mean and 1-sigma scatter).
@@ -188,12 +231,14 @@ lpt2_status lpt2_growth_table(lpt2_plan_t plan, double a, double* k, double* d1,
  * Device pointers; `in` is left unchanged. */
 lpt2_status lpt2_fft3d(lpt2_plan_t plan, int direction, const void* in, void* out, void* stream);
 
-/* Per-kernel timing with HIP events on the calling stream.  enable != 0
- * records an event pair around every kernel launch of later calls; the
- * counters accumulate until lpt2_profile_reset.  lpt2_profile_get reports
- * kernel i (0-based, i < lpt2_profile_count): its name (static storage),
- * launches, summed milliseconds and algorithmic bytes per launch (the
- * compulsory reads and writes of that kernel).  Synchronises. */
+/* Per-kernel timing with HIP events on the stream each kernel is launched
+ * on.  enable != 0 records an event pair around every kernel launch of later
+ * eager calls (not inside a graph capture); the counters accumulate until
+ * lpt2_profile_reset.  lpt2_profile_get reports entry i (0-based,
+ * i < lpt2_profile_count), one per (launch site, bytes per launch): its name
+ * (static storage), launches, summed milliseconds and algorithmic bytes per
+ * launch (the compulsory reads and writes of that kernel over its whole
+ * batch).  Synchronises. */
 lpt2_status lpt2_profile_enable(lpt2_plan_t plan, int enable);
 lpt2_status lpt2_profile_reset(lpt2_plan_t plan);
 int         lpt2_profile_count(lpt2_plan_t plan);

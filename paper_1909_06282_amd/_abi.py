@@ -44,7 +44,8 @@ EXPORTS = [
     "lpt2_displace", "lpt2_source_spectrum", "lpt2_triangle_ratio", "lpt2_backward", "lpt2_paint_cic",
     "lpt2_paint_cic_backward", "lpt2_growth_table", "lpt2_fft3d", "lpt2_profile_enable",
     "lpt2_profile_reset", "lpt2_profile_count", "lpt2_profile_get", "lpt2_workspace_bytes",
-    "lpt2_strerror", "lpt2_last_error",
+    "lpt2_strerror", "lpt2_last_error", "lpt2_set_graph", "lpt2_get_tiles", "lpt2_set_tiles",
+    "lpt2_tile_options", "lpt2_autotune",
 ]
 
 _lib = None
@@ -81,6 +82,11 @@ def load() -> C.CDLL:
     L.lpt2_profile_get.argtypes = [plan_t, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_longlong), dp, dp]
     L.lpt2_workspace_bytes.argtypes = [plan_t]
     L.lpt2_workspace_bytes.restype = C.c_longlong
+    L.lpt2_set_graph.argtypes = [plan_t, C.c_int]
+    L.lpt2_get_tiles.argtypes = [plan_t, C.c_int, ip]
+    L.lpt2_set_tiles.argtypes = [plan_t, C.c_int, ip]
+    L.lpt2_tile_options.argtypes = [plan_t, C.c_int, ip]
+    L.lpt2_autotune.argtypes = [plan_t, C.c_double, vpp, vpp, vpp, C.c_char_p, vp]
     L.lpt2_strerror.argtypes = [C.c_int]
     L.lpt2_strerror.restype = C.c_char_p
     L.lpt2_last_error.argtypes = [plan_t]
@@ -88,7 +94,8 @@ def load() -> C.CDLL:
     for name in ("lpt2_plan", "lpt2_destroy", "lpt2_realisation_info", "lpt2_displace", "lpt2_source_spectrum",
                  "lpt2_triangle_ratio", "lpt2_backward", "lpt2_paint_cic", "lpt2_paint_cic_backward",
                  "lpt2_growth_table", "lpt2_fft3d", "lpt2_profile_enable", "lpt2_profile_reset",
-                 "lpt2_profile_get"):
+                 "lpt2_profile_get", "lpt2_set_graph", "lpt2_get_tiles", "lpt2_set_tiles", "lpt2_tile_options",
+                 "lpt2_autotune"):
         getattr(L, name).restype = C.c_int
     L.lpt2_realisations.restype = C.c_int
     L.lpt2_profile_count.restype = C.c_int

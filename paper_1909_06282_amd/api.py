@@ -127,6 +127,9 @@ class Plan:
         noise = self._lists(noise)
         if len(noise) != len(self.sizes):
             raise ValueError(f"plan holds {len(self.sizes)} realisations")
+        if (psi1 is not None and len(self._lists(psi1)) != len(noise)) or \
+                (psi2 is not None and len(self._lists(psi2)) != len(noise)):
+            raise ValueError(f"plan holds {len(self.sizes)} realisations")
         if psi1 is None:
             psi1 = [torch.empty((3, n, n, n), dtype=self.dtype, device=w.device) for w, n in zip(noise, self.sizes)]
         if psi2 is None:
@@ -139,6 +142,38 @@ class Plan:
         _abi.check(self._lib.lpt2_displace(self.handle, float(a), _ptrs(noise), _ptrs(psi1), _ptrs(psi2),
                                            _stream(stream)), self.handle)
         return (psi1[0], psi2[0]) if single else (psi1, psi2)
+
+    def set_graph(self, enable: bool = True):
+        """lpt2_set_graph: capture lpt2_displace into cached hipGraphs."""
+        _abi.check(self._lib.lpt2_set_graph(self.handle, int(bool(enable))), self.handle)
+
+    def tile_options(self, grid: int = 0):
+        w = (C.c_int * 3)()
+        _abi.check(self._lib.lpt2_tile_options(self.handle, int(grid), w), self.handle)
+        return list(w)
+
+    def get_tiles(self, grid: int = 0):
+        w = (C.c_int * 3)()
+        _abi.check(self._lib.lpt2_get_tiles(self.handle, int(grid), w), self.handle)
+        return list(w)
+
+    def set_tiles(self, grid: int, tiles):
+        w = (C.c_int * 3)(*[int(x) for x in tiles])
+        _abi.check(self._lib.lpt2_set_tiles(self.handle, int(grid), w), self.handle)
+
+    def autotune(self, a: float, noise, psi1, psi2, cache_path: str | None = None, stream=None):
+        """lpt2_autotune over the plan's realisations (buffers as for displace; overwritten)."""
+        noise, psi1, psi2 = self._lists(noise), self._lists(psi1), self._lists(psi2)
+        if not (len(noise) == len(psi1) == len(psi2) == len(self.sizes)):
+            raise ValueError(f"plan holds {len(self.sizes)} realisations")
+        for w, p1, p2, n in zip(noise, psi1, psi2, self.sizes):
+            self._check_field(w, (n, n, n), "noise")
+            self._check_field(p1, (3, n, n, n), "psi1")
+            self._check_field(p2, (3, n, n, n), "psi2")
+        path = None if cache_path is None else str(cache_path).encode()
+        _abi.check(self._lib.lpt2_autotune(self.handle, float(a), _ptrs(noise), _ptrs(psi1), _ptrs(psi2), path,
+                                           _stream(stream)), self.handle)
+        return [self.get_tiles(g) for g in range(len(self.cfgs))]
 
     def backward(self, a: float, noise, g_psi1, g_psi2, g_noise=None, stream=None):
         """lpt2_backward: d/dw sum(g_psi1 psi1 + g_psi2 psi2)."""

@@ -12,6 +12,8 @@
 // axis), where a line sits in registers in real space.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include "fft_core.hpp"
 #include "kernels.hpp"
 
@@ -113,8 +115,21 @@ __device__ __forceinline__ void c2r_prepare(const Cx<T>* src, int r, Cx<T>* v, i
   }
 }
 
+// Line `line` of a Batch (f-major, then realisation, then line): where it
+// sits in the caller's buffer (reals) and in the workspace (complex).
+template <int N>
+__device__ __forceinline__ void batch_line(const Batch& b, long line, int& f, int& r, long& ext_off, long& ws_off) {
+  constexpr long NN = (long)N * N;
+  const int fr = (int)(line / NN);  // < nf * nr
+  const long l = line - (long)fr * NN;
+  f = fr / b.nr;
+  r = fr - f * b.nr;
+  ext_off = f * b.ext_fstride + l * N;
+  ws_off = f * b.ws_fstride + r * b.ws_rstride + l * (N / 2);
+}
+
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_zr2c(const T* in, Cx<T>* out, long nlines, const Cx<T>* __restrict__ tw) {
+__global__ __launch_bounds__(256) void k_zr2c(Batch b, Cx<T>* ws, long nlines, const Cx<T>* __restrict__ tw) {
   using C = LineCfg<N>;
   __shared__ Cx<T> lds[C::G * C::SPAN];
   __shared__ Cx<T> stw[N];
@@ -122,17 +137,19 @@ __global__ __launch_bounds__(256) void k_zr2c(const T* in, Cx<T>* out, long nlin
   const int t = threadIdx.x % C::TPL, g = threadIdx.x / C::TPL;
   const long line = (long)blockIdx.x * C::G + g;
   const bool act = line < nlines;
-  const long lsafe = act ? line : 0;
+  int f, r;
+  long eo, wo;
+  batch_line<N>(b, act ? line : 0, f, r, eo, wo);
   Cx<T>* lb = lds + g * C::SPAN;
   Cx<T> v[C::E];
-  load_real_line<T, N>(in + lsafe * N, v, t, act);
+  load_real_line<T, N>(static_cast<const T*>(b.ext[r]) + eo, v, t, act);
   fft<T, C::L, -1, 1, SY_WAVE, false>(v, t, stw, 2, lb);
-  r2c_finish<T, N, false>(v, t, lb, stw, out + lsafe * C::L, act);
+  r2c_finish<T, N, false>(v, t, lb, stw, ws + wo, act);
 }
 
-// lines of field f = line / lines_per_field are multiplied by m_z^rpow[f]
+// field f of the batch is multiplied by m_z^zp.r[f] before the transform
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_zc2r(const Cx<T>* in, T* out, long nlines, ZPow zp,
+__global__ __launch_bounds__(256) void k_zc2r(const Cx<T>* ws, Batch b, long nlines, ZPow zp,
                                               const Cx<T>* __restrict__ tw) {
   using C = LineCfg<N>;
   __shared__ Cx<T> lds[C::G * C::SPAN];
@@ -141,14 +158,15 @@ __global__ __launch_bounds__(256) void k_zc2r(const Cx<T>* in, T* out, long nlin
   const int t = threadIdx.x % C::TPL, g = threadIdx.x / C::TPL;
   const long line = (long)blockIdx.x * C::G + g;
   const bool act = line < nlines;
-  const long lsafe = act ? line : 0;
-  const int f = (int)(lsafe / zp.lines_per_field);
-  const int r = f < ZPOW_MAX ? zp.r[f] : 0;
+  int f, r;
+  long eo, wo;
+  batch_line<N>(b, act ? line : 0, f, r, eo, wo);
+  const int rp = f < ZPOW_MAX ? zp.r[f] : 0;
   Cx<T>* lb = lds + g * C::SPAN;
   Cx<T> v[C::E];
-  c2r_prepare<T, N, false>(in + lsafe * C::L, r, v, t, lb, stw, act);
+  c2r_prepare<T, N, false>(ws + wo, rp, v, t, lb, stw, act);
   fft<T, C::L, +1, 1, SY_WAVE, false>(v, t, stw, 2, lb);
-  Cx<T>* d2 = reinterpret_cast<Cx<T>*>(out + lsafe * N);
+  Cx<T>* d2 = reinterpret_cast<Cx<T>*>(static_cast<T*>(const_cast<void*>(b.ext[r])) + eo);
   if (act) {
 #pragma unroll
     for (int sl = 0; sl < C::E; ++sl) d2[slot_elem<C::L, C::E, C::RLI>(t, sl)] = v[sl];
@@ -348,17 +366,18 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_colfft(Cx<T>* __r
 }
 
 // Fused y pass of the inverse chain: output o is the inverse y-FFT of input
-// field src[o] multiplied by m_y^pw[o].  Persistent over column tiles (the
+// field src[o] multiplied by m_y^pw[o], over `nplanes` x planes (the planes of
+// several realisations follow each other).  Persistent over column tiles (the
 // grid holds the resident blocks): the column of the next source, or of the
 // next tile's first source, is loaded while the current outputs transform.
 template <typename T, int N, int WW>
 __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T>* __restrict__ in, long fsi,
                                                                   Cx<T>* __restrict__ out, long fso, YOp op,
-                                                                  const Cx<T>* __restrict__ tw) {
+                                                                  long nplanes, const Cx<T>* __restrict__ tw) {
   using C = ColCfg<T, N, WW>;
   constexpr int M = N / 2;
   constexpr int BPP = (M + C::W - 1) / C::W;
-  constexpr long NTILES = (long)N * BPP;
+  const long NTILES = nplanes * BPP;
   __shared__ Cx<T> lds[2 * C::L * C::W];  // two exchange buffers
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
@@ -416,8 +435,10 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
 // Displacement x pass (the hot path's two x passes).  One input column X
 // (z and y already forward-transformed), forward x-FFT, then one gather per
 // mode of the radial table(s) (built in FP64, stored rounded once to T), then the outputs
-// with their k_x powers (integer mode numbers, exact in T).  Persistent over
-// column tiles; the next tile's input column loads while this one transforms.
+// with their k_x powers (integer mode numbers, exact in T).  Realisation
+// blockIdx.y (one after the other, in the input and in every output field);
+// persistent over its column tiles; the next tile's input column loads while
+// this one transforms.
 //   MODE 0: tab = interleaved (PHI, PSI1) per |m|^2;
 //           out 0..2: U_p = F_x^-1[-m_x^p PHI X], out 3..4: V_p = F_x^-1[i m_x^p PSI1 X]
 //   MODE 1: tab = PSI2;  out 0..1: Q_p = F_x^-1[-i m_x^p PSI2 X]
@@ -430,12 +451,15 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
   using C = ColCfg<T, N, WW>;
   constexpr int M = N / 2;
   constexpr long NCOL = (long)N * M;
+  constexpr long FIELD = (long)N * NCOL;  // one realisation's half spectrum
   __shared__ Cx<T> lds[2 * C::L * C::W];  // two exchange buffers
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
   int phase = 0;
   const int c = threadIdx.x % C::W, t = threadIdx.x / C::W;
   constexpr long NTILES = (NCOL + C::W - 1) / C::W;
+  in += blockIdx.y * FIELD;               // realisation blockIdx.y
+  out += blockIdx.y * FIELD;
   Cx<T> va[C::E], vb[C::E], y[C::E], pf[C::E];
   auto load = [&](long tile) {
     const long col = tile * C::W + c;
@@ -625,43 +649,66 @@ int default_width(int prec, int n, int kind) {
   return col_width(prec, n, 1);
 }
 
-// Grid for a persistent kernel: the blocks that can be resident at once
-// (occupancy of this kernel x compute units), at most one per tile.
-static long resident_grid(const void* kernel, int block, long ntiles) {
+// Blocks of a persistent kernel that can be resident at once (occupancy of
+// this kernel x compute units); the grid is this, at most one per tile.
+static long resident_blocks(const void* kernel, int block) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-    return ntiles;
+    return 1L << 30;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, 0) != hipSuccess || per < 1) per = 1;
-  const long g = (long)per * cus;
-  return g < ntiles ? g : ntiles;
+  return (long)per * cus;
 }
+static inline long min_l(long a, long b) { return a < b ? a : b; }
 
 static inline size_t esize(int prec) { return prec == PREC_F32 ? 4 : 8; }
 static inline bool pow2n(int n) { return n >= 8 && n <= 512 && (n & (n - 1)) == 0; }
 
+Batch batch_one(const void* ext, int nf, long ext_fstride, long ws_fstride) {
+  Batch b;
+  std::memset(&b, 0, sizeof(b));
+  b.nf = nf;
+  b.nr = 1;
+  b.ext_fstride = ext_fstride;
+  b.ws_fstride = ws_fstride;
+  b.ws_rstride = 0;
+  b.ext[0] = ext;
+  return b;
+}
+
+// Checks a Batch against its buffers: every caller buffer holds its nf
+// fields of n^3 reals at ext_fstride, the workspace every (f, r) field.
+static bool batch_ok(int prec, int n, const Batch& b, size_t ext_cap, const void* ws, size_t ws_cap) {
+  if (b.nf < 1 || b.nf > 16 || b.nr < 1 || b.nr > BATCH_MAX || !ws) return false;
+  if (b.ext_fstride < 0 || b.ws_fstride < 0 || b.ws_rstride < 0) return false;
+  const size_t es = esize(prec), n3 = (size_t)n * n * n, nnm = (size_t)n * n * (n / 2);
+  if (((size_t)(b.nf - 1) * b.ext_fstride + n3) * es > ext_cap) return false;
+  const size_t end = (size_t)(b.nf - 1) * b.ws_fstride + (size_t)(b.nr - 1) * b.ws_rstride + nnm;
+  if (end * 2 * es > ws_cap) return false;
+  for (int r = 0; r < b.nr; ++r)
+    if (!b.ext[r]) return false;
+  return true;
+}
+
 template <typename T, int N>
-static hipError_t zr2c_t(const void* in, void* out, long nlines, const void* tw, hipStream_t s) {
+static hipError_t zr2c_t(const Batch& b, void* ws, const void* tw, hipStream_t s) {
   using C = LineCfg<N>;
+  const long nlines = (long)b.nf * b.nr * N * N;
   const long blocks = (nlines + C::G - 1) / C::G;
-  hipLaunchKernelGGL((k_zr2c<T, N>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const T*)in, (Cx<T>*)out, nlines,
+  hipLaunchKernelGGL((k_zr2c<T, N>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, b, (Cx<T>*)ws, nlines,
                      (const Cx<T>*)tw);
   return hipGetLastError();
 }
-hipError_t launch_zr2c(int prec, int n, const void* in, size_t in_cap, void* out, size_t out_cap, long nlines,
-                       const void* tw, hipStream_t s) {
-  if (nlines <= 0) return hipSuccess;
-  if (!pow2n(n) || !in || !out || !tw) return hipErrorInvalidValue;
-  const size_t line = (size_t)n * esize(prec);  // n reals = n/2 complex
-  if ((size_t)nlines * line > in_cap || (size_t)nlines * line > out_cap) return hipErrorInvalidValue;
-#define CALL(NN) return prec == PREC_F32 ? zr2c_t<float, NN>(in, out, nlines, tw, s) : zr2c_t<double, NN>(in, out, nlines, tw, s)
+hipError_t launch_zr2c(int prec, int n, const Batch& b, size_t ext_cap, void* ws, size_t ws_cap, const void* tw,
+                       hipStream_t s) {
+  if (!pow2n(n) || !tw || !batch_ok(prec, n, b, ext_cap, ws, ws_cap)) return hipErrorInvalidValue;
+#define CALL(NN) return prec == PREC_F32 ? zr2c_t<float, NN>(b, ws, tw, s) : zr2c_t<double, NN>(b, ws, tw, s)
   LPT2_SWITCH_N(n, CALL)
 #undef CALL
   return hipErrorInvalidValue;
 }
 
-ZPow zpow_none(long lines_per_field) {
+ZPow zpow_none() {
   ZPow z;
-  z.lines_per_field = lines_per_field > 0 ? lines_per_field : 1;
   for (int i = 0; i < ZPOW_MAX; ++i) {
     z.r[i] = 0;
     z.fmap[i] = i;
@@ -669,7 +716,6 @@ ZPow zpow_none(long lines_per_field) {
   return z;
 }
 static bool zpow_ok(const ZPow& zp) {
-  if (zp.lines_per_field <= 0) return false;
   for (int i = 0; i < ZPOW_MAX; ++i)
     if (zp.r[i] < 0 || zp.r[i] > 2) return false;
   for (int i = 0; i < 6; ++i)
@@ -678,20 +724,18 @@ static bool zpow_ok(const ZPow& zp) {
 }
 
 template <typename T, int N>
-static hipError_t zc2r_t(const void* in, void* out, long nlines, const ZPow& zp, const void* tw, hipStream_t s) {
+static hipError_t zc2r_t(const void* ws, const Batch& b, const ZPow& zp, const void* tw, hipStream_t s) {
   using C = LineCfg<N>;
+  const long nlines = (long)b.nf * b.nr * N * N;
   const long blocks = (nlines + C::G - 1) / C::G;
-  hipLaunchKernelGGL((k_zc2r<T, N>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in, (T*)out, nlines,
-                     zp, (const Cx<T>*)tw);
+  hipLaunchKernelGGL((k_zc2r<T, N>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)ws, b, nlines, zp,
+                     (const Cx<T>*)tw);
   return hipGetLastError();
 }
-hipError_t launch_zc2r(int prec, int n, const void* in, size_t in_cap, void* out, size_t out_cap, long nlines,
-                       const ZPow& zp, const void* tw, hipStream_t s) {
-  if (nlines <= 0) return hipSuccess;
-  if (!pow2n(n) || !in || !out || !tw || !zpow_ok(zp)) return hipErrorInvalidValue;
-  const size_t line = (size_t)n * esize(prec);
-  if ((size_t)nlines * line > in_cap || (size_t)nlines * line > out_cap) return hipErrorInvalidValue;
-#define CALL(NN) return prec == PREC_F32 ? zc2r_t<float, NN>(in, out, nlines, zp, tw, s) : zc2r_t<double, NN>(in, out, nlines, zp, tw, s)
+hipError_t launch_zc2r(int prec, int n, const void* ws, size_t ws_cap, const Batch& b, size_t ext_cap, const ZPow& zp,
+                       const void* tw, hipStream_t s) {
+  if (!pow2n(n) || !tw || !zpow_ok(zp) || !batch_ok(prec, n, b, ext_cap, ws, ws_cap)) return hipErrorInvalidValue;
+#define CALL(NN) return prec == PREC_F32 ? zc2r_t<float, NN>(ws, b, zp, tw, s) : zc2r_t<double, NN>(ws, b, zp, tw, s)
   LPT2_SWITCH_N(n, CALL)
 #undef CALL
   return hipErrorInvalidValue;
@@ -782,75 +826,79 @@ hipError_t launch_colfft(int prec, int n, int dir, void* data, size_t cap, long 
 }
 
 template <typename T, int N, int WW>
-static hipError_t ycombo_w(const void* in, long fsi, void* out, long fso, const YOp& op, const void* tw,
+static hipError_t ycombo_w(int nr, const void* in, long fsi, void* out, long fso, const YOp& op, const void* tw,
                            hipStream_t s) {
   using C = ColCfg<T, N, WW>;
   constexpr int M = N / 2;
-  static const long blocks =
-      resident_grid(reinterpret_cast<const void*>(&k_ycombo<T, N, WW>), C::BLOCK, (long)N * ((M + C::W - 1) / C::W));
+  static const long res = resident_blocks(reinterpret_cast<const void*>(&k_ycombo<T, N, WW>), C::BLOCK);
+  const long nplanes = (long)nr * N;
+  const long blocks = min_l(res, nplanes * ((M + C::W - 1) / C::W));
   hipLaunchKernelGGL((k_ycombo<T, N, WW>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in, fsi,
-                     (Cx<T>*)out, fso, op, (const Cx<T>*)tw);
+                     (Cx<T>*)out, fso, op, nplanes, (const Cx<T>*)tw);
   return hipGetLastError();
 }
 template <typename T, int N>
-static hipError_t ycombo_t(int w, const void* in, long fsi, void* out, long fso, const YOp& op, const void* tw,
+static hipError_t ycombo_t(int w, int nr, const void* in, long fsi, void* out, long fso, const YOp& op, const void* tw,
                            hipStream_t s) {
-  if (w == col_w<T>(N, 0)) return ycombo_w<T, N, col_w<T>(N, 0)>(in, fsi, out, fso, op, tw, s);
-  if (w == col_w<T>(N, 1)) return ycombo_w<T, N, col_w<T>(N, 1)>(in, fsi, out, fso, op, tw, s);
-  if (w == col_w<T>(N, 2)) return ycombo_w<T, N, col_w<T>(N, 2)>(in, fsi, out, fso, op, tw, s);
+  if (w == col_w<T>(N, 0)) return ycombo_w<T, N, col_w<T>(N, 0)>(nr, in, fsi, out, fso, op, tw, s);
+  if (w == col_w<T>(N, 1)) return ycombo_w<T, N, col_w<T>(N, 1)>(nr, in, fsi, out, fso, op, tw, s);
+  if (w == col_w<T>(N, 2)) return ycombo_w<T, N, col_w<T>(N, 2)>(nr, in, fsi, out, fso, op, tw, s);
   return hipErrorInvalidValue;
 }
-hipError_t launch_ycombo(int prec, int n, const void* in, size_t in_cap, long in_fstride, void* out, size_t out_cap,
-                         long out_fstride, const YOp& op, const void* tw, hipStream_t s, int w) {
+hipError_t launch_ycombo(int prec, int n, int nr, const void* in, size_t in_cap, long in_fstride, void* out,
+                         size_t out_cap, long out_fstride, const YOp& op, const void* tw, hipStream_t s, int w) {
   if (w == 0) w = default_width(prec, n, KIND_MULTI);
-  if (op.nin < 1 || op.nout < 1 || op.nin > YOP_MAX || op.nout > YOP_MAX) return hipErrorInvalidValue;
+  if (op.nin < 1 || op.nout < 1 || op.nin > YOP_MAX || op.nout > YOP_MAX || nr < 1) return hipErrorInvalidValue;
   if (!pow2n(n) || !in || !out || !tw || in_fstride < 0 || out_fstride < 0) return hipErrorInvalidValue;
   for (int o = 0; o < op.nout; ++o)
     if (op.src[o] < 0 || op.src[o] >= op.nin || op.pw[o] < 0 || op.pw[o] > 2) return hipErrorInvalidValue;
-  const size_t cb = 2 * esize(prec), field = (size_t)n * n * (n / 2);
+  const size_t cb = 2 * esize(prec), field = (size_t)nr * n * n * (n / 2);
   if (((size_t)(op.nin - 1) * in_fstride + field) * cb > in_cap) return hipErrorInvalidValue;
   if (((size_t)(op.nout - 1) * out_fstride + field) * cb > out_cap) return hipErrorInvalidValue;
-#define CALL(NN) return prec == PREC_F32 ? ycombo_t<float, NN>(w, in, in_fstride, out, out_fstride, op, tw, s) : ycombo_t<double, NN>(w, in, in_fstride, out, out_fstride, op, tw, s)
+#define CALL(NN) return prec == PREC_F32 ? ycombo_t<float, NN>(w, nr, in, in_fstride, out, out_fstride, op, tw, s) : ycombo_t<double, NN>(w, nr, in, in_fstride, out, out_fstride, op, tw, s)
   LPT2_SWITCH_N(n, CALL)
 #undef CALL
   return hipErrorInvalidValue;
 }
 
 template <typename T, int N, int WW>
-static hipError_t xdisp_w(int mode, const void* in, void* out, long fso, const void* tab, const void* tw,
+static hipError_t xdisp_w(int nr, int mode, const void* in, void* out, long fso, const void* tab, const void* tw,
                           hipStream_t s) {
   using C = ColCfg<T, N, WW>;
-  const long ntiles = ((long)N * (N / 2) + C::W - 1) / C::W;
-  static const long b0 = resident_grid(reinterpret_cast<const void*>(&k_xdisp<T, N, WW, 0>), C::BLOCK, ntiles);
-  static const long b1 = resident_grid(reinterpret_cast<const void*>(&k_xdisp<T, N, WW, 1>), C::BLOCK, ntiles);
-  const long blocks = mode == 0 ? b0 : b1;
+  const long ntiles = ((long)N * (N / 2) + C::W - 1) / C::W;  // per realisation
+  static const long r0 = resident_blocks(reinterpret_cast<const void*>(&k_xdisp<T, N, WW, 0>), C::BLOCK);
+  static const long r1 = resident_blocks(reinterpret_cast<const void*>(&k_xdisp<T, N, WW, 1>), C::BLOCK);
+  // the resident blocks shared out over the realisations (grid.y)
+  const long per = ((mode == 0 ? r0 : r1) + nr - 1) / nr;
+  const dim3 grid((unsigned)min_l(per, ntiles), (unsigned)nr);
   if (mode == 0)
-    hipLaunchKernelGGL((k_xdisp<T, N, WW, 0>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in,
-                       (Cx<T>*)out, fso, (const T*)tab, (const Cx<T>*)tw);
+    hipLaunchKernelGGL((k_xdisp<T, N, WW, 0>), grid, dim3(C::BLOCK), 0, s, (const Cx<T>*)in, (Cx<T>*)out, fso,
+                       (const T*)tab, (const Cx<T>*)tw);
   else
-    hipLaunchKernelGGL((k_xdisp<T, N, WW, 1>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in,
-                       (Cx<T>*)out, fso, (const T*)tab, (const Cx<T>*)tw);
+    hipLaunchKernelGGL((k_xdisp<T, N, WW, 1>), grid, dim3(C::BLOCK), 0, s, (const Cx<T>*)in, (Cx<T>*)out, fso,
+                       (const T*)tab, (const Cx<T>*)tw);
   return hipGetLastError();
 }
 template <typename T, int N>
-static hipError_t xdisp_t(int w, int mode, const void* in, void* out, long fso, const void* tab, const void* tw,
-                          hipStream_t s) {
-  if (w == col_w<T>(N, 0)) return xdisp_w<T, N, col_w<T>(N, 0)>(mode, in, out, fso, tab, tw, s);
-  if (w == col_w<T>(N, 1)) return xdisp_w<T, N, col_w<T>(N, 1)>(mode, in, out, fso, tab, tw, s);
-  if (w == col_w<T>(N, 2)) return xdisp_w<T, N, col_w<T>(N, 2)>(mode, in, out, fso, tab, tw, s);
+static hipError_t xdisp_t(int w, int nr, int mode, const void* in, void* out, long fso, const void* tab,
+                          const void* tw, hipStream_t s) {
+  if (w == col_w<T>(N, 0)) return xdisp_w<T, N, col_w<T>(N, 0)>(nr, mode, in, out, fso, tab, tw, s);
+  if (w == col_w<T>(N, 1)) return xdisp_w<T, N, col_w<T>(N, 1)>(nr, mode, in, out, fso, tab, tw, s);
+  if (w == col_w<T>(N, 2)) return xdisp_w<T, N, col_w<T>(N, 2)>(nr, mode, in, out, fso, tab, tw, s);
   return hipErrorInvalidValue;
 }
-hipError_t launch_xdisp(int prec, int n, int mode, const void* in, size_t in_cap, void* out, size_t out_cap,
+hipError_t launch_xdisp(int prec, int n, int nr, int mode, const void* in, size_t in_cap, void* out, size_t out_cap,
                         long out_fstride, const void* tab, size_t tab_cap, const void* tw, hipStream_t s, int w) {
   if (w == 0) w = default_width(prec, n, KIND_MULTI);
-  if (!pow2n(n) || !in || !out || !tab || !tw || out_fstride < 0 || (mode != 0 && mode != 1))
+  if (!pow2n(n) || !in || !out || !tab || !tw || out_fstride < 0 || (mode != 0 && mode != 1) || nr < 1)
     return hipErrorInvalidValue;
-  const size_t cb = 2 * esize(prec), field = (size_t)n * n * (n / 2);
+  const size_t cb = 2 * esize(prec), field = (size_t)nr * n * n * (n / 2);
   const int nout = mode == 0 ? 5 : 2;
   if (field * cb > in_cap || ((size_t)(nout - 1) * out_fstride + field) * cb > out_cap) return hipErrorInvalidValue;
+  if (nr > 65535) return hipErrorInvalidValue;  // grid.y
   const size_t n2cnt = 3 * (size_t)(n / 2) * (n / 2) + 1;
   if (n2cnt * esize(prec) * (mode == 0 ? 2 : 1) > tab_cap) return hipErrorInvalidValue;
-#define CALL(NN) return prec == PREC_F32 ? xdisp_t<float, NN>(w, mode, in, out, out_fstride, tab, tw, s) : xdisp_t<double, NN>(w, mode, in, out, out_fstride, tab, tw, s)
+#define CALL(NN) return prec == PREC_F32 ? xdisp_t<float, NN>(w, nr, mode, in, out, out_fstride, tab, tw, s) : xdisp_t<double, NN>(w, nr, mode, in, out, out_fstride, tab, tw, s)
   LPT2_SWITCH_N(n, CALL)
 #undef CALL
   return hipErrorInvalidValue;

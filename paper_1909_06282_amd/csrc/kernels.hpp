@@ -31,16 +31,29 @@ struct XOp {
   const double* tables[16];
 };
 
-// Per-field power of m_z applied to a half-spectrum line before the inverse
-// z transform: field f = line / lines_per_field is multiplied by m_z^r[f]
-// (r in {0, 1, 2}).
+// Per-field power of m_z applied to a half-spectrum line before an inverse
+// z transform: field f is multiplied by m_z^r[f] (r in {0, 1, 2}).
 constexpr int ZPOW_MAX = 16;
 struct ZPow {
-  long lines_per_field;
   int r[ZPOW_MAX];
   int fmap[ZPOW_MAX];   // source pass: logical field f is stored at field fmap[f]
 };
-ZPow zpow_none(long lines_per_field);
+ZPow zpow_none();
+
+// Realisation addressing of the z passes that read or write caller buffers:
+// nf fields of nr realisations (nr <= BATCH_MAX), n^2 lines per field.
+//   caller side: line l of field f of realisation r at ext[r] + f*ext_fstride + l*n   (reals)
+//   workspace:   at ws + f*ws_fstride + r*ws_rstride + l*(n/2)                        (complex)
+// Every ext[r] must hold ext_cap bytes.  Lines are numbered f-major, then r, then l.
+constexpr int BATCH_MAX = 64;
+struct Batch {
+  int nf, nr;
+  long ext_fstride;
+  long ws_fstride, ws_rstride;
+  const void* ext[BATCH_MAX];
+};
+// one realisation whose nf fields sit at ext + f*ext_fstride (reals); workspace fields at ws_fstride
+Batch batch_one(const void* ext, int nf, long ext_fstride, long ws_fstride);
 
 // Fused inverse y pass: output o = F^-1_y[ m_y^pw[o] * input src[o] ]
 // (outputs grouped by source field).
@@ -50,11 +63,12 @@ struct YOp {
   int src[YOP_MAX], pw[YOP_MAX];
 };
 
-// z axis (contiguous): nlines lines of n reals <-> n/2 complex
-hipError_t launch_zr2c(int prec, int n, const void* in, size_t in_cap, void* out, size_t out_cap, long nlines,
+// z axis (contiguous): real lines of n values <-> n/2 complex modes
+hipError_t launch_zr2c(int prec, int n, const Batch& b, size_t ext_cap, void* ws, size_t ws_cap, const void* tw,
+                       hipStream_t s);
+// (field f multiplied by m_z^zp.r[f] before the transform)
+hipError_t launch_zc2r(int prec, int n, const void* ws, size_t ws_cap, const Batch& b, size_t ext_cap, const ZPow& zp,
                        const void* tw, hipStream_t s);
-hipError_t launch_zc2r(int prec, int n, const void* in, size_t in_cap, void* out, size_t out_cap, long nlines,
-                       const ZPow& zp, const void* tw, hipStream_t s);
 // strided complex column FFT in place: nplanes planes of ncols columns,
 // element (row, col) of plane p at data + p*plane_stride + row*rowstride + col
 // w: columns per block, one of col_width(n, 0..2); 0 picks default_width
@@ -63,13 +77,16 @@ hipError_t launch_colfft(int prec, int n, int dir, void* data, size_t cap, long 
 enum { KIND_COL = 0, KIND_MULTI = 1 };
 int col_width(int prec, int n, int i);       // the three tile widths offered for (precision, grid size)
 int default_width(int prec, int n, int kind);
-// fused inverse y pass over the n planes x n/2 columns of each field
-hipError_t launch_ycombo(int prec, int n, const void* in, size_t in_cap, long in_fstride, void* out, size_t out_cap,
-                         long out_fstride, const YOp& op, const void* tw, hipStream_t s, int w = 0);
+// fused inverse y pass over the nr*n planes x n/2 columns of each field
+// (nr realisations stored one after the other inside every field slot)
+hipError_t launch_ycombo(int prec, int n, int nr, const void* in, size_t in_cap, long in_fstride, void* out,
+                         size_t out_cap, long out_fstride, const YOp& op, const void* tw, hipStream_t s, int w = 0);
 // displacement x pass: mode 0 (tab = interleaved PHI, PSI1 per |m|^2; five
 // outputs U0,U1,U2,V0,V1) or mode 1 (tab = PSI2; outputs Q0,Q1).  The table
 // is in the working precision (pair: 2 values per |m|^2); tab_cap in bytes.
-hipError_t launch_xdisp(int prec, int n, int mode, const void* in, size_t in_cap, void* out, size_t out_cap,
+// nr realisations one after the other (n^2 (n/2) complex each) in the input
+// and in every output field.
+hipError_t launch_xdisp(int prec, int n, int nr, int mode, const void* in, size_t in_cap, void* out, size_t out_cap,
                         long out_fstride, const void* tab, size_t tab_cap, const void* tw, hipStream_t s, int w = 0);
 // fused x pass over the n*(n/2) columns of each field
 hipError_t launch_xpass(int prec, int n, const void* in, size_t in_cap, long in_fstride, void* out, size_t out_cap,

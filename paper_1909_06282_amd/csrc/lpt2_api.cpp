@@ -3,6 +3,7 @@
 // each entry point, and per-kernel event timing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -36,8 +37,20 @@ struct Grid {
   double amp = 0.0, lkmin = 0.0, lkmax = 0.0;
   void* tw = nullptr;
   int tiles[3] = {0, 0, 0};  // columns per block: y/x single passes, fused y pass, fused x pass (0 = default)
+  int rfirst = 0;            // index of this grid's first realisation
+  int bsub = 1;              // realisations transformed side by side (a batch)
+  size_t ws_off = 0;         // this grid's batch region in the workspace
+  hipStream_t st = nullptr;  // own stream when the plan holds several grids
+  hipEvent_t join = nullptr;
   std::vector<Tables> tables;
   std::vector<Tables> gr_tables;  // GR growth at a (for S_GR and the triangle ratios)
+};
+
+struct GraphEntry {
+  double a;
+  std::vector<const void*> ptrs;  // noise, psi1, psi2 of every realisation
+  hipGraph_t graph;
+  hipGraphExec_t exec;
 };
 
 struct ProfEntry {
@@ -65,11 +78,17 @@ struct lpt2_plan_s {
   struct Pending { int idx; hipEvent_t a, b; };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
+  hipEvent_t fork = nullptr;        // several grids: their streams wait on this
+  bool graph_mode = false;
+  bool capturing = false;            // no per-launch events inside a capture
+  hipStream_t cap_stream = nullptr;  // stream the graphs are captured on
+  std::vector<GraphEntry> graphs;
 };
 
 namespace {
 
 constexpr int WS_FIELDS = 16;  // half-spectrum-sized slots in the workspace
+constexpr size_t BATCH_WS_BUDGET = (size_t)16 << 30;  // workspace bytes a grid's batch may take
 
 lpt2_status fail(lpt2_plan_t p, lpt2_status st, const std::string& msg) {
   if (p)
@@ -150,9 +169,11 @@ lpt2_status validate(const lpt2_config& c, std::string& why) {
 double cos_deg(double th) { return th == 90.0 ? 0.0 : std::cos(th * kPi / 180.0); }
 
 // ---- profiling ---------------------------------------------------------------
+// one entry per (launch site, bytes per launch): the same site on grids or
+// batches of different sizes is counted separately
 int prof_slot(lpt2_plan_t p, const char* name, double bytes) {
   for (size_t i = 0; i < p->prof_tab.size(); ++i)
-    if (p->prof_tab[i].name == name) return (int)i;
+    if (p->prof_tab[i].name == name && p->prof_tab[i].bytes == bytes) return (int)i;
   p->prof_tab.push_back({name, 0, 0.0, bytes});
   return (int)p->prof_tab.size() - 1;
 }
@@ -182,7 +203,8 @@ template <class F>
 lpt2_status run(lpt2_plan_t p, hipStream_t s, const char* name, double bytes, F&& launch) {
   hipEvent_t a = nullptr, b = nullptr;
   int idx = -1;
-  if (p->prof) {
+  const bool prof = p->prof && !p->capturing;
+  if (prof) {
     idx = prof_slot(p, name, bytes);
     a = take_event(p);
     b = take_event(p);
@@ -190,7 +212,7 @@ lpt2_status run(lpt2_plan_t p, hipStream_t s, const char* name, double bytes, F&
   }
   hipError_t e = launch();
   if (e != hipSuccess) return hip_fail(p, e, name);
-  if (p->prof && a && b) {
+  if (prof && a && b) {
     (void)hipEventRecord(b, s);
     p->pending.push_back({idx, a, b});
     p->prof_tab[idx].launches++;
@@ -202,6 +224,15 @@ lpt2_status run(lpt2_plan_t p, hipStream_t s, const char* name, double bytes, F&
     lpt2_status st_ = run(p, s, name, (double)(bytes), [&]() { return (expr); }); \
     if (st_ != LPT2_OK) return st_;                                         \
   } while (0)
+
+// Destroys the captured graphs (the caller has synchronised the device).
+void drop_graphs(lpt2_plan_t p) {
+  for (auto& ge : p->graphs) {
+    if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
+    if (ge.graph) (void)hipGraphDestroy(ge.graph);
+  }
+  p->graphs.clear();
+}
 
 // ---- growth tables -------------------------------------------------------------
 lpt2_status build_tables(lpt2_plan_t p, Grid& g, double a, bool gr, hipStream_t s, Tables& out) {
@@ -276,6 +307,7 @@ lpt2_status get_tables(lpt2_plan_t p, Grid& g, double a, bool gr, hipStream_t s,
   if (cache.size() >= 32) {  // drop the oldest entry once its users are done
     (void)hipStreamSynchronize(s);
     (void)hipDeviceSynchronize();
+    drop_graphs(p);           // captured graphs may read the tables
     (void)hipFree(cache.front().d1n);
     if (cache.front().radial) (void)hipFree(cache.front().radial);
     cache.erase(cache.begin());
@@ -317,31 +349,50 @@ void op_tables(XOp& op, const Grid& g, const Tables* t) {
 
 // ---- pipeline pieces ------------------------------------------------------------
 // Workspace slot i holds one half spectrum (n*n*(n/2) complex = one real
-// n^3 field).  Every launch passes the capacity of each buffer: for a slot,
-// the bytes to the end of the workspace; for a caller's field, its
-// documented size.
+// n^3 field) of each of the nr realisations of a batch, one after the other.
+// Every launch passes the capacity of each buffer: for a slot, the bytes to
+// the end of the workspace; for a caller's field, its documented size.
 struct Ctx {
   lpt2_plan_t p;
   Grid& g;
   hipStream_t s;
-  size_t cs;  // bytes per complex
-  char* slot(int i) const { return p->ws + (size_t)i * g.nnm * cs; }
-  size_t cap(const void* ptr) const {  // bytes from a workspace pointer to the workspace end
+  size_t cs;         // bytes per complex
+  char* base;        // slot 0
+  int nr = 1;        // realisations per slot
+  char* end = nullptr;  // end of the workspace region this context may use (nullptr: the workspace end)
+  long sstride() const { return (long)nr * g.nnm; }  // complex from one slot to the next
+  char* slot(int i) const { return base + (size_t)i * sstride() * cs; }
+  size_t cap(const void* ptr) const {  // bytes from a workspace pointer to the region end
     const char* q = (const char*)ptr;
-    return (q >= p->ws && q < p->ws + p->ws_bytes) ? (size_t)(p->ws + p->ws_bytes - q) : 0;
+    const char* e = end ? end : p->ws + p->ws_bytes;
+    return (q >= p->ws && q < e) ? (size_t)(e - q) : 0;
   }
   size_t field() const { return (size_t)g.n3 * p->es; }  // bytes of one real field
+  double fields(double k) const { return k * (double)field() * nr; }  // bytes of k fields of the batch
+  // nf caller fields per realisation (n^3 reals apart) <-> nf slots from `ws`
+  Batch batch(const void* const* ext, int nf) const {
+    Batch b;
+    std::memset(&b, 0, sizeof(b));
+    b.nf = nf;
+    b.nr = nr;
+    b.ext_fstride = g.n3;
+    b.ws_fstride = sstride();
+    b.ws_rstride = g.nnm;
+    for (int r = 0; r < nr; ++r) b.ext[r] = ext[r];
+    return b;
+  }
+  Batch one(const void* ext, int nf) const { return batch_one(ext, nf, g.n3, sstride()); }
 };
 
-// forward z and y passes of `nf` real fields at `in` into spectral slots
-lpt2_status fwd_zy(Ctx& c, const char* nz, const char* ny, const void* in, size_t in_cap, void* out, int nf) {
+// forward z and y passes of `b` (caller fields, ext_cap bytes each) into spectral slots at `out`
+lpt2_status fwd_zy(Ctx& c, const char* nz, const char* ny, const Batch& b, size_t ext_cap, void* out) {
   lpt2_plan_t p = c.p;
   hipStream_t s = c.s;
   Grid& g = c.g;
-  const double fb = (double)c.field();
-  RUN(nz, 2.0 * fb * nf, launch_zr2c(p->prec, g.n, in, in_cap, out, c.cap(out), (long)nf * g.n * g.n, g.tw, s));
-  RUN(ny, 2.0 * fb * nf,
-      launch_colfft(p->prec, g.n, -1, out, c.cap(out), (long)nf * g.n, g.n * g.m, (int)g.m, g.m, g.tw, s,
+  const double by = 2.0 * (double)c.field() * b.nf * b.nr;
+  RUN(nz, by, launch_zr2c(p->prec, g.n, b, ext_cap, out, c.cap(out), g.tw, s));
+  RUN(ny, by,
+      launch_colfft(p->prec, g.n, -1, out, c.cap(out), (long)b.nf * b.nr * g.n, g.n * g.m, (int)g.m, g.m, g.tw, s,
                     g.tiles[0]));
   return LPT2_OK;
 }
@@ -349,9 +400,8 @@ lpt2_status inv_y(Ctx& c, const char* ny, void* data, int nf) {
   lpt2_plan_t p = c.p;
   hipStream_t s = c.s;
   Grid& g = c.g;
-  const double fb = (double)c.field();
-  RUN(ny, 2.0 * fb * nf,
-      launch_colfft(p->prec, g.n, +1, data, c.cap(data), (long)nf * g.n, g.n * g.m, (int)g.m, g.m, g.tw, s,
+  RUN(ny, c.fields(2.0 * nf),
+      launch_colfft(p->prec, g.n, +1, data, c.cap(data), (long)nf * c.nr * g.n, g.n * g.m, (int)g.m, g.m, g.tw, s,
                     g.tiles[0]));
   return LPT2_OK;
 }
@@ -359,19 +409,19 @@ lpt2_status fwd_y(Ctx& c, const char* ny, void* data, int nf) {
   lpt2_plan_t p = c.p;
   hipStream_t s = c.s;
   Grid& g = c.g;
-  const double fb = (double)c.field();
-  RUN(ny, 2.0 * fb * nf,
-      launch_colfft(p->prec, g.n, -1, data, c.cap(data), (long)nf * g.n, g.n * g.m, (int)g.m, g.m, g.tw, s,
+  RUN(ny, c.fields(2.0 * nf),
+      launch_colfft(p->prec, g.n, -1, data, c.cap(data), (long)nf * c.nr * g.n, g.n * g.m, (int)g.m, g.m, g.tw, s,
                     g.tiles[0]));
   return LPT2_OK;
 }
+// generic x pass (one realisation per Ctx)
 lpt2_status xp(Ctx& c, const char* name, const void* in, void* out, const XOp& op) {
   lpt2_plan_t p = c.p;
   hipStream_t s = c.s;
   Grid& g = c.g;
-  const double fb = (double)c.field();
-  const long fst = g.nnm;
-  RUN(name, fb * (op.nin + op.nout),
+  if (c.nr != 1) return fail(p, LPT2_EINVAL, "generic x pass takes one realisation");
+  const long fst = c.sstride();
+  RUN(name, c.fields(op.nin + op.nout),
       launch_xpass(p->prec, g.n, in, c.cap(in), fst, out, c.cap(out), fst, op, g.n2cnt, g.tw, s));
   return LPT2_OK;
 }
@@ -383,42 +433,48 @@ lpt2_status xdisp(Ctx& c, const char* name, int mode, const void* in, void* out,
   const int row = mode == 0 ? (f32 ? TAB_PAIR32 : TAB_PAIR64) : (f32 ? TAB_PSI2_32 : TAB_PSI2);
   const void* tab = t->radial + (size_t)row * g.n2cnt;
   const size_t cap = sizeof(double) * (size_t)(TAB_ROWS - row) * g.n2cnt;
-  RUN(name, (double)c.field() * (mode == 0 ? 6 : 3),
-      launch_xdisp(p->prec, g.n, mode, in, c.cap(in), out, c.cap(out), g.nnm, tab, cap, g.tw, s, g.tiles[2]));
+  RUN(name, c.fields(mode == 0 ? 6 : 3),
+      launch_xdisp(p->prec, g.n, c.nr, mode, in, c.cap(in), out, c.cap(out), c.sstride(), tab, cap, g.tw, s,
+                   g.tiles[2]));
   return LPT2_OK;
 }
-lpt2_status z_c2r(Ctx& c, const char* name, const void* in, void* out, size_t out_cap, int nf,
-                  const int* rpow = nullptr) {
+// inverse z pass of nf slots at `in` into the fields of `b` (m_z powers rpow per field)
+lpt2_status z_c2r(Ctx& c, const char* name, const void* in, const Batch& b, size_t ext_cap, const int* rpow = nullptr) {
   lpt2_plan_t p = c.p;
   hipStream_t s = c.s;
   Grid& g = c.g;
-  const double fb = (double)c.field();
-  ZPow zp = zpow_none((long)g.n * g.n);
+  ZPow zp = zpow_none();
   if (rpow)
-    for (int f = 0; f < nf && f < ZPOW_MAX; ++f) zp.r[f] = rpow[f];
-  RUN(name, 2.0 * fb * nf,
-      launch_zc2r(p->prec, g.n, in, c.cap(in), out, out_cap, (long)nf * g.n * g.n, zp, g.tw, s));
+    for (int f = 0; f < b.nf && f < ZPOW_MAX; ++f) zp.r[f] = rpow[f];
+  RUN(name, 2.0 * (double)c.field() * b.nf * b.nr,
+      launch_zc2r(p->prec, g.n, in, c.cap(in), b, ext_cap, zp, g.tw, s));
   return LPT2_OK;
+}
+// in-place inverse z pass of nf workspace slots (one realisation)
+lpt2_status z_c2r_ws(Ctx& c, const char* name, void* data, int nf) {
+  return z_c2r(c, name, data, c.one(data, nf), c.cap(data));
 }
 lpt2_status z_source(Ctx& c, const void* phi, void* sk, const int* rpow = nullptr, const int* fmap = nullptr) {
   lpt2_plan_t p = c.p;
   hipStream_t s = c.s;
   Grid& g = c.g;
-  ZPow zp = zpow_none((long)g.n * g.n);
+  ZPow zp = zpow_none();
   for (int f = 0; f < 6; ++f) {
     if (rpow) zp.r[f] = rpow[f];
     if (fmap) zp.fmap[f] = fmap[f];
   }
-  RUN("z_fused_source", (double)c.field() * 7.0,
-      launch_zsource(p->prec, g.n, phi, c.cap(phi), g.nnm, zp, sk, c.cap(sk), (long)g.n * g.n, g.tw, s));
+  RUN("z_fused_source", c.fields(7.0),
+      launch_zsource(p->prec, g.n, phi, c.cap(phi), c.sstride(), zp, sk, c.cap(sk), (long)c.nr * g.n * g.n, g.tw,
+                     s));
   return LPT2_OK;
 }
 lpt2_status ycombo(Ctx& c, const char* name, const void* in, void* out, const YOp& op) {
   lpt2_plan_t p = c.p;
   hipStream_t s = c.s;
   Grid& g = c.g;
-  RUN(name, (double)c.field() * (op.nin + op.nout),
-      launch_ycombo(p->prec, g.n, in, c.cap(in), g.nnm, out, c.cap(out), g.nnm, op, g.tw, s, g.tiles[1]));
+  RUN(name, c.fields(op.nin + op.nout),
+      launch_ycombo(p->prec, g.n, c.nr, in, c.cap(in), c.sstride(), out, c.cap(out), c.sstride(), op, g.tw, s,
+                    g.tiles[1]));
   return LPT2_OK;
 }
 YOp yop(int nin, int nout, const int* src, const int* pw) {
@@ -438,16 +494,15 @@ YOp yop(int nin, int nout, const int* src, const int* pw) {
     if (st_ != LPT2_OK) return st_; \
   } while (0)
 
-// psi1, psi2 of one realisation (see lpt2_displace).  The k-space factors
-// are split by axis: the radial part (and k_x) is applied in the x pass,
-// k_y in the y pass and k_z in the z pass, so five x-transforms carry the
-// nine fields:  U_p = F_x^-1[-k_x^p A/k^2 X] (p = 0,1,2),
+// psi1, psi2 of the c.nr realisations of a batch (see lpt2_displace).  The
+// k-space factors are split by axis: the radial part (and k_x) is applied in
+// the x pass, k_y in the y pass and k_z in the z pass, so five x-transforms
+// carry the nine fields:  U_p = F_x^-1[-k_x^p A/k^2 X] (p = 0,1,2),
 // V_p = F_x^-1[i k_x^p A D1/k^2 X] (p = 0,1), and e.g.
 // phi_yz = F_z^-1[k_z F_y^-1[k_y U_0]] (integer mode numbers throughout;
 // the (2 pi/L) factors sit in the radial tables).  Slots 0..14.
-lpt2_status displace_one(Ctx& c, const Tables* t, const void* noise, void* psi1, void* psi2) {
-  Grid& g = c.g;
-  CHK(fwd_zy(c, "z_r2c_noise", "y_fwd_noise", noise, c.field(), c.slot(0), 1));
+lpt2_status displace_batch(Ctx& c, const Tables* t, const void* const* noise, void* const* psi1, void* const* psi2) {
+  CHK(fwd_zy(c, "z_r2c_noise", "y_fwd_noise", c.batch(noise, 1), c.field(), c.slot(0)));
   CHK(xdisp(c, "x_fused_psi1_phi", 0, c.slot(0), c.slot(1), t));
   // outputs (inputs U0,U1,U2,V0,V1 = 0..4, grouped so each is read once):
   // psi1 x,y,z, then phi stored as xx,xy,xz,yy,zz,yz
@@ -455,7 +510,7 @@ lpt2_status displace_one(Ctx& c, const Tables* t, const void* noise, void* psi1,
   const int pw9[9] = {0, 1, 0, 0, 1, 0, 2, 0, 1};
   CHK(ycombo(c, "y_inv_psi1_phi", c.slot(1), c.slot(6), yop(5, 9, src9, pw9)));
   const int rz1[3] = {0, 0, 1};
-  CHK(z_c2r(c, "z_c2r_psi1", c.slot(6), psi1, 3 * c.field(), 3, rz1));
+  CHK(z_c2r(c, "z_c2r_psi1", c.slot(6), c.batch(psi1, 3), 3 * c.field(), rz1));
   // source pass order xx,yy,zz,xy,xz,yz: m_z powers and storage positions
   const int rzs[6] = {0, 0, 2, 0, 1, 1};
   const int fms[6] = {0, 3, 4, 1, 2, 5};
@@ -465,7 +520,7 @@ lpt2_status displace_one(Ctx& c, const Tables* t, const void* noise, void* psi1,
   const int src3[3] = {1, 0, 0};
   const int pw3[3] = {0, 1, 0};
   CHK(ycombo(c, "y_inv_psi2", c.slot(1), c.slot(3), yop(2, 3, src3, pw3)));
-  CHK(z_c2r(c, "z_c2r_psi2", c.slot(3), psi2, 3 * c.field(), 3, rz1));
+  CHK(z_c2r(c, "z_c2r_psi2", c.slot(3), c.batch(psi2, 3), 3 * c.field(), rz1));
   return LPT2_OK;
 }
 
@@ -473,7 +528,7 @@ lpt2_status displace_one(Ctx& c, const Tables* t, const void* noise, void* psi1,
 // `dst` (uses slots 0..6 and 10)
 lpt2_status source_k(Ctx& c, const Tables* t, const void* noise, int dst, double scale) {
   Grid& g = c.g;
-  CHK(fwd_zy(c, "z_r2c_noise", "y_fwd_noise", noise, c.field(), c.slot(0), 1));
+  CHK(fwd_zy(c, "z_r2c_noise", "y_fwd_noise", c.one(noise, 1), c.field(), c.slot(0)));
   XOp op = op_blank(1, 6, 1);
   op_tables(op, g, t);
   for (int q = 0; q < 6; ++q) op_set(op, q, MUL_REAL, PI_[q], PJ_[q], TAB_PHI, -1.0);
@@ -495,7 +550,7 @@ lpt2_status mg_source_k(Ctx& c, const Tables* t, const void* noise) {
   const long cnt = g.n3;
   const bool fr = g.c.gravity == GRAV_FR;
   if (c.cap(c.slot(10)) < 2 * c.field()) return fail(p, LPT2_EINVAL, "workspace too small");
-  CHK(fwd_zy(c, "z_r2c_noise", "y_fwd_noise", noise, c.field(), c.slot(0), 1));
+  CHK(fwd_zy(c, "z_r2c_noise", "y_fwd_noise", c.one(noise, 1), c.field(), c.slot(0)));
   // accumulators (real fields stored in spectral slots): R1 5, R2 6, tr->R3 7, R5 8, chi^2 9
   for (int i = 5; i <= 9; ++i) RUN("fill", 0.0, launch_fill(p->prec, c.slot(i), cnt, 0.0, s));
   for (int q = 0; q < 6; ++q) {
@@ -507,7 +562,7 @@ lpt2_status mg_source_k(Ctx& c, const Tables* t, const void* noise) {
     if (fr) op_set(op, 2, MUL_REAL, i, j, TAB_R4, -1.0);
     CHK(xp(c, "x_mg_phi", c.slot(0), c.slot(1), op));
     CHK(inv_y(c, "y_inv_mg", c.slot(1), op.nout));
-    CHK(z_c2r(c, "z_c2r_mg", c.slot(1), c.slot(1), c.cap(c.slot(1)), op.nout));  // in place
+    CHK(z_c2r_ws(c, "z_c2r_mg", c.slot(1), op.nout));  // in place
     const double w = (i == j) ? 1.0 : 2.0;
     RUN("mg_pair", 0.0,
         launch_mg_pair(p->prec, cnt, w, c.slot(1), c.slot(2), fr ? c.slot(3) : nullptr, c.slot(5), c.slot(6),
@@ -522,7 +577,7 @@ lpt2_status mg_source_k(Ctx& c, const Tables* t, const void* noise) {
       op_set(op, 1, MUL_PI, j, -1, TAB_R6, 1.0);
       CHK(xp(c, "x_mg_grad", c.slot(0), c.slot(1), op));
       CHK(inv_y(c, "y_inv_mg", c.slot(1), 2));
-      CHK(z_c2r(c, "z_c2r_mg", c.slot(1), c.slot(1), c.cap(c.slot(1)), 2));
+      CHK(z_c2r_ws(c, "z_c2r_mg", c.slot(1), 2));
       RUN("mg_dot", 0.0, launch_mg_dot(p->prec, cnt, c.slot(1), c.slot(2), c.slot(8), s));
     }
     XOp op = op_blank(1, 1, 1);
@@ -530,11 +585,11 @@ lpt2_status mg_source_k(Ctx& c, const Tables* t, const void* noise) {
     op_set(op, 0, MUL_REAL, -1, -1, TAB_R3, 1.0);
     CHK(xp(c, "x_mg_chi", c.slot(0), c.slot(9), op));
     CHK(inv_y(c, "y_inv_mg", c.slot(9), 1));
-    CHK(z_c2r(c, "z_c2r_mg", c.slot(9), c.slot(9), c.cap(c.slot(9)), 1));
+    CHK(z_c2r_ws(c, "z_c2r_mg", c.slot(9), 1));
     RUN("square", 0.0, launch_square(p->prec, cnt, c.slot(9), s));
   }
   const int nr = fr ? 5 : 3;
-  CHK(fwd_zy(c, "z_r2c_mg", "y_fwd_mg", c.slot(5), c.cap(c.slot(5)), c.slot(5), nr));
+  CHK(fwd_zy(c, "z_r2c_mg", "y_fwd_mg", c.one(c.slot(5), nr), c.cap(c.slot(5)), c.slot(5)));
   const double G = four_pi_g_rho(g.c, t->a);
   XOp op = op_blank(nr, 1, 0);
   op_tables(op, g, t);
@@ -556,15 +611,15 @@ lpt2_status backward_one(Ctx& c, const Tables* t, const void* noise, const void*
   Grid& g = c.g;
   const double fb = (double)c.field();
   // S_bar = F^-1[ sum_i conj(-i m_i PSI2) F psi2_bar_i ]
-  CHK(fwd_zy(c, "z_r2c_gpsi2", "y_fwd_gpsi2", g2, 3 * c.field(), c.slot(1), 3));
+  CHK(fwd_zy(c, "z_r2c_gpsi2", "y_fwd_gpsi2", c.one(g2, 3), 3 * c.field(), c.slot(1)));
   XOp o1 = op_blank(3, 1, 1);
   op_tables(o1, g, t);
   for (int i = 0; i < 3; ++i) op_set(o1, i, MUL_PI, i, -1, TAB_PSI2, 1.0);
   CHK(xp(c, "x_adj_psi2", c.slot(1), c.slot(10), o1));
   CHK(inv_y(c, "y_inv_sbar", c.slot(10), 1));
-  CHK(z_c2r(c, "z_c2r_sbar", c.slot(10), c.slot(10), c.cap(c.slot(10)), 1));
+  CHK(z_c2r_ws(c, "z_c2r_sbar", c.slot(10), 1));
   // phi_,ij recomputed from the noise
-  CHK(fwd_zy(c, "z_r2c_noise", "y_fwd_noise", noise, c.field(), c.slot(0), 1));
+  CHK(fwd_zy(c, "z_r2c_noise", "y_fwd_noise", c.one(noise, 1), c.field(), c.slot(0)));
   XOp o2 = op_blank(1, 6, 1);
   op_tables(o2, g, t);
   for (int q = 0; q < 6; ++q) op_set(o2, q, MUL_REAL, PI_[q], PJ_[q], TAB_PHI, -1.0);
@@ -574,7 +629,7 @@ lpt2_status backward_one(Ctx& c, const Tables* t, const void* noise, const void*
       launch_zprodrule(p->prec, g.n, c.slot(1), c.cap(c.slot(1)), g.nnm, c.slot(10), c.cap(c.slot(10)), c.slot(1),
                        c.cap(c.slot(1)), g.nnm, (long)g.n * g.n, g.tw, s));
   RUN("z_r2c_gpsi1", 2.0 * fb * 3,
-      launch_zr2c(p->prec, g.n, g1, 3 * c.field(), c.slot(7), c.cap(c.slot(7)), 3L * g.n * g.n, g.tw, s));
+      launch_zr2c(p->prec, g.n, c.one(g1, 3), 3 * c.field(), c.slot(7), c.cap(c.slot(7)), g.tw, s));
   CHK(fwd_y(c, "y_fwd_adj", c.slot(1), 9));
   XOp o3 = op_blank(9, 1, 1);
   op_tables(o3, g, t);
@@ -582,13 +637,227 @@ lpt2_status backward_one(Ctx& c, const Tables* t, const void* noise, const void*
   for (int i = 0; i < 3; ++i) op_set(o3, 6 + i, MUL_MI, i, -1, TAB_PSI1, 1.0);
   CHK(xp(c, "x_adj_noise", c.slot(1), c.slot(0), o3));
   CHK(inv_y(c, "y_inv_gnoise", c.slot(0), 1));
-  CHK(z_c2r(c, "z_c2r_gnoise", c.slot(0), gw, c.field(), 1));
+  CHK(z_c2r(c, "z_c2r_gnoise", c.slot(0), c.one(gw, 1), c.field()));
   return LPT2_OK;
 }
 
 lpt2_status check_a(lpt2_plan_t p, double a) {
   if (!(a > 0.0) || !std::isfinite(a)) return fail(p, LPT2_EINVAL, "scale factor a must be > 0");
   return LPT2_OK;
+}
+
+// ---- batched displacement: grids, batches, streams, graphs -------------------------
+// growth tables of every grid at a (built on s if missing)
+lpt2_status tables_for(lpt2_plan_t p, double a, hipStream_t s, std::vector<Tables*>& out) {
+  out.assign(p->grids.size(), nullptr);
+  for (size_t i = 0; i < p->grids.size(); ++i) CHK(get_tables(p, p->grids[i], a, false, s, &out[i]));
+  return LPT2_OK;
+}
+
+// every realisation of grid gi, bsub at a time, on `st`
+lpt2_status run_grid(lpt2_plan_t p, int gi, const Tables* t, const void* const* noise, void* const* psi1,
+                     void* const* psi2, hipStream_t st) {
+  Grid& g = p->grids[gi];
+  char* base = p->ws + g.ws_off;
+  char* end = base + (size_t)WS_FIELDS * g.bsub * g.n3 * p->es;
+  for (int r0 = 0; r0 < g.count; r0 += g.bsub) {
+    Ctx c{p, g, st, 2 * p->es, base, std::min(g.bsub, g.count - r0), end};
+    const int r = g.rfirst + r0;
+    CHK(displace_batch(c, t, noise + r, psi1 + r, psi2 + r));
+  }
+  return LPT2_OK;
+}
+
+// all grids; with several grids, each on its own stream between a fork on s
+// and a join back into s (the same sequence records as graph branches)
+lpt2_status run_displace(lpt2_plan_t p, const std::vector<Tables*>& tabs, const void* const* noise,
+                         void* const* psi1, void* const* psi2, hipStream_t s) {
+  if (p->grids.size() == 1) return run_grid(p, 0, tabs[0], noise, psi1, psi2, s);
+  hipError_t e = hipEventRecord(p->fork, s);
+  if (e != hipSuccess) return hip_fail(p, e, "fork");
+  lpt2_status st = LPT2_OK;
+  for (size_t i = 0; i < p->grids.size(); ++i) {
+    Grid& g = p->grids[i];
+    e = hipStreamWaitEvent(g.st, p->fork, 0);
+    if (e != hipSuccess && st == LPT2_OK) st = hip_fail(p, e, "fork wait");
+    if (st == LPT2_OK) st = run_grid(p, (int)i, tabs[i], noise, psi1, psi2, g.st);
+    e = hipEventRecord(g.join, g.st);  // joined also after an error, so a capture can end
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, g.join, 0);
+    if (e != hipSuccess && st == LPT2_OK) st = hip_fail(p, e, "join");
+  }
+  return st;
+}
+
+// the captured graph of the whole batch for (a, these buffers)
+lpt2_status graph_for(lpt2_plan_t p, double a, const std::vector<Tables*>& tabs, const void* const* noise,
+                      void* const* psi1, void* const* psi2, GraphEntry** out) {
+  const size_t nr = p->rgrid.size();
+  std::vector<const void*> key(3 * nr);
+  for (size_t r = 0; r < nr; ++r) {
+    key[3 * r] = noise[r];
+    key[3 * r + 1] = psi1[r];
+    key[3 * r + 2] = psi2[r];
+  }
+  for (auto& ge : p->graphs)
+    if (ge.a == a && ge.ptrs == key) {
+      *out = &ge;
+      return LPT2_OK;
+    }
+  if (p->graphs.size() >= 8) {  // keep a few; the oldest may still run
+    (void)hipDeviceSynchronize();
+    (void)hipGraphExecDestroy(p->graphs.front().exec);
+    (void)hipGraphDestroy(p->graphs.front().graph);
+    p->graphs.erase(p->graphs.begin());
+  }
+  hipStream_t cs = p->cap_stream;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return hip_fail(p, e, "begin capture");
+  p->capturing = true;
+  lpt2_status st = run_displace(p, tabs, noise, psi1, psi2, cs);
+  p->capturing = false;
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs, &graph);
+  if (st != LPT2_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(p, e, "end capture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hip_fail(p, e, "graph instantiate");
+  }
+  p->graphs.push_back({a, key, graph, exec});
+  *out = &p->graphs.back();
+  return LPT2_OK;
+}
+
+lpt2_status set_tiles(lpt2_plan_t p, Grid& g, const int* tiles) {
+  for (int k = 0; k < 3; ++k) {
+    bool ok = tiles[k] == 0;
+    for (int i = 0; i < 3; ++i) ok = ok || tiles[k] == col_width(p->prec, g.n, i);
+    if (!ok) return fail(p, LPT2_EINVAL, "tile width " + std::to_string(tiles[k]) + " not offered for this grid");
+  }
+  bool same = true;
+  for (int k = 0; k < 3; ++k) same = same && g.tiles[k] == tiles[k];
+  if (same) return LPT2_OK;
+  (void)hipDeviceSynchronize();
+  drop_graphs(p);  // graphs hold the old launch shapes
+  for (int k = 0; k < 3; ++k) g.tiles[k] = tiles[k];
+  return LPT2_OK;
+}
+
+// ---- tile tuner ------------------------------------------------------------------
+// Times every combination of the offered tile widths (single y/x passes,
+// fused y pass, fused x pass) on the grid's own batch and keeps the fastest.
+// Results are cached in a text file, one line per (device, precision, n,
+// batch):  lpt2-tiles <arch> <fp32|fp64> <n> <batch> <col> <y> <x>
+std::string tune_key(lpt2_plan_t p, const Grid& g) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+  }
+  return arch + " " + (p->prec == PREC_F32 ? "fp32" : "fp64") + " " + std::to_string(g.n) + " " +
+         std::to_string(g.bsub);
+}
+
+bool tune_lookup(const char* path, const std::string& key, int* tiles) {
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    char arch[128], prec[16];
+    int n = 0, b = 0, t0 = 0, t1 = 0, t2 = 0;
+    if (std::sscanf(line, "lpt2-tiles %127s %15s %d %d %d %d %d", arch, prec, &n, &b, &t0, &t1, &t2) != 7) continue;
+    const std::string k = std::string(arch) + " " + prec + " " + std::to_string(n) + " " + std::to_string(b);
+    if (k == key) {  // the last matching line wins
+      tiles[0] = t0;
+      tiles[1] = t1;
+      tiles[2] = t2;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+// minimum over `reps` timed runs of grid gi (after one warm run)
+lpt2_status time_grid(lpt2_plan_t p, int gi, const Tables* t, const void* const* noise, void* const* psi1,
+                      void* const* psi2, hipStream_t s, int reps, float* best) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(p, e, "tuner events");
+  }
+  lpt2_status st = run_grid(p, gi, t, noise, psi1, psi2, s);
+  *best = 1e30f;
+  for (int i = 0; i < reps && st == LPT2_OK; ++i) {
+    (void)hipEventRecord(e0, s);
+    st = run_grid(p, gi, t, noise, psi1, psi2, s);
+    (void)hipEventRecord(e1, s);
+    float ms = 0.f;
+    if (st == LPT2_OK && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+      *best = std::min(*best, ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
+lpt2_status autotune(lpt2_plan_t p, const std::vector<Tables*>& tabs, const void* const* noise, void* const* psi1,
+                     void* const* psi2, const char* path, hipStream_t s) {
+  const bool prof = p->prof;
+  p->prof = false;
+  lpt2_status st = LPT2_OK;
+  std::string lines;
+  for (size_t gi = 0; gi < p->grids.size() && st == LPT2_OK; ++gi) {
+    Grid& g = p->grids[gi];
+    const std::string key = tune_key(p, g);
+    int tiles[3];
+    if (tune_lookup(path, key, tiles) && set_tiles(p, g, tiles) == LPT2_OK) continue;
+    int opt[3], nopt = 0;
+    for (int i = 0; i < 3; ++i) {
+      const int w = col_width(p->prec, g.n, i);
+      bool dup = false;
+      for (int j = 0; j < nopt; ++j) dup = dup || opt[j] == w;
+      if (!dup) opt[nopt++] = w;
+    }
+    float best = 1e30f;
+    int bt[3] = {0, 0, 0};
+    for (int i0 = 0; i0 < nopt && st == LPT2_OK; ++i0)
+      for (int i1 = 0; i1 < nopt && st == LPT2_OK; ++i1)
+        for (int i2 = 0; i2 < nopt && st == LPT2_OK; ++i2) {
+          const int tt[3] = {opt[i0], opt[i1], opt[i2]};
+          st = set_tiles(p, g, tt);
+          float ms = 0.f;
+          if (st == LPT2_OK) st = time_grid(p, (int)gi, tabs[gi], noise, psi1, psi2, s, 3, &ms);
+          if (st == LPT2_OK && ms < best) {
+            best = ms;
+            std::memcpy(bt, tt, sizeof(bt));
+          }
+        }
+    if (st == LPT2_OK) st = set_tiles(p, g, bt);
+    if (st == LPT2_OK)
+      lines += "lpt2-tiles " + key + " " + std::to_string(bt[0]) + " " + std::to_string(bt[1]) + " " +
+               std::to_string(bt[2]) + "\n";
+  }
+  p->prof = prof;
+  if (st == LPT2_OK && path && !lines.empty()) {
+    FILE* f = std::fopen(path, "a");
+    if (!f) return fail(p, LPT2_EINVAL, std::string("cannot append to tuning cache ") + path);
+    std::fputs(lines.c_str(), f);
+    std::fclose(f);
+  }
+  return st;
 }
 
 }  // namespace
@@ -695,26 +964,43 @@ lpt2_status lpt2_plan(const lpt2_config* cfgs, int n_cfgs, const int* counts, lp
       lpt2_destroy(p);
       return fail(nullptr, LPT2_EDEVICE, std::string("twiddle upload: ") + hipGetErrorString(e));
     }
-    if (const char* ev = std::getenv("LPT2_TILES")) {  // "col,y,x" widths, for tuning experiments
-      int a = 0, b = 0, cc = 0;
-      if (std::sscanf(ev, "%d,%d,%d", &a, &b, &cc) == 3) {
-        Grid& gb = p->grids.back();
-        const int want[3] = {a, b, cc};
-        for (int k = 0; k < 3; ++k)
-          for (int j = 0; j < 3; ++j)
-            if (col_width(p->prec, gb.n, j) == want[k]) gb.tiles[k] = want[k];
-      }
-    }
     for (int r = 0; r < p->grids.back().count; ++r) p->rgrid.push_back(i);
     const size_t fbytes = (size_t)g.n3 * p->es;
     if (fbytes > maxf) maxf = fbytes;
   }
-  p->ws_bytes = maxf * WS_FIELDS;
+  // batches: each grid gets a region of WS_FIELDS slots of bsub realisations
+  // (bsub as large as the batch budget and the per-launch pointer table allow)
+  size_t region_total = 0;
+  int rfirst = 0;
+  for (auto& g : p->grids) {
+    const size_t per = (size_t)WS_FIELDS * g.n3 * p->es;
+    size_t b = BATCH_WS_BUDGET / per;
+    if (b < 1) b = 1;
+    if (b > (size_t)BATCH_MAX) b = BATCH_MAX;
+    if (b > (size_t)g.count) b = g.count;
+    g.bsub = (int)b;
+    g.rfirst = rfirst;
+    rfirst += g.count;
+    g.ws_off = region_total;
+    region_total += per * b;
+  }
+  p->ws_bytes = std::max(maxf * WS_FIELDS, region_total);
   hipError_t e = hipMalloc((void**)&p->ws, p->ws_bytes);
   if (e != hipSuccess) {
     p->ws = nullptr;
     lpt2_destroy(p);
     return fail(nullptr, LPT2_ENOMEM, "workspace allocation failed");
+  }
+  if (p->grids.size() > 1) {  // grids of a plan run side by side on streams of their own
+    e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+    for (auto& g : p->grids) {
+      if (e == hipSuccess) e = hipStreamCreateWithFlags(&g.st, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&g.join, hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+      lpt2_destroy(p);
+      return fail(nullptr, LPT2_EDEVICE, std::string("stream setup: ") + hipGetErrorString(e));
+    }
   }
   e = hipMalloc((void**)&p->bin_partial, sizeof(double) * (BIN_BLOCKS * (size_t)BIN_MAXBINS * 4 + 4 * BIN_MAXBINS));
   if (e != hipSuccess) {
@@ -730,7 +1016,12 @@ lpt2_status lpt2_plan(const lpt2_config* cfgs, int n_cfgs, const int* counts, lp
 lpt2_status lpt2_destroy(lpt2_plan_t p) {
   if (!p) return LPT2_OK;
   (void)hipDeviceSynchronize();
+  drop_graphs(p);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->fork) (void)hipEventDestroy(p->fork);
   for (auto& g : p->grids) {
+    if (g.st) (void)hipStreamDestroy(g.st);
+    if (g.join) (void)hipEventDestroy(g.join);
     if (g.tw) (void)hipFree(g.tw);
     for (auto& t : g.tables) {
       (void)hipFree(t.d1n);
@@ -769,14 +1060,73 @@ lpt2_status lpt2_displace(lpt2_plan_t p, double a, const void* const* noise, voi
   for (int r = 0; r < nr; ++r)
     if (!noise[r] || !psi1[r] || !psi2[r]) return fail(p, LPT2_EINVAL, "null field pointer for realisation " + std::to_string(r));
   hipStream_t s = (hipStream_t)stream;
-  for (int r = 0; r < nr; ++r) {
-    Grid& g = p->grids[p->rgrid[r]];
-    Tables* t = nullptr;
-    CHK(get_tables(p, g, a, false, s, &t));
-    Ctx c{p, g, s, 2 * p->es};
-    CHK(displace_one(c, t, noise[r], psi1[r], psi2[r]));
-  }
+  std::vector<Tables*> tabs;
+  CHK(tables_for(p, a, s, tabs));
+  if (!p->graph_mode) return run_displace(p, tabs, noise, psi1, psi2, s);
+  GraphEntry* ge = nullptr;
+  CHK(graph_for(p, a, tabs, noise, psi1, psi2, &ge));
+  hipError_t e = hipGraphLaunch(ge->exec, s);
+  if (e != hipSuccess) return hip_fail(p, e, "graph launch");
   return LPT2_OK;
+}
+
+lpt2_status lpt2_set_graph(lpt2_plan_t p, int enable) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  if (enable && !p->cap_stream) {
+    hipError_t e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      p->cap_stream = nullptr;
+      return hip_fail(p, e, "capture stream");
+    }
+  }
+  if (!enable) {
+    (void)hipDeviceSynchronize();
+    drop_graphs(p);
+  }
+  p->graph_mode = enable != 0;
+  return LPT2_OK;
+}
+
+lpt2_status lpt2_get_tiles(lpt2_plan_t p, int grid, int* tiles) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  if (!tiles || grid < 0 || grid >= (int)p->grids.size()) return fail(p, LPT2_EINVAL, "bad grid index or NULL");
+  const Grid& g = p->grids[grid];
+  for (int k = 0; k < 3; ++k) tiles[k] = g.tiles[k] ? g.tiles[k] : default_width(p->prec, g.n, k == 0 ? KIND_COL : KIND_MULTI);
+  return LPT2_OK;
+}
+
+lpt2_status lpt2_tile_options(lpt2_plan_t p, int grid, int* widths) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  if (!widths || grid < 0 || grid >= (int)p->grids.size()) return fail(p, LPT2_EINVAL, "bad grid index or NULL");
+  for (int i = 0; i < 3; ++i) widths[i] = col_width(p->prec, p->grids[grid].n, i);
+  return LPT2_OK;
+}
+
+lpt2_status lpt2_set_tiles(lpt2_plan_t p, int grid, const int* tiles) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  if (!tiles || grid < 0 || grid >= (int)p->grids.size()) return fail(p, LPT2_EINVAL, "bad grid index or NULL");
+  CHK(set_tiles(p, p->grids[grid], tiles));
+  return LPT2_OK;
+}
+
+lpt2_status lpt2_autotune(lpt2_plan_t p, double a, const void* const* noise, void* const* psi1, void* const* psi2,
+                          const char* cache_path, void* stream) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  CHK(check_a(p, a));
+  if (!noise || !psi1 || !psi2) return fail(p, LPT2_EINVAL, "null pointer array");
+  const int nr = (int)p->rgrid.size();
+  for (int r = 0; r < nr; ++r)
+    if (!noise[r] || !psi1[r] || !psi2[r]) return fail(p, LPT2_EINVAL, "null field pointer for realisation " + std::to_string(r));
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<Tables*> tabs;
+  CHK(tables_for(p, a, s, tabs));
+  return autotune(p, tabs, noise, psi1, psi2, cache_path, s);
 }
 
 lpt2_status lpt2_source_spectrum(lpt2_plan_t p, double a, const void* noise, int nbins, int quantity, double* k_mean,
@@ -792,7 +1142,7 @@ lpt2_status lpt2_source_spectrum(lpt2_plan_t p, double a, const void* noise, int
   Grid& g = p->grids[p->rgrid[0]];
   Tables* t = nullptr;
   CHK(get_tables(p, g, a, false, s, &t));
-  Ctx c{p, g, s, 2 * p->es};
+  Ctx c{p, g, s, 2 * p->es, p->ws, 1};
   const double kf = 2.0 * kPi / g.cfg.box;
   if (quantity == LPT2_SPEC_POWER) {
     CHK(source_k(c, t, noise, 11, 1.0));
@@ -873,7 +1223,7 @@ lpt2_status lpt2_backward(lpt2_plan_t p, double a, const void* const* noise, con
     Grid& g = p->grids[p->rgrid[r]];
     Tables* t = nullptr;
     CHK(get_tables(p, g, a, false, s, &t));
-    Ctx c{p, g, s, 2 * p->es};
+    Ctx c{p, g, s, 2 * p->es, p->ws, 1};
     CHK(backward_one(c, t, noise[r], g_psi1[r], g_psi2[r], g_noise[r]));
   }
   return LPT2_OK;
@@ -927,10 +1277,10 @@ lpt2_status lpt2_fft3d(lpt2_plan_t p, int direction, const void* in, void* out, 
   if (direction != -1 && direction != 1) return fail(p, LPT2_EINVAL, "direction must be -1 or +1");
   hipStream_t s = (hipStream_t)stream;
   Grid& g = p->grids[p->rgrid[0]];
-  Ctx c{p, g, s, 2 * p->es};
+  Ctx c{p, g, s, 2 * p->es, p->ws, 1};
   const double fb = (double)g.n3 * p->es;
   if (direction < 0) {
-    RUN("z_r2c", 2.0 * fb, launch_zr2c(p->prec, g.n, in, c.field(), out, c.field(), (long)g.n * g.n, g.tw, s));
+    RUN("z_r2c", 2.0 * fb, launch_zr2c(p->prec, g.n, c.one(in, 1), c.field(), out, c.field(), g.tw, s));
     RUN("y_fwd", 2.0 * fb,
         launch_colfft(p->prec, g.n, -1, out, c.field(), g.n, g.n * g.m, (int)g.m, g.m, g.tw, s));
     RUN("x_fwd", 2.0 * fb,
@@ -941,7 +1291,7 @@ lpt2_status lpt2_fft3d(lpt2_plan_t p, int direction, const void* in, void* out, 
     RUN("x_inv", 2.0 * fb,
         launch_colfft(p->prec, g.n, +1, c.slot(0), c.cap(c.slot(0)), 1, 0, (int)(g.n * g.m), g.n * g.m, g.tw, s));
     CHK(inv_y(c, "y_inv", c.slot(0), 1));
-    CHK(z_c2r(c, "z_c2r", c.slot(0), out, c.field(), 1));
+    CHK(z_c2r(c, "z_c2r", c.slot(0), c.one(out, 1), c.field()));
   }
   return LPT2_OK;
 }

@@ -5,7 +5,9 @@
   * C3: 512^3, L = 1024, FP32 against the full FP64 oracle (one seed per
     (|f_R0|, z) corner is too slow for the oracle; seed 1 at F6 z = 0 and F4
     z = 1 are checked);
-  * C4: the 128^3 and 64^3 members of the batched mix, FP32;
+  * C4: the batched mix (64 x 128^3 + 32 x 64^3, seeds 100-195) as one
+    tuned, graph-captured FP32 plan: every realisation against the batched
+    FP64 GPU path, the first and last of each size against the oracle;
   * C5: the adjoint at 128^3: FP32 gradient against the FP64 oracle's
     autograd gradient, and the FP64 GPU gradient against central finite
     differences (eps = 1e-3) on 64 cells.
@@ -81,10 +83,57 @@ def test_c3_fp32_displacements(fr0, z):
     _parity("fp32", 1.0 / (1.0 + z), 1, 1e-5, fr0_abs=fr0, **C3)
 
 
-@pytest.mark.parametrize("n,box,seed", [(128, 256.0, 100), (64, 128.0, 164)])
-def test_c4_members_fp32(n, box, seed):
-    print(f"C4 member n={n}", flush=True)
-    _parity("fp32", 1.0, seed, 1e-5, n=n, box=box, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1")
+C4 = [dict(n=128, box=256.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1"),
+      dict(n=64, box=128.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1")]
+C4_COUNTS = [64, 32]          # seeds 100..163 (128^3), 164..195 (64^3)
+
+
+def _c4_plan(prec):
+    from paper_1909_06282_amd import Plan
+    cfgs = [gpu_config(precision=prec, **c) for c in C4]
+    return Plan(cfgs, counts=C4_COUNTS), cfgs
+
+
+def test_c4_batched_graph_fp32_vs_fp64_and_oracle(tmp_path):
+    # the batched mix as bench.py runs it: one plan, tiles from the tuner,
+    # the whole batch as one captured graph
+    print("C4 batched 64x128^3 + 32x64^3", flush=True)
+    seeds = list(range(100, 196))
+    sizes = [128] * 64 + [64] * 32
+    w64 = [white_noise(n, s) for n, s in zip(sizes, seeds)]
+    plan32, cfgs32 = _c4_plan("fp32")
+    n32 = [to_dev(w, torch.float32) for w in w64]
+    o1 = [torch.empty((3, n, n, n), dtype=torch.float32, device="cuda") for n in sizes]
+    o2 = [torch.empty_like(x) for x in o1]
+    tiles = plan32.autotune(1.0, n32, o1, o2, cache_path=str(tmp_path / "tiles.txt"))
+    print(f"  tuned tiles {tiles}", flush=True)
+    plan32.set_graph(True)
+    for x in o1 + o2:
+        x.fill_(float("nan"))
+    plan32.displace(1.0, n32, o1, o2)
+    plan32.displace(1.0, n32, o1, o2)        # a replay of the captured graph
+    torch.cuda.synchronize()
+    plan64, cfgs64 = _c4_plan("fp64")
+    q1, q2 = plan64.displace(1.0, [to_dev(w, torch.float64) for w in w64])
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i in range(len(sizes)):          # every realisation: FP32 batch vs FP64 batch
+        t32 = o1[i].double() + o2[i].double()
+        t64 = q1[i] + q2[i]
+        err = float((t32 - t64).abs().max() / t64.abs().max())
+        e1 = float((o1[i].double() - q1[i]).abs().max() / q1[i].abs().max())
+        e2 = float((o2[i].double() - q2[i]).abs().max() / q2[i].abs().max())
+        worst = max(worst, err, e1, e2)
+        assert err < 1e-5 and e1 < 1e-5 and e2 < 1e-5, f"realisation {i} (seed {seeds[i]})"
+    print(f"  worst FP32 vs FP64 over 96 realisations {worst:.3e}", flush=True)
+    for i in (0, 63, 64, 95):            # first and last of each size against the oracle
+        cfg = cfgs64[0] if i < 64 else cfgs64[1]
+        m = oracle_model(cfg)
+        r1, r2 = fields.displace(w64[i], m, 1.0, growth.tables(m, 1.0))
+        e64 = max(normwise(q1[i], r1), normwise(q2[i], r2))
+        e32 = max(normwise(o1[i], r1), normwise(o2[i], r2), normwise(o1[i].double() + o2[i].double(), r1 + r2))
+        print(f"  realisation {i} n={cfg.n} seed {seeds[i]}: fp64 {e64:.3e} fp32 {e32:.3e}", flush=True)
+        assert e64 < 1e-12 and e32 < 1e-5
 
 
 def _c5_loss_pieces(prec):
