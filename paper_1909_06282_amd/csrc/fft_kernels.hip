@@ -206,6 +206,11 @@ __device__ __forceinline__ void c2r_prepare_regs(const Cx<T>* raw, int r, Cx<T>*
 // multiplied by m_z^zp.r[f] first), then
 // the forward R2C of the S line.  The line of field f+1 is loaded while
 // field f is transformed, so the load latency hides behind the transform.
+// The field loop is not unrolled: unrolled, the six transforms with the
+// prefetch in flight need ~240 VGPRs (two waves per SIMD) in FP32, rolled
+// ~170 (three), and measured 15% faster at n = 512.  In FP64 the prefetch
+// alone would leave one wave per SIMD, so FP64 loads each field in turn
+// (measured 35% faster at n = 512).
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_zsource(const Cx<T>* __restrict__ phi, long fstride, ZPow zp,
                                                  Cx<T>* __restrict__ sk, long nlines, const Cx<T>* __restrict__ tw) {
@@ -218,13 +223,14 @@ __global__ __launch_bounds__(256) void k_zsource(const Cx<T>* __restrict__ phi, 
   const bool act = line < nlines;
   const long lsafe = act ? line : 0;
   Cx<T>* lb = lds + g * C::SPAN;
+  constexpr bool PF = sizeof(T) == 4;  // prefetch the next field (FP32 only: FP64 runs out of VGPRs)
   Cx<T> a[C::E], s[C::E], v[C::E], raw[C::E], nxt[C::E];
   const Cx<T>* src = phi + lsafe * C::L;
 #pragma unroll
   for (int q = 0; q < C::E; ++q) raw[q] = act ? src[zp.fmap[0] * fstride + t + q * C::TPL] : zero<T>();
-#pragma unroll
+#pragma unroll 1
   for (int f = 0; f < 6; ++f) {
-    if (f < 5) {
+    if (PF && f < 5) {
 #pragma unroll
       for (int q = 0; q < C::E; ++q) nxt[q] = act ? src[zp.fmap[f + 1] * fstride + t + q * C::TPL] : zero<T>();
     }
@@ -246,8 +252,13 @@ __global__ __launch_bounds__(256) void k_zsource(const Cx<T>* __restrict__ phi, 
 #pragma unroll
       for (int i = 0; i < C::E; ++i) s[i] = mk(s[i].x - v[i].x * v[i].x, s[i].y - v[i].y * v[i].y);
     }
+    if (PF) {
 #pragma unroll
-    for (int q = 0; q < C::E; ++q) raw[q] = nxt[q];
+      for (int q = 0; q < C::E; ++q) raw[q] = nxt[q];
+    } else if (f < 5) {
+#pragma unroll
+      for (int q = 0; q < C::E; ++q) raw[q] = act ? src[zp.fmap[f + 1] * fstride + t + q * C::TPL] : zero<T>();
+    }
   }
   fft<T, C::L, -1, 1, SY_WAVE, true>(s, t, stw, 2, lb);
   r2c_finish<T, N>(s, t, lb, stw, sk + lsafe * C::L, act);
@@ -460,7 +471,10 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
   constexpr long NTILES = (NCOL + C::W - 1) / C::W;
   in += blockIdx.y * FIELD;               // realisation blockIdx.y
   out += blockIdx.y * FIELD;
-  Cx<T> va[C::E], vb[C::E], y[C::E], pf[C::E];
+  Cx<T> va[C::E], y[C::E], pf[C::E];
+  // radial factors per slot: MODE 0 the (PHI, PSI1) pair, MODE 1 PSI2 in .x
+  Cx<T> rf[MODE == 0 ? C::E : 1];
+  T rq[MODE == 0 ? 1 : C::E];
   auto load = [&](long tile) {
     const long col = tile * C::W + c;
     const bool a = col < NCOL;
@@ -479,35 +493,46 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
     const int my = iy < N / 2 ? iy : iy - N;
     const bool keep_y = iy != N / 2;
     const int n2yz = my * my + iz * iz;
+    // the radial factors of the modes this thread holds after the forward
+    // transform: gathered before it (latency hidden behind the transform), or
+    // after it where that measured faster (the two-output FP32 pass, whose
+    // early gathers compete with the next tile's prefetch)
+    auto gather = [&]() {
+  #pragma unroll
+      for (int sl = 0; sl < C::E; ++sl) {
+        const int ix = slot_elem<C::L, C::E, C::RLF>(t, sl);
+        const int mx = ix < N / 2 ? ix : ix - N;
+        const int n2 = mx * mx + n2yz;
+        const bool keep = keep_y && ix != N / 2 && n2 != 0;
+        if constexpr (MODE == 0)
+          rf[sl] = keep ? reinterpret_cast<const Cx<T>*>(tab)[n2] : zero<T>();
+        else
+          rq[sl] = keep ? tab[n2] : T(0);
+      }
+    };
+    constexpr bool EARLY = MODE == 0 || sizeof(T) == 8;
+    if (EARLY) gather();
   #pragma unroll
     for (int sl = 0; sl < C::E; ++sl) va[sl] = pf[sl];
     if (tile + gridDim.x < NTILES) load(tile + gridDim.x);  // next tile's column, in flight meanwhile
     fft<T, C::L, -1, C::W, SY_PING>(va, t, stw, 1, lds + c, C::L * C::W, &phase);
-  #pragma unroll
-    for (int sl = 0; sl < C::E; ++sl) {
-      const int ix = slot_elem<C::L, C::E, C::RLF>(t, sl);
-      const int mx = ix < N / 2 ? ix : ix - N;
-      const int n2 = mx * mx + n2yz;
-      const bool keep = keep_y && ix != N / 2 && n2 != 0;
-      if (MODE == 0) {
-        const Cx<T> r = keep ? reinterpret_cast<const Cx<T>*>(tab)[n2] : zero<T>();
-        vb[sl] = scale(va[sl], r.y);
-        va[sl] = scale(va[sl], r.x);
-      } else {
-        va[sl] = scale(va[sl], keep ? tab[n2] : T(0));
-      }
-    }
+    if (!EARLY) gather();
     constexpr int NOUT = MODE == 0 ? 5 : 2;
   #pragma unroll 1
     for (int o = 0; o < NOUT; ++o) {
-      // MODE 0: o < 3 -> -m_x^o * va ; o = 3, 4 -> i m_x^(o-3) * vb.  MODE 1: -i m_x^o * va
+      // MODE 0: o < 3 -> -m_x^o PHI X ; o = 3, 4 -> i m_x^(o-3) PSI1 X.  MODE 1: -i m_x^o PSI2 X
       const bool second = MODE == 0 && o >= 3;
       const int p = second ? o - 3 : o;
   #pragma unroll
       for (int sl = 0; sl < C::E; ++sl) {
         const int ix = slot_elem<C::L, C::E, C::RLF>(t, sl);
         const T f = mpow<T>(ix < N / 2 ? ix : ix - N, p);
-        const Cx<T> a = second ? vb[sl] : va[sl];
+        T r;
+        if constexpr (MODE == 0)
+          r = second ? rf[sl].y : rf[sl].x;
+        else
+          r = rq[sl];
+        const Cx<T> a = scale(va[sl], r);
         if (MODE == 0)
           y[sl] = second ? mk(-a.y * f, a.x * f) : mk(-a.x * f, -a.y * f);
         else
