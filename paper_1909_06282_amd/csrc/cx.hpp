@@ -36,4 +36,22 @@ __host__ __device__ __forceinline__ Cx<T> mul_si(Cx<T> a) {
 template <typename T>
 __host__ __device__ __forceinline__ Cx<T> zero() { return mk(T(0), T(0)); }
 
+// Streaming (non-temporal) global accesses: data that one pass touches once
+// goes through the caches without displacing what is reused (the radial
+// tables the x passes gather).
+template <typename T>
+__device__ __forceinline__ void st_nt(Cx<T>* p, Cx<T> v) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2 w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, reinterpret_cast<v2*>(p));
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> ld_nt(const Cx<T>* p) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 w = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return mk(w.x, w.y);
+}
+
 }  // namespace lpt2
