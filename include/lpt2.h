@@ -194,6 +194,32 @@ lpt2_status lpt2_source_spectrum(lpt2_plan_t plan, double a, const void* noise, 
 lpt2_status lpt2_triangle_ratio(lpt2_plan_t plan, double a, double ratio, double theta_deg,
                                 int winther, const double* k, int nk, double* out);
 
+/* Candidate triangles of the factorisation choice (Sec. 3, triangle
+ * comparison), in this order: T1 (k1 = k2, 90 deg), T2 (k1 = k2, 80 deg),
+ * k1 = k2 at 70 deg, equilateral (60 deg), squeezed (k1/k2 = 1e-3, 90 deg),
+ * k1 = 2 k2 at 80 and at 70 deg, and Winther's (D1(k)^2 in place of
+ * D1(k1) D1(k2), 90 deg).  lpt2_factorisation_candidate writes candidate
+ * i's name (static storage), k1/k2 ratio, angle and Winther flag (any
+ * pointer may be NULL); i out of range -> LPT2_EINVAL. */
+int         lpt2_factorisation_candidates(void);
+lpt2_status lpt2_factorisation_candidate(int i, const char** name, double* ratio,
+                                         double* theta_deg, int* winther);
+
+/* Factorisation choice (Sec. 3): the binned ratio S_MG/S_GR of realisation 0
+ * at a, as lpt2_source_spectrum with LPT2_SPEC_RATIO and nbins shells, is
+ * compared with each candidate's lpt2_triangle_ratio at the shell mean
+ * wavenumbers; the cost of a candidate is sum_shells count (mean - R)^2 over
+ * the populated shells with 0 < k_mean <= kcut (h/Mpc).  Writes the index of
+ * the cheapest candidate to *best and, if costs is not NULL, every cost to
+ * costs[0..lpt2_factorisation_candidates()).  apply != 0 sets the D2
+ * factorisation of realisation 0's configuration to the chosen candidate
+ * (its cached growth tables and captured graphs are dropped and rebuilt on
+ * the next call).  nbins in 1..512, kcut > 0; no populated shell below kcut
+ * -> LPT2_EINVAL.  Synchronises. */
+lpt2_status lpt2_choose_factorisation(lpt2_plan_t plan, double a, const void* noise, int nbins,
+                                      double kcut, int apply, int* best, double* costs,
+                                      void* stream);
+
 /* Vector-Jacobian product of lpt2_displace: given g_psi1[r], g_psi2[r]
  * (device, [3][n][n][n]) returns g_noise[r] = d/dw sum(g_psi1 psi1 + g_psi2 psi2)
  * (device, [n][n][n]).  phi_,ij are recomputed from noise[r], not stored.

@@ -8,8 +8,8 @@ a k-dependent D2(k,a).  All steps run in hand-written HIP kernels behind the
 C ABI of include/lpt2.h (liblpt2.so, built in-tree by ``build.py``); this
 package only marshals arguments.
 """
-from .api import LPT2Config, Plan
+from .api import LPT2Config, Plan, factorisation_candidate
 from ._abi import LPT2Error, load as load_library
 from .autograd import Displace, PaintCIC
 
-__all__ = ["LPT2Config", "Plan", "LPT2Error", "load_library", "Displace", "PaintCIC"]
+__all__ = ["LPT2Config", "Plan", "LPT2Error", "load_library", "Displace", "PaintCIC", "factorisation_candidate"]

@@ -45,7 +45,8 @@ EXPORTS = [
     "lpt2_paint_cic_backward", "lpt2_growth_table", "lpt2_fft3d", "lpt2_profile_enable",
     "lpt2_profile_reset", "lpt2_profile_count", "lpt2_profile_get", "lpt2_workspace_bytes",
     "lpt2_strerror", "lpt2_last_error", "lpt2_set_graph", "lpt2_get_tiles", "lpt2_set_tiles",
-    "lpt2_tile_options", "lpt2_autotune",
+    "lpt2_tile_options", "lpt2_autotune", "lpt2_factorisation_candidates", "lpt2_factorisation_candidate",
+    "lpt2_choose_factorisation",
 ]
 
 _lib = None
@@ -87,6 +88,10 @@ def load() -> C.CDLL:
     L.lpt2_set_tiles.argtypes = [plan_t, C.c_int, ip]
     L.lpt2_tile_options.argtypes = [plan_t, C.c_int, ip]
     L.lpt2_autotune.argtypes = [plan_t, C.c_double, vpp, vpp, vpp, C.c_char_p, vp]
+    L.lpt2_factorisation_candidates.argtypes = []
+    L.lpt2_factorisation_candidates.restype = C.c_int
+    L.lpt2_factorisation_candidate.argtypes = [C.c_int, C.POINTER(C.c_char_p), dp, dp, ip]
+    L.lpt2_choose_factorisation.argtypes = [plan_t, C.c_double, vp, C.c_int, C.c_double, C.c_int, ip, dp, vp]
     L.lpt2_strerror.argtypes = [C.c_int]
     L.lpt2_strerror.restype = C.c_char_p
     L.lpt2_last_error.argtypes = [plan_t]
@@ -95,7 +100,7 @@ def load() -> C.CDLL:
                  "lpt2_triangle_ratio", "lpt2_backward", "lpt2_paint_cic", "lpt2_paint_cic_backward",
                  "lpt2_growth_table", "lpt2_fft3d", "lpt2_profile_enable", "lpt2_profile_reset",
                  "lpt2_profile_get", "lpt2_set_graph", "lpt2_get_tiles", "lpt2_set_tiles", "lpt2_tile_options",
-                 "lpt2_autotune"):
+                 "lpt2_autotune", "lpt2_factorisation_candidate", "lpt2_choose_factorisation"):
         getattr(L, name).restype = C.c_int
     L.lpt2_realisations.restype = C.c_int
     L.lpt2_profile_count.restype = C.c_int

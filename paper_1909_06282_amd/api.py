@@ -77,6 +77,14 @@ def _ptrs(ts: Sequence[torch.Tensor]):
     return arr
 
 
+def factorisation_candidate(i: int):
+    """(name, k1/k2 ratio, angle in degrees, winther) of candidate i."""
+    L = _abi.load()
+    nm, r, th, w = C.c_char_p(), C.c_double(), C.c_double(), C.c_int()
+    _abi.check(L.lpt2_factorisation_candidate(int(i), C.byref(nm), C.byref(r), C.byref(th), C.byref(w)))
+    return nm.value.decode(), r.value, th.value, bool(w.value)
+
+
 class Plan:
     """Owns an lpt2 plan (workspace, twiddles, growth-table cache)."""
 
@@ -209,6 +217,20 @@ class Plan:
                                                  k.ctypes.data_as(C.POINTER(C.c_double)), k.size,
                                                  out.ctypes.data_as(C.POINTER(C.c_double))), self.handle)
         return out
+
+    def choose_factorisation(self, a: float, noise: torch.Tensor, nbins: int = 128, kcut: float = 0.4,
+                             apply: bool = False, stream=None):
+        """lpt2_choose_factorisation -> (candidate name, {name: cost})."""
+        n = self.sizes[0]
+        self._check_field(noise, (n, n, n), "noise")
+        nc = self._lib.lpt2_factorisation_candidates()
+        costs = (C.c_double * nc)()
+        best = C.c_int()
+        _abi.check(self._lib.lpt2_choose_factorisation(self.handle, float(a), C.c_void_p(noise.data_ptr()),
+                                                       int(nbins), float(kcut), int(bool(apply)), C.byref(best),
+                                                       costs, _stream(stream)), self.handle)
+        names = [factorisation_candidate(i)[0] for i in range(nc)]
+        return names[best.value], dict(zip(names, list(costs)))
 
     def growth_table(self, a: float):
         nk = self.cfgs[0].nk_growth

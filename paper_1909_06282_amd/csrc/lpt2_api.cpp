@@ -1129,16 +1129,9 @@ lpt2_status lpt2_autotune(lpt2_plan_t p, double a, const void* const* noise, voi
   return autotune(p, tabs, noise, psi1, psi2, cache_path, s);
 }
 
-lpt2_status lpt2_source_spectrum(lpt2_plan_t p, double a, const void* noise, int nbins, int quantity, double* k_mean,
-                                 double* count, double* mean, double* std_dev, void* stream) {
-  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
-  Busy b(p);
-  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
-  CHK(check_a(p, a));
-  if (!noise || !k_mean || !count || !mean || !std_dev) return fail(p, LPT2_EINVAL, "null pointer");
-  if (nbins < 1 || nbins > BIN_MAXBINS) return fail(p, LPT2_EINVAL, "nbins must be in 1..512");
-  if (quantity != LPT2_SPEC_POWER && quantity != LPT2_SPEC_RATIO) return fail(p, LPT2_EINVAL, "unknown quantity");
-  hipStream_t s = (hipStream_t)stream;
+// bodies of lpt2_source_spectrum and lpt2_triangle_ratio (the caller holds the plan)
+static lpt2_status spectrum_impl(lpt2_plan_t p, double a, const void* noise, int nbins, int quantity, double* k_mean,
+                                 double* count, double* mean, double* std_dev, hipStream_t s) {
   Grid& g = p->grids[p->rgrid[0]];
   Tables* t = nullptr;
   CHK(get_tables(p, g, a, false, s, &t));
@@ -1178,14 +1171,8 @@ lpt2_status lpt2_source_spectrum(lpt2_plan_t p, double a, const void* noise, int
   return LPT2_OK;
 }
 
-lpt2_status lpt2_triangle_ratio(lpt2_plan_t p, double a, double ratio, double theta_deg, int winther, const double* k,
-                                int nk, double* out) {
-  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
-  Busy b(p);
-  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
-  CHK(check_a(p, a));
-  if (!k || !out || nk < 0) return fail(p, LPT2_EINVAL, "null pointer");
-  if (!(ratio > 0.0) || !(theta_deg > 0.0 && theta_deg < 180.0)) return fail(p, LPT2_EINVAL, "bad triangle");
+static lpt2_status triangle_impl(lpt2_plan_t p, double a, double ratio, double theta_deg, int winther,
+                                 const double* k, int nk, double* out) {
   Grid& g = p->grids[p->rgrid[0]];
   hipStream_t s = nullptr;
   Tables *t = nullptr, *tg = nullptr;
@@ -1203,6 +1190,112 @@ lpt2_status lpt2_triangle_ratio(lpt2_plan_t p, double a, double ratio, double th
     const double dd = winther ? std::pow(interp_lnk(d1.data(), n, g.lkmin, g.lkmax, k[i]), 2)
                               : interp_lnk(d1.data(), n, g.lkmin, g.lkmax, k1) * interp_lnk(d1.data(), n, g.lkmin, g.lkmax, k2);
     out[i] = dd * brace(g.c, k[i], k1, k2, cs, a) / (d1g[0] * d1g[0] * (1.0 - cs * cs));
+  }
+  return LPT2_OK;
+}
+
+lpt2_status lpt2_source_spectrum(lpt2_plan_t p, double a, const void* noise, int nbins, int quantity, double* k_mean,
+                                 double* count, double* mean, double* std_dev, void* stream) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  CHK(check_a(p, a));
+  if (!noise || !k_mean || !count || !mean || !std_dev) return fail(p, LPT2_EINVAL, "null pointer");
+  if (nbins < 1 || nbins > BIN_MAXBINS) return fail(p, LPT2_EINVAL, "nbins must be in 1..512");
+  if (quantity != LPT2_SPEC_POWER && quantity != LPT2_SPEC_RATIO) return fail(p, LPT2_EINVAL, "unknown quantity");
+  return spectrum_impl(p, a, noise, nbins, quantity, k_mean, count, mean, std_dev, (hipStream_t)stream);
+}
+
+lpt2_status lpt2_triangle_ratio(lpt2_plan_t p, double a, double ratio, double theta_deg, int winther, const double* k,
+                                int nk, double* out) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  CHK(check_a(p, a));
+  if (!k || !out || nk < 0) return fail(p, LPT2_EINVAL, "null pointer");
+  if (!(ratio > 0.0) || !(theta_deg > 0.0 && theta_deg < 180.0)) return fail(p, LPT2_EINVAL, "bad triangle");
+  return triangle_impl(p, a, ratio, theta_deg, winther, k, nk, out);
+}
+
+// candidate triangles of the factorisation choice (Sec. 3, triangle comparison)
+struct Candidate {
+  const char* name;
+  double ratio, theta;
+  int winther;
+};
+static const Candidate kCandidates[] = {
+    {"T1", 1.0, 90.0, 0},        {"T2", 1.0, 80.0, 0},       {"iso70", 1.0, 70.0, 0}, {"equilateral", 1.0, 60.0, 0},
+    {"squeezed", 1e-3, 90.0, 0}, {"r2_80", 2.0, 80.0, 0},    {"r2_70", 2.0, 70.0, 0}, {"winther", 1.0, 90.0, 1},
+};
+static constexpr int kNCandidates = (int)(sizeof(kCandidates) / sizeof(kCandidates[0]));
+
+int lpt2_factorisation_candidates(void) { return kNCandidates; }
+
+lpt2_status lpt2_factorisation_candidate(int i, const char** name, double* ratio, double* theta_deg, int* winther) {
+  if (i < 0 || i >= kNCandidates) return fail(nullptr, LPT2_EINVAL, "candidate index out of range");
+  if (name) *name = kCandidates[i].name;
+  if (ratio) *ratio = kCandidates[i].ratio;
+  if (theta_deg) *theta_deg = kCandidates[i].theta;
+  if (winther) *winther = kCandidates[i].winther;
+  return LPT2_OK;
+}
+
+lpt2_status lpt2_choose_factorisation(lpt2_plan_t p, double a, const void* noise, int nbins, double kcut, int apply,
+                                      int* best, double* costs, void* stream) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  CHK(check_a(p, a));
+  if (!noise || !best) return fail(p, LPT2_EINVAL, "null pointer");
+  if (nbins < 1 || nbins > BIN_MAXBINS) return fail(p, LPT2_EINVAL, "nbins must be in 1..512");
+  if (!(kcut > 0.0)) return fail(p, LPT2_EINVAL, "kcut must be > 0");
+  std::vector<double> km(nbins), cnt(nbins), mean(nbins), sd(nbins);
+  CHK(spectrum_impl(p, a, noise, nbins, LPT2_SPEC_RATIO, km.data(), cnt.data(), mean.data(), sd.data(),
+                    (hipStream_t)stream));
+  std::vector<double> ks, ws, ms;
+  for (int i = 0; i < nbins; ++i)
+    if (cnt[i] > 0.0 && km[i] > 0.0 && km[i] <= kcut) {
+      ks.push_back(km[i]);
+      ws.push_back(cnt[i]);
+      ms.push_back(mean[i]);
+    }
+  if (ks.empty()) return fail(p, LPT2_EINVAL, "no populated shell with 0 < k <= kcut");
+  std::vector<double> rt(ks.size());
+  int bi = -1;
+  double bc = 0.0;
+  for (int c = 0; c < kNCandidates; ++c) {
+    const Candidate& q = kCandidates[c];
+    CHK(triangle_impl(p, a, q.ratio, q.theta, q.winther, ks.data(), (int)ks.size(), rt.data()));
+    double cost = 0.0;
+    for (size_t i = 0; i < ks.size(); ++i) cost += ws[i] * (ms[i] - rt[i]) * (ms[i] - rt[i]);
+    if (costs) costs[c] = cost;
+    if (bi < 0 || cost < bc) {
+      bi = c;
+      bc = cost;
+    }
+  }
+  *best = bi;
+  if (apply) {
+    const Candidate& q = kCandidates[bi];
+    (void)hipDeviceSynchronize();
+    drop_graphs(p);
+    {  // the measured configuration (that of realisation 0) takes the chosen D2 table
+      Grid& g = p->grids[p->rgrid[0]];
+      if (q.winther) {
+        g.cfg.factorisation = LPT2_D2_WINTHER;
+      } else if (q.ratio == 1.0 && q.theta == 90.0) {
+        g.cfg.factorisation = LPT2_D2_T1;
+      } else {
+        g.cfg.factorisation = LPT2_D2_TRIANGLE;
+        g.cfg.tri_ratio = q.ratio;
+        g.cfg.tri_theta_deg = q.theta;
+      }
+      for (auto& t : g.tables) {  // D2 tables change; rebuilt on the next call
+        (void)hipFree(t.d1n);
+        if (t.radial) (void)hipFree(t.radial);
+      }
+      g.tables.clear();
+    }
   }
   return LPT2_OK;
 }

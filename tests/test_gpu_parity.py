@@ -199,6 +199,39 @@ def test_source_ratio_matches_oracle(gravity):
         assert np.max(np.abs(got["mean"][nz] - 1)) < 1e-12
 
 
+def test_choose_factorisation_matches_oracle():
+    print("factorisation choice f(R) 64^3", flush=True)
+    from paper_1909_06282_amd import LPT2Error, Plan
+    n, nb = 64, 32
+    plan, cfg = _plan(n=n, box=256.0, gravity="fr_hs", fr0_abs=1e-4, factorisation="eds", nk_growth=64)
+    w = white_noise(n, 5)
+    wd = to_dev(w, torch.float64)
+    name, costs = plan.choose_factorisation(1.0, wd, nbins=nb, kcut=0.4)
+    m = oracle_model(cfg)
+    tab = _tables(m, 1.0)
+    km, cnt, mean, _ = mgsource.source_ratio(w, m, 1.0, nb, tab)
+    best, ocosts = mgsource.choose_triangle(km, cnt, mean, m, 1.0, 0.4, tab)
+    print(f"  chosen {name} (oracle {best}); costs {costs}", flush=True)
+    assert name == best
+    assert set(costs) == set(ocosts)
+    for k, v in ocosts.items():
+        assert abs(costs[k] - v) <= 1e-8 * max(1.0, abs(v)), k
+    # apply: the plan's D2 table becomes the chosen candidate's
+    name2, _ = plan.choose_factorisation(1.0, wd, nbins=nb, kcut=0.4, apply=True)
+    assert name2 == name
+    p1, p2 = plan.displace(1.0, wd)
+    from paper_1909_06282_amd import factorisation_candidate
+    _, r, th, win = factorisation_candidate(list(costs).index(name))
+    kw = dict(factorisation="winther") if win else (dict(factorisation="t1") if (r == 1.0 and th == 90.0) else
+                                                    dict(factorisation="triangle", tri_ratio=r, tri_theta_deg=th))
+    ref = Plan(gpu_config(n=n, box=256.0, gravity="fr_hs", fr0_abs=1e-4, nk_growth=64, **kw))
+    q1, q2 = ref.displace(1.0, wd)
+    torch.cuda.synchronize()
+    assert torch.equal(p1, q1) and torch.equal(p2, q2)
+    with pytest.raises(LPT2Error):
+        plan.choose_factorisation(1.0, wd, nbins=nb, kcut=1e-4)
+
+
 def test_triangle_ratio_matches_oracle():
     plan, cfg = _plan(n=8, box=16.0, gravity="fr_hs", fr0_abs=1e-4, factorisation="t1", nk_growth=64)
     m = oracle_model(cfg)
