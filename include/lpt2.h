@@ -62,10 +62,15 @@ typedef enum { LPT2_GRAV_GR = 0, LPT2_GRAV_FR_HS = 1, LPT2_GRAV_MU_CONST = 2 } l
  *   T1       eq. full-d2 on the orthogonal isosceles triangle (k1 = k2, 90 deg)
  *   TRIANGLE eq. full-d2 on k1/k2 = tri_ratio at tri_theta_deg
  *   WINTHER  T1 geometry with D1(k)^2 in place of D1(k1) D1(k2)
- *   BOUCHET  D2 = -3/7 D1^2 Omega_m(a)^(-1/143)                          */
+ *   BOUCHET  D2 = -3/7 D1^2 Omega_m(a)^(-1/143)
+ *   AUTO     chosen by the library once per a (Sec. 3): the first call at a
+ *            that needs D2 (lpt2_displace, lpt2_backward, lpt2_autotune,
+ *            lpt2_source_spectrum) runs lpt2_choose_factorisation's fit on
+ *            the configuration's first realisation (n/2 shells, k <= 0.4
+ *            h/Mpc) and synchronises; later calls use the chosen candidate. */
 typedef enum {
   LPT2_D2_EDS = 0, LPT2_D2_T1 = 1, LPT2_D2_TRIANGLE = 2,
-  LPT2_D2_WINTHER = 3, LPT2_D2_BOUCHET = 4
+  LPT2_D2_WINTHER = 3, LPT2_D2_BOUCHET = 4, LPT2_D2_AUTO = 5
 } lpt2_factorisation;
 
 typedef enum { LPT2_SPEC_POWER = 0, LPT2_SPEC_RATIO = 1 } lpt2_spec_quantity;
@@ -171,6 +176,22 @@ lpt2_status lpt2_autotune(lpt2_plan_t plan, double a, const void* const* noise,
                           void* const* psi1, void* const* psi2, const char* cache_path,
                           void* stream);
 
+/* Test entry (a density field in place of white noise): psi1 and psi2 of
+ * realisation 0's grid for the given real-space density contrast delta
+ * ([n][n][n] device, the plan's precision): delta(k) = F[delta] mask, then as
+ * lpt2_displace (no sqrt(P) shaping).  Growth and radial tables are cached
+ * per a beside the white-noise ones.  An AUTO configuration must have made
+ * its choice at a (LPT2_ESTATE otherwise). */
+lpt2_status lpt2_displace_delta(lpt2_plan_t plan, double a, const void* delta, void* psi1,
+                                void* psi2, void* stream);
+
+/* Eulerian particle positions (eq. position): x = (q + psi1 + psi2) mod L for
+ * the particles of realisation r's grid, q = (ix, iy, iz) L/n; psi1, psi2
+ * and pos are [3][n][n][n] device arrays in the plan's precision (pos may
+ * alias neither input).  Asynchronous on `stream`. */
+lpt2_status lpt2_positions(lpt2_plan_t plan, int r, const void* psi1, const void* psi2, void* pos,
+                           void* stream);
+
 /* Shell-binned spectrum of the source for realisation 0 (Sec. 3: bin a
  * per-mode quantity in k, report mean and 1-sigma scatter).
  * quantity = LPT2_SPEC_POWER: q = V |S(k)/n^3|^2 of the displacement path's
@@ -211,14 +232,19 @@ lpt2_status lpt2_factorisation_candidate(int i, const char** name, double* ratio
  * wavenumbers; the cost of a candidate is sum_shells count (mean - R)^2 over
  * the populated shells with 0 < k_mean <= kcut (h/Mpc).  Writes the index of
  * the cheapest candidate to *best and, if costs is not NULL, every cost to
- * costs[0..lpt2_factorisation_candidates()).  apply != 0 sets the D2
- * factorisation of realisation 0's configuration to the chosen candidate
- * (its cached growth tables and captured graphs are dropped and rebuilt on
- * the next call).  nbins in 1..512, kcut > 0; no populated shell below kcut
- * -> LPT2_EINVAL.  Synchronises. */
+ * costs[0..lpt2_factorisation_candidates()).  apply != 0 makes the chosen
+ * candidate realisation 0's configuration's D2: for an AUTO configuration
+ * its choice at this a; for any other, its factorisation at every a (cached
+ * growth tables and captured graphs are dropped and rebuilt on the next
+ * call).  nbins in 1..512, kcut > 0; no populated shell below kcut ->
+ * LPT2_EINVAL.  Synchronises. */
 lpt2_status lpt2_choose_factorisation(lpt2_plan_t plan, double a, const void* noise, int nbins,
                                       double kcut, int apply, int* best, double* costs,
                                       void* stream);
+
+/* The candidate an AUTO configuration `grid` uses at a (index as in
+ * lpt2_factorisation_candidate), or -1 if not chosen yet (or not AUTO). */
+lpt2_status lpt2_auto_choice(lpt2_plan_t plan, int grid, double a, int* candidate);
 
 /* Vector-Jacobian product of lpt2_displace: given g_psi1[r], g_psi2[r]
  * (device, [3][n][n][n]) returns g_noise[r] = d/dw sum(g_psi1 psi1 + g_psi2 psi2)

@@ -11,7 +11,7 @@ LIB_PATH = os.environ.get("LPT2_LIBRARY") or os.path.join(HERE, "liblpt2.so")
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
 FP64, FP32 = 0, 1
 GRAV_GR, GRAV_FR_HS, GRAV_MU_CONST = 0, 1, 2
-D2_EDS, D2_T1, D2_TRIANGLE, D2_WINTHER, D2_BOUCHET = 0, 1, 2, 3, 4
+D2_EDS, D2_T1, D2_TRIANGLE, D2_WINTHER, D2_BOUCHET, D2_AUTO = 0, 1, 2, 3, 4, 5
 SPEC_POWER, SPEC_RATIO = 0, 1
 
 
@@ -46,7 +46,7 @@ EXPORTS = [
     "lpt2_profile_reset", "lpt2_profile_count", "lpt2_profile_get", "lpt2_workspace_bytes",
     "lpt2_strerror", "lpt2_last_error", "lpt2_set_graph", "lpt2_get_tiles", "lpt2_set_tiles",
     "lpt2_tile_options", "lpt2_autotune", "lpt2_factorisation_candidates", "lpt2_factorisation_candidate",
-    "lpt2_choose_factorisation",
+    "lpt2_choose_factorisation", "lpt2_auto_choice", "lpt2_displace_delta", "lpt2_positions",
 ]
 
 _lib = None
@@ -92,6 +92,9 @@ def load() -> C.CDLL:
     L.lpt2_factorisation_candidates.restype = C.c_int
     L.lpt2_factorisation_candidate.argtypes = [C.c_int, C.POINTER(C.c_char_p), dp, dp, ip]
     L.lpt2_choose_factorisation.argtypes = [plan_t, C.c_double, vp, C.c_int, C.c_double, C.c_int, ip, dp, vp]
+    L.lpt2_auto_choice.argtypes = [plan_t, C.c_int, C.c_double, ip]
+    L.lpt2_displace_delta.argtypes = [plan_t, C.c_double, vp, vp, vp, vp]
+    L.lpt2_positions.argtypes = [plan_t, C.c_int, vp, vp, vp, vp]
     L.lpt2_strerror.argtypes = [C.c_int]
     L.lpt2_strerror.restype = C.c_char_p
     L.lpt2_last_error.argtypes = [plan_t]
@@ -100,7 +103,8 @@ def load() -> C.CDLL:
                  "lpt2_triangle_ratio", "lpt2_backward", "lpt2_paint_cic", "lpt2_paint_cic_backward",
                  "lpt2_growth_table", "lpt2_fft3d", "lpt2_profile_enable", "lpt2_profile_reset",
                  "lpt2_profile_get", "lpt2_set_graph", "lpt2_get_tiles", "lpt2_set_tiles", "lpt2_tile_options",
-                 "lpt2_autotune", "lpt2_factorisation_candidate", "lpt2_choose_factorisation"):
+                 "lpt2_autotune", "lpt2_factorisation_candidate", "lpt2_choose_factorisation", "lpt2_auto_choice",
+                 "lpt2_displace_delta", "lpt2_positions"):
         getattr(L, name).restype = C.c_int
     L.lpt2_realisations.restype = C.c_int
     L.lpt2_profile_count.restype = C.c_int

@@ -17,7 +17,7 @@ from . import _abi
 
 _GRAVITY = {"gr": _abi.GRAV_GR, "fr_hs": _abi.GRAV_FR_HS, "mu_const": _abi.GRAV_MU_CONST}
 _FACT = {"eds": _abi.D2_EDS, "t1": _abi.D2_T1, "triangle": _abi.D2_TRIANGLE,
-         "winther": _abi.D2_WINTHER, "bouchet": _abi.D2_BOUCHET}
+         "winther": _abi.D2_WINTHER, "bouchet": _abi.D2_BOUCHET, "auto": _abi.D2_AUTO}
 _PREC = {"fp64": _abi.FP64, "fp32": _abi.FP32}
 
 
@@ -231,6 +231,37 @@ class Plan:
                                                        costs, _stream(stream)), self.handle)
         names = [factorisation_candidate(i)[0] for i in range(nc)]
         return names[best.value], dict(zip(names, list(costs)))
+
+    def auto_choice(self, grid: int, a: float):
+        """Name of the candidate an AUTO configuration uses at a (None if not chosen yet)."""
+        c = C.c_int()
+        _abi.check(self._lib.lpt2_auto_choice(self.handle, int(grid), float(a), C.byref(c)), self.handle)
+        return None if c.value < 0 else factorisation_candidate(c.value)[0]
+
+    def displace_delta(self, a: float, delta: torch.Tensor, psi1=None, psi2=None, stream=None):
+        """lpt2_displace_delta (test entry): psi1, psi2 from a real-space density contrast."""
+        n = self.sizes[0]
+        self._check_field(delta, (n, n, n), "delta")
+        psi1 = torch.empty((3, n, n, n), dtype=self.dtype, device=delta.device) if psi1 is None else psi1
+        psi2 = torch.empty((3, n, n, n), dtype=self.dtype, device=delta.device) if psi2 is None else psi2
+        self._check_field(psi1, (3, n, n, n), "psi1")
+        self._check_field(psi2, (3, n, n, n), "psi2")
+        _abi.check(self._lib.lpt2_displace_delta(self.handle, float(a), C.c_void_p(delta.data_ptr()),
+                                                 C.c_void_p(psi1.data_ptr()), C.c_void_p(psi2.data_ptr()),
+                                                 _stream(stream)), self.handle)
+        return psi1, psi2
+
+    def positions(self, psi1: torch.Tensor, psi2: torch.Tensor, r: int = 0, out=None, stream=None):
+        """lpt2_positions: x = (q + psi1 + psi2) mod L for realisation r's particles."""
+        n = self.sizes[r]
+        self._check_field(psi1, (3, n, n, n), "psi1")
+        self._check_field(psi2, (3, n, n, n), "psi2")
+        out = torch.empty_like(psi1) if out is None else out
+        self._check_field(out, (3, n, n, n), "pos")
+        _abi.check(self._lib.lpt2_positions(self.handle, int(r), C.c_void_p(psi1.data_ptr()),
+                                            C.c_void_p(psi2.data_ptr()), C.c_void_p(out.data_ptr()),
+                                            _stream(stream)), self.handle)
+        return out
 
     def growth_table(self, a: float):
         nk = self.cfgs[0].nk_growth

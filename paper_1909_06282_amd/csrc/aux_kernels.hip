@@ -84,7 +84,7 @@ __global__ void k_radial(RadialSetup r, const double* __restrict__ d1n, const do
     const double n3 = (double)r.n * (double)r.n * (double)r.n;
     const double t = bbks(r.c, k);
     const double p = r.amp * pow(k, r.c.ns) * t * t;
-    const double A = sqrt(p * n3 / (r.box * r.box * r.box));
+    const double A = r.unit ? 1.0 : sqrt(p * n3 / (r.box * r.box * r.box));
     const double d1 = interp_lnk(d1n, r.nk, r.lkmin, r.lkmax, k);
     const double d2 = interp_lnk(d2n, r.nk, r.lkmin, r.lkmax, k);
     const double inv = 1.0 / n3;
@@ -369,6 +369,38 @@ hipError_t launch_cic(int prec, int n, double box, const void* psi1, const void*
   else
     hipLaunchKernelGGL(k_cic<double>, dim3(blocks), dim3(256), 0, s, n, ic, (const double*)psi1, (const double*)psi2,
                        (double*)delta);
+  return hipGetLastError();
+}
+
+// Eulerian positions (eq. position): particle (ix, iy, iz) starts at
+// q = (ix, iy, iz) L/n; x = q + psi1 + psi2 wrapped into [0, L).
+template <typename T>
+__global__ void k_positions(int n, double box, const T* __restrict__ p1, const T* __restrict__ p2,
+                            T* __restrict__ x) {
+  const long n3 = (long)n * n * n;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * n3) return;
+  const int c = (int)(i / n3);
+  const long p = i - c * n3;
+  const long id = c == 0 ? p / ((long)n * n) : (c == 1 ? (p / n) % n : p % n);
+  const T L = (T)box;
+  const T q = (T)id * (T)(box / n);
+  T v = (q + p1[i]) + p2[i];
+  v = v - floor(v / L) * L;
+  if (v >= L) v -= L;  // rounding at the upper edge
+  if (v < T(0)) v += L;
+  x[i] = v;
+}
+
+hipError_t launch_positions(int prec, int n, double box, const void* psi1, const void* psi2, void* pos, hipStream_t s) {
+  const long cnt = 3L * n * n * n;
+  const unsigned blocks = (unsigned)((cnt + 255) / 256);
+  if (prec == PREC_F32)
+    hipLaunchKernelGGL(k_positions<float>, dim3(blocks), dim3(256), 0, s, n, box, (const float*)psi1,
+                       (const float*)psi2, (float*)pos);
+  else
+    hipLaunchKernelGGL(k_positions<double>, dim3(blocks), dim3(256), 0, s, n, box, (const double*)psi1,
+                       (const double*)psi2, (double*)pos);
   return hipGetLastError();
 }
 

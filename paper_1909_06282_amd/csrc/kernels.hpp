@@ -128,6 +128,7 @@ struct RadialSetup {
   double box, amp, a;
   int nk;
   double lkmin, lkmax;
+  int unit;   // 1: no sqrt(P n^3/V) shaping (the input is a density field, not white noise)
 };
 // per-|m|^2 FP64 tables: TAB_COUNT arrays of n2max + 1 = 3 (n/2)^2 + 1 entries,
 // then the interleaved pair table (PHI, PSI1) of 2 (n2max + 1) entries
@@ -142,6 +143,8 @@ hipError_t launch_bin(int prec, int n, const void* A, size_t a_cap, const void* 
                       double qscale, int nbins, double kf, double* partial, double* out4, hipStream_t s);
 
 hipError_t launch_cic(int prec, int n, double box, const void* psi1, const void* psi2, void* delta, hipStream_t s);
+// x = (q + psi1 + psi2) mod box per particle and component ([3][n][n][n] each)
+hipError_t launch_positions(int prec, int n, double box, const void* psi1, const void* psi2, void* pos, hipStream_t s);
 hipError_t launch_cic_back(int prec, int n, double box, const void* psi1, const void* psi2, const void* gdelta,
                            void* gpsi, hipStream_t s);
 

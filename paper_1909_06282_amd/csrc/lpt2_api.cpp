@@ -23,6 +23,8 @@ thread_local std::string g_err;  // errors without a plan
 
 struct Tables {
   double a = 0.0;
+  bool unit = false;       // radial tables without the sqrt(P) shaping (density input)
+  int cand = -1;           // AUTO configurations: the candidate D2 was built for (-1: provisional T1)
   double* d1n = nullptr;   // nk normalised D1 on the nodes
   double* d2n = nullptr;   // nk normalised D2 on the nodes
   double* radial = nullptr;  // TAB_COUNT x n2cnt
@@ -44,6 +46,7 @@ struct Grid {
   hipEvent_t join = nullptr;
   std::vector<Tables> tables;
   std::vector<Tables> gr_tables;  // GR growth at a (for S_GR and the triangle ratios)
+  std::vector<std::pair<double, int>> auto_choice;  // AUTO: (a, chosen candidate)
 };
 
 struct GraphEntry {
@@ -153,7 +156,7 @@ lpt2_status validate(const lpt2_config& c, std::string& why) {
     if (c.hs_n != 1) { why = "only Hu-Sawicki n = 1 has its M_k coefficients given"; return LPT2_EUNSUPPORTED; }
   }
   if (c.gravity == LPT2_GRAV_MU_CONST && !(c.mu_const > 0.0)) { why = "mu_const must be > 0"; return LPT2_EINVAL; }
-  if (c.factorisation < 0 || c.factorisation > 4) { why = "unknown factorisation"; return LPT2_EINVAL; }
+  if (c.factorisation < 0 || c.factorisation > LPT2_D2_AUTO) { why = "unknown factorisation"; return LPT2_EINVAL; }
   if (c.factorisation == LPT2_D2_TRIANGLE &&
       (!(c.tri_ratio > 0.0) || !(c.tri_theta_deg > 0.0 && c.tri_theta_deg < 180.0))) {
     why = "triangle needs ratio > 0 and 0 < theta < 180";
@@ -234,11 +237,32 @@ void drop_graphs(lpt2_plan_t p) {
   p->graphs.clear();
 }
 
+// ---- candidate triangles of the factorisation choice -----------------------------
+// (Sec. 3, triangle comparison)
+struct Candidate {
+  const char* name;
+  double ratio, theta;
+  int winther;
+};
+const Candidate kCandidates[] = {
+    {"T1", 1.0, 90.0, 0},        {"T2", 1.0, 80.0, 0},    {"iso70", 1.0, 70.0, 0}, {"equilateral", 1.0, 60.0, 0},
+    {"squeezed", 1e-3, 90.0, 0}, {"r2_80", 2.0, 80.0, 0}, {"r2_70", 2.0, 70.0, 0}, {"winther", 1.0, 90.0, 1},
+};
+constexpr int kNCandidates = (int)(sizeof(kCandidates) / sizeof(kCandidates[0]));
+constexpr int kAutoNone = -1;
+
+int auto_lookup(const Grid& g, double a) {
+  for (const auto& c : g.auto_choice)
+    if (c.first == a) return c.second;
+  return kAutoNone;
+}
+
 // ---- growth tables -------------------------------------------------------------
-lpt2_status build_tables(lpt2_plan_t p, Grid& g, double a, bool gr, hipStream_t s, Tables& out) {
+lpt2_status build_tables(lpt2_plan_t p, Grid& g, double a, bool gr, bool unit, hipStream_t s, Tables& out) {
   const lpt2_config& cf = g.cfg;
   Tables t;
   t.a = a;
+  t.unit = unit;
   const int nk = cf.nk_growth;
   hipError_t e = hipMalloc((void**)&t.d1n, sizeof(double) * nk * 2);
   if (e != hipSuccess) return fail(p, LPT2_ENOMEM, "growth table allocation failed");
@@ -255,13 +279,25 @@ lpt2_status build_tables(lpt2_plan_t p, Grid& g, double a, bool gr, hipStream_t 
   gs.winther = 0;
   gs.ratio = 1.0;
   gs.cs = 0.0;
-  switch (gr ? LPT2_D2_EDS : cf.factorisation) {
+  int fac = gr ? LPT2_D2_EDS : cf.factorisation;
+  double tri_ratio = cf.tri_ratio, tri_theta = cf.tri_theta_deg;
+  if (fac == LPT2_D2_AUTO) {  // the chosen candidate at a, else provisionally T1 (D1 does not depend on it)
+    t.cand = auto_lookup(g, a);
+    fac = LPT2_D2_T1;
+    if (t.cand >= 0) {
+      const Candidate& q = kCandidates[t.cand];
+      fac = q.winther ? LPT2_D2_WINTHER : LPT2_D2_TRIANGLE;
+      tri_ratio = q.ratio;
+      tri_theta = q.theta;
+    }
+  }
+  switch (fac) {
     case LPT2_D2_EDS: gs.mode = 0; break;
     case LPT2_D2_BOUCHET: gs.mode = 2; break;
     case LPT2_D2_TRIANGLE:
       gs.mode = 1;
-      gs.ratio = cf.tri_ratio;
-      gs.cs = cos_deg(cf.tri_theta_deg);
+      gs.ratio = tri_ratio;
+      gs.cs = cos_deg(tri_theta);
       break;
     case LPT2_D2_WINTHER: gs.mode = 1; gs.winther = 1; break;
     default: gs.mode = 1; break;  // T1
@@ -286,6 +322,7 @@ lpt2_status build_tables(lpt2_plan_t p, Grid& g, double a, bool gr, hipStream_t 
     rs.nk = nk;
     rs.lkmin = g.lkmin;
     rs.lkmax = g.lkmax;
+    rs.unit = unit ? 1 : 0;
     st = run(p, s, "radial_tables", 0.0, [&]() { return launch_radial(rs, t.d1n, t.d2n, t.radial, g.n2cnt, s); });
     if (st != LPT2_OK) {
       (void)hipFree(t.d1n);
@@ -297,23 +334,38 @@ lpt2_status build_tables(lpt2_plan_t p, Grid& g, double a, bool gr, hipStream_t 
   return LPT2_OK;
 }
 
-lpt2_status get_tables(lpt2_plan_t p, Grid& g, double a, bool gr, hipStream_t s, Tables** out) {
+void free_tables(Tables& t) {
+  (void)hipFree(t.d1n);
+  if (t.radial) (void)hipFree(t.radial);
+}
+
+lpt2_status get_tables(lpt2_plan_t p, Grid& g, double a, bool gr, hipStream_t s, Tables** out, bool unit = false) {
   std::vector<Tables>& cache = gr ? g.gr_tables : g.tables;
-  for (auto& t : cache)
-    if (t.a == a) {
+  const int cand = (!gr && g.cfg.factorisation == LPT2_D2_AUTO) ? auto_lookup(g, a) : kAutoNone;
+  for (size_t i = 0; i < cache.size(); ++i) {
+    Tables& t = cache[i];
+    if (t.a != a || t.unit != unit) continue;
+    if (t.cand == cand) {
       *out = &t;
       return LPT2_OK;
     }
+    // an AUTO configuration whose choice at a was made after these tables
+    (void)hipStreamSynchronize(s);
+    (void)hipDeviceSynchronize();
+    drop_graphs(p);
+    free_tables(t);
+    cache.erase(cache.begin() + (long)i);
+    break;
+  }
   if (cache.size() >= 32) {  // drop the oldest entry once its users are done
     (void)hipStreamSynchronize(s);
     (void)hipDeviceSynchronize();
     drop_graphs(p);           // captured graphs may read the tables
-    (void)hipFree(cache.front().d1n);
-    if (cache.front().radial) (void)hipFree(cache.front().radial);
+    free_tables(cache.front());
     cache.erase(cache.begin());
   }
   Tables t;
-  lpt2_status st = build_tables(p, g, a, gr, s, t);
+  lpt2_status st = build_tables(p, g, a, gr, unit, s, t);
   if (st != LPT2_OK) return st;
   cache.push_back(t);
   *out = &cache.back();
@@ -860,6 +912,120 @@ lpt2_status autotune(lpt2_plan_t p, const std::vector<Tables*>& tabs, const void
   return st;
 }
 
+// bodies of lpt2_source_spectrum and lpt2_triangle_ratio (the caller holds the plan)
+lpt2_status spectrum_impl(lpt2_plan_t p, Grid& g, double a, const void* noise, int nbins, int quantity,
+                                 double* k_mean, double* count, double* mean, double* std_dev, hipStream_t s) {
+  Tables* t = nullptr;
+  CHK(get_tables(p, g, a, false, s, &t));
+  Ctx c{p, g, s, 2 * p->es, p->ws, 1};
+  const double kf = 2.0 * kPi / g.cfg.box;
+  if (quantity == LPT2_SPEC_POWER) {
+    CHK(source_k(c, t, noise, 11, 1.0));
+    const double n3 = (double)g.n3;
+    const double qs = g.cfg.box * g.cfg.box * g.cfg.box / (n3 * n3);
+    RUN("shell_bin", 0.0,
+        launch_bin(p->prec, g.n, c.slot(11), c.cap(c.slot(11)), nullptr, 0, 0, qs, nbins, kf, p->bin_partial,
+                   p->bin_out, s));
+  } else {
+    Tables* tg = nullptr;
+    CHK(get_tables(p, g, a, true, s, &tg));
+    double d1gr = 0.0;
+    hipError_t e = hipMemcpyAsync(&d1gr, tg->d1n, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(p, e, "D1_GR readback");
+    const double G = four_pi_g_rho(g.c, a);
+    CHK(source_k(c, t, noise, 11, -G * d1gr * d1gr));
+    CHK(mg_source_k(c, t, noise));
+    RUN("shell_bin", 0.0,
+        launch_bin(p->prec, g.n, c.slot(10), c.cap(c.slot(10)), c.slot(11), c.cap(c.slot(11)), 1, 1.0, nbins, kf,
+                   p->bin_partial, p->bin_out, s));
+  }
+  std::vector<double> h(4 * (size_t)nbins);
+  hipError_t e = hipMemcpyAsync(h.data(), p->bin_out, sizeof(double) * 4 * nbins, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(p, e, "spectrum readback");
+  for (int i = 0; i < nbins; ++i) {
+    k_mean[i] = h[i];
+    count[i] = h[nbins + i];
+    mean[i] = h[2 * nbins + i];
+    std_dev[i] = h[3 * nbins + i];
+  }
+  return LPT2_OK;
+}
+
+lpt2_status triangle_impl(lpt2_plan_t p, Grid& g, double a, double ratio, double theta_deg, int winther,
+                                 const double* k, int nk, double* out) {
+  hipStream_t s = nullptr;
+  Tables *t = nullptr, *tg = nullptr;
+  CHK(get_tables(p, g, a, false, s, &t));
+  CHK(get_tables(p, g, a, true, s, &tg));
+  const int n = g.cfg.nk_growth;
+  std::vector<double> d1(n), d1g(1);
+  hipError_t e = hipMemcpy(d1.data(), t->d1n, sizeof(double) * n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(d1g.data(), tg->d1n, sizeof(double), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(p, e, "growth readback");
+  const double cs = cos_deg(theta_deg);
+  for (int i = 0; i < nk; ++i) {
+    double k1, k2;
+    triangle(k[i], ratio, cs, k1, k2);
+    const double dd = winther ? std::pow(interp_lnk(d1.data(), n, g.lkmin, g.lkmax, k[i]), 2)
+                              : interp_lnk(d1.data(), n, g.lkmin, g.lkmax, k1) * interp_lnk(d1.data(), n, g.lkmin, g.lkmax, k2);
+    out[i] = dd * brace(g.c, k[i], k1, k2, cs, a) / (d1g[0] * d1g[0] * (1.0 - cs * cs));
+  }
+  return LPT2_OK;
+}
+
+// The fit of the factorisation choice: the cheapest candidate for grid g at a
+// (count-weighted squared misfit of the binned ratio, shells 0 < k <= kcut).
+lpt2_status fit_candidates(lpt2_plan_t p, Grid& g, double a, const void* noise, int nbins, double kcut,
+                                  hipStream_t s, int* best, double* costs) {
+  std::vector<double> km(nbins), cnt(nbins), mean(nbins), sd(nbins);
+  CHK(spectrum_impl(p, g, a, noise, nbins, LPT2_SPEC_RATIO, km.data(), cnt.data(), mean.data(), sd.data(), s));
+  std::vector<double> ks, ws, ms;
+  for (int i = 0; i < nbins; ++i)
+    if (cnt[i] > 0.0 && km[i] > 0.0 && km[i] <= kcut) {
+      ks.push_back(km[i]);
+      ws.push_back(cnt[i]);
+      ms.push_back(mean[i]);
+    }
+  if (ks.empty()) return fail(p, LPT2_EINVAL, "no populated shell with 0 < k <= kcut");
+  std::vector<double> rt(ks.size());
+  int bi = -1;
+  double bc = 0.0;
+  for (int c = 0; c < kNCandidates; ++c) {
+    const Candidate& q = kCandidates[c];
+    CHK(triangle_impl(p, g, a, q.ratio, q.theta, q.winther, ks.data(), (int)ks.size(), rt.data()));
+    double cost = 0.0;
+    for (size_t i = 0; i < ks.size(); ++i) cost += ws[i] * (ms[i] - rt[i]) * (ms[i] - rt[i]);
+    if (costs) costs[c] = cost;
+    if (bi < 0 || cost < bc) {
+      bi = c;
+      bc = cost;
+    }
+  }
+  *best = bi;
+  return LPT2_OK;
+}
+
+void set_auto(Grid& g, double a, int cand) {
+  for (auto& c : g.auto_choice)
+    if (c.first == a) {
+      c.second = cand;
+      return;
+    }
+  g.auto_choice.push_back({a, cand});
+}
+
+// AUTO configurations: the factorisation at a is chosen once, from the
+// source ratio of `noise` (n/2 shells of width k_f, k <= 0.4 h/Mpc).
+lpt2_status resolve_auto(lpt2_plan_t p, Grid& g, double a, const void* noise, hipStream_t s) {
+  if (g.cfg.factorisation != LPT2_D2_AUTO || auto_lookup(g, a) != kAutoNone) return LPT2_OK;
+  int best = 0;
+  CHK(fit_candidates(p, g, a, noise, std::min(g.n / 2, BIN_MAXBINS), 0.4, s, &best, nullptr));
+  set_auto(g, a, best);
+  return LPT2_OK;
+}
+
 }  // namespace
 
 // =============================================================================
@@ -1060,6 +1226,7 @@ lpt2_status lpt2_displace(lpt2_plan_t p, double a, const void* const* noise, voi
   for (int r = 0; r < nr; ++r)
     if (!noise[r] || !psi1[r] || !psi2[r]) return fail(p, LPT2_EINVAL, "null field pointer for realisation " + std::to_string(r));
   hipStream_t s = (hipStream_t)stream;
+  for (auto& g : p->grids) CHK(resolve_auto(p, g, a, noise[g.rfirst], s));  // before any capture
   std::vector<Tables*> tabs;
   CHK(tables_for(p, a, s, tabs));
   if (!p->graph_mode) return run_displace(p, tabs, noise, psi1, psi2, s);
@@ -1124,74 +1291,10 @@ lpt2_status lpt2_autotune(lpt2_plan_t p, double a, const void* const* noise, voi
   for (int r = 0; r < nr; ++r)
     if (!noise[r] || !psi1[r] || !psi2[r]) return fail(p, LPT2_EINVAL, "null field pointer for realisation " + std::to_string(r));
   hipStream_t s = (hipStream_t)stream;
+  for (auto& g : p->grids) CHK(resolve_auto(p, g, a, noise[g.rfirst], s));
   std::vector<Tables*> tabs;
   CHK(tables_for(p, a, s, tabs));
   return autotune(p, tabs, noise, psi1, psi2, cache_path, s);
-}
-
-// bodies of lpt2_source_spectrum and lpt2_triangle_ratio (the caller holds the plan)
-static lpt2_status spectrum_impl(lpt2_plan_t p, double a, const void* noise, int nbins, int quantity, double* k_mean,
-                                 double* count, double* mean, double* std_dev, hipStream_t s) {
-  Grid& g = p->grids[p->rgrid[0]];
-  Tables* t = nullptr;
-  CHK(get_tables(p, g, a, false, s, &t));
-  Ctx c{p, g, s, 2 * p->es, p->ws, 1};
-  const double kf = 2.0 * kPi / g.cfg.box;
-  if (quantity == LPT2_SPEC_POWER) {
-    CHK(source_k(c, t, noise, 11, 1.0));
-    const double n3 = (double)g.n3;
-    const double qs = g.cfg.box * g.cfg.box * g.cfg.box / (n3 * n3);
-    RUN("shell_bin", 0.0,
-        launch_bin(p->prec, g.n, c.slot(11), c.cap(c.slot(11)), nullptr, 0, 0, qs, nbins, kf, p->bin_partial,
-                   p->bin_out, s));
-  } else {
-    Tables* tg = nullptr;
-    CHK(get_tables(p, g, a, true, s, &tg));
-    double d1gr = 0.0;
-    hipError_t e = hipMemcpyAsync(&d1gr, tg->d1n, sizeof(double), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(p, e, "D1_GR readback");
-    const double G = four_pi_g_rho(g.c, a);
-    CHK(source_k(c, t, noise, 11, -G * d1gr * d1gr));
-    CHK(mg_source_k(c, t, noise));
-    RUN("shell_bin", 0.0,
-        launch_bin(p->prec, g.n, c.slot(10), c.cap(c.slot(10)), c.slot(11), c.cap(c.slot(11)), 1, 1.0, nbins, kf,
-                   p->bin_partial, p->bin_out, s));
-  }
-  std::vector<double> h(4 * (size_t)nbins);
-  hipError_t e = hipMemcpyAsync(h.data(), p->bin_out, sizeof(double) * 4 * nbins, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(p, e, "spectrum readback");
-  for (int i = 0; i < nbins; ++i) {
-    k_mean[i] = h[i];
-    count[i] = h[nbins + i];
-    mean[i] = h[2 * nbins + i];
-    std_dev[i] = h[3 * nbins + i];
-  }
-  return LPT2_OK;
-}
-
-static lpt2_status triangle_impl(lpt2_plan_t p, double a, double ratio, double theta_deg, int winther,
-                                 const double* k, int nk, double* out) {
-  Grid& g = p->grids[p->rgrid[0]];
-  hipStream_t s = nullptr;
-  Tables *t = nullptr, *tg = nullptr;
-  CHK(get_tables(p, g, a, false, s, &t));
-  CHK(get_tables(p, g, a, true, s, &tg));
-  const int n = g.cfg.nk_growth;
-  std::vector<double> d1(n), d1g(1);
-  hipError_t e = hipMemcpy(d1.data(), t->d1n, sizeof(double) * n, hipMemcpyDeviceToHost);
-  if (e == hipSuccess) e = hipMemcpy(d1g.data(), tg->d1n, sizeof(double), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(p, e, "growth readback");
-  const double cs = cos_deg(theta_deg);
-  for (int i = 0; i < nk; ++i) {
-    double k1, k2;
-    triangle(k[i], ratio, cs, k1, k2);
-    const double dd = winther ? std::pow(interp_lnk(d1.data(), n, g.lkmin, g.lkmax, k[i]), 2)
-                              : interp_lnk(d1.data(), n, g.lkmin, g.lkmax, k1) * interp_lnk(d1.data(), n, g.lkmin, g.lkmax, k2);
-    out[i] = dd * brace(g.c, k[i], k1, k2, cs, a) / (d1g[0] * d1g[0] * (1.0 - cs * cs));
-  }
-  return LPT2_OK;
 }
 
 lpt2_status lpt2_source_spectrum(lpt2_plan_t p, double a, const void* noise, int nbins, int quantity, double* k_mean,
@@ -1203,7 +1306,10 @@ lpt2_status lpt2_source_spectrum(lpt2_plan_t p, double a, const void* noise, int
   if (!noise || !k_mean || !count || !mean || !std_dev) return fail(p, LPT2_EINVAL, "null pointer");
   if (nbins < 1 || nbins > BIN_MAXBINS) return fail(p, LPT2_EINVAL, "nbins must be in 1..512");
   if (quantity != LPT2_SPEC_POWER && quantity != LPT2_SPEC_RATIO) return fail(p, LPT2_EINVAL, "unknown quantity");
-  return spectrum_impl(p, a, noise, nbins, quantity, k_mean, count, mean, std_dev, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  Grid& g = p->grids[p->rgrid[0]];
+  CHK(resolve_auto(p, g, a, noise, s));
+  return spectrum_impl(p, g, a, noise, nbins, quantity, k_mean, count, mean, std_dev, s);
 }
 
 lpt2_status lpt2_triangle_ratio(lpt2_plan_t p, double a, double ratio, double theta_deg, int winther, const double* k,
@@ -1214,20 +1320,8 @@ lpt2_status lpt2_triangle_ratio(lpt2_plan_t p, double a, double ratio, double th
   CHK(check_a(p, a));
   if (!k || !out || nk < 0) return fail(p, LPT2_EINVAL, "null pointer");
   if (!(ratio > 0.0) || !(theta_deg > 0.0 && theta_deg < 180.0)) return fail(p, LPT2_EINVAL, "bad triangle");
-  return triangle_impl(p, a, ratio, theta_deg, winther, k, nk, out);
+  return triangle_impl(p, p->grids[p->rgrid[0]], a, ratio, theta_deg, winther, k, nk, out);
 }
-
-// candidate triangles of the factorisation choice (Sec. 3, triangle comparison)
-struct Candidate {
-  const char* name;
-  double ratio, theta;
-  int winther;
-};
-static const Candidate kCandidates[] = {
-    {"T1", 1.0, 90.0, 0},        {"T2", 1.0, 80.0, 0},       {"iso70", 1.0, 70.0, 0}, {"equilateral", 1.0, 60.0, 0},
-    {"squeezed", 1e-3, 90.0, 0}, {"r2_80", 2.0, 80.0, 0},    {"r2_70", 2.0, 70.0, 0}, {"winther", 1.0, 90.0, 1},
-};
-static constexpr int kNCandidates = (int)(sizeof(kCandidates) / sizeof(kCandidates[0]));
 
 int lpt2_factorisation_candidates(void) { return kNCandidates; }
 
@@ -1249,54 +1343,68 @@ lpt2_status lpt2_choose_factorisation(lpt2_plan_t p, double a, const void* noise
   if (!noise || !best) return fail(p, LPT2_EINVAL, "null pointer");
   if (nbins < 1 || nbins > BIN_MAXBINS) return fail(p, LPT2_EINVAL, "nbins must be in 1..512");
   if (!(kcut > 0.0)) return fail(p, LPT2_EINVAL, "kcut must be > 0");
-  std::vector<double> km(nbins), cnt(nbins), mean(nbins), sd(nbins);
-  CHK(spectrum_impl(p, a, noise, nbins, LPT2_SPEC_RATIO, km.data(), cnt.data(), mean.data(), sd.data(),
-                    (hipStream_t)stream));
-  std::vector<double> ks, ws, ms;
-  for (int i = 0; i < nbins; ++i)
-    if (cnt[i] > 0.0 && km[i] > 0.0 && km[i] <= kcut) {
-      ks.push_back(km[i]);
-      ws.push_back(cnt[i]);
-      ms.push_back(mean[i]);
-    }
-  if (ks.empty()) return fail(p, LPT2_EINVAL, "no populated shell with 0 < k <= kcut");
-  std::vector<double> rt(ks.size());
-  int bi = -1;
-  double bc = 0.0;
-  for (int c = 0; c < kNCandidates; ++c) {
-    const Candidate& q = kCandidates[c];
-    CHK(triangle_impl(p, a, q.ratio, q.theta, q.winther, ks.data(), (int)ks.size(), rt.data()));
-    double cost = 0.0;
-    for (size_t i = 0; i < ks.size(); ++i) cost += ws[i] * (ms[i] - rt[i]) * (ms[i] - rt[i]);
-    if (costs) costs[c] = cost;
-    if (bi < 0 || cost < bc) {
-      bi = c;
-      bc = cost;
-    }
-  }
+  Grid& g = p->grids[p->rgrid[0]];
+  int bi = 0;
+  CHK(fit_candidates(p, g, a, noise, nbins, kcut, (hipStream_t)stream, &bi, costs));
   *best = bi;
-  if (apply) {
-    const Candidate& q = kCandidates[bi];
-    (void)hipDeviceSynchronize();
-    drop_graphs(p);
-    {  // the measured configuration (that of realisation 0) takes the chosen D2 table
-      Grid& g = p->grids[p->rgrid[0]];
-      if (q.winther) {
-        g.cfg.factorisation = LPT2_D2_WINTHER;
-      } else if (q.ratio == 1.0 && q.theta == 90.0) {
-        g.cfg.factorisation = LPT2_D2_T1;
-      } else {
-        g.cfg.factorisation = LPT2_D2_TRIANGLE;
-        g.cfg.tri_ratio = q.ratio;
-        g.cfg.tri_theta_deg = q.theta;
-      }
-      for (auto& t : g.tables) {  // D2 tables change; rebuilt on the next call
-        (void)hipFree(t.d1n);
-        if (t.radial) (void)hipFree(t.radial);
-      }
-      g.tables.clear();
-    }
+  if (!apply) return LPT2_OK;
+  if (g.cfg.factorisation == LPT2_D2_AUTO) {  // the tables at a are rebuilt on their next use
+    set_auto(g, a, bi);
+    return LPT2_OK;
   }
+  // a fixed factorisation is replaced by the chosen candidate at every a
+  const Candidate& q = kCandidates[bi];
+  (void)hipDeviceSynchronize();
+  drop_graphs(p);
+  if (q.winther) {
+    g.cfg.factorisation = LPT2_D2_WINTHER;
+  } else if (q.ratio == 1.0 && q.theta == 90.0) {
+    g.cfg.factorisation = LPT2_D2_T1;
+  } else {
+    g.cfg.factorisation = LPT2_D2_TRIANGLE;
+    g.cfg.tri_ratio = q.ratio;
+    g.cfg.tri_theta_deg = q.theta;
+  }
+  for (auto& t : g.tables) free_tables(t);  // D2 changes; rebuilt on the next call
+  g.tables.clear();
+  return LPT2_OK;
+}
+
+lpt2_status lpt2_auto_choice(lpt2_plan_t p, int grid, double a, int* candidate) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  if (!candidate || grid < 0 || grid >= (int)p->grids.size()) return fail(p, LPT2_EINVAL, "bad grid index or NULL");
+  *candidate = auto_lookup(p->grids[grid], a);
+  return LPT2_OK;
+}
+
+lpt2_status lpt2_displace_delta(lpt2_plan_t p, double a, const void* delta, void* psi1, void* psi2, void* stream) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  CHK(check_a(p, a));
+  if (!delta || !psi1 || !psi2) return fail(p, LPT2_EINVAL, "null pointer");
+  Grid& g = p->grids[p->rgrid[0]];
+  if (g.cfg.factorisation == LPT2_D2_AUTO && auto_lookup(g, a) == kAutoNone)
+    return fail(p, LPT2_ESTATE, "AUTO factorisation not chosen at this a (run lpt2_displace or "
+                                "lpt2_choose_factorisation first)");
+  hipStream_t s = (hipStream_t)stream;
+  Tables* t = nullptr;
+  CHK(get_tables(p, g, a, false, s, &t, true));
+  Ctx c{p, g, s, 2 * p->es, p->ws, 1};
+  const void* in[1] = {delta};
+  void* o1[1] = {psi1};
+  void* o2[1] = {psi2};
+  return displace_batch(c, t, in, o1, o2);
+}
+
+lpt2_status lpt2_positions(lpt2_plan_t p, int r, const void* psi1, const void* psi2, void* pos, void* stream) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  if (r < 0 || r >= (int)p->rgrid.size()) return fail(p, LPT2_EINVAL, "realisation index out of range");
+  if (!psi1 || !psi2 || !pos) return fail(p, LPT2_EINVAL, "null pointer");
+  const Grid& g = p->grids[p->rgrid[r]];
+  hipStream_t s = (hipStream_t)stream;
+  RUN("positions", 9.0 * (double)g.n3 * p->es,
+      launch_positions(p->prec, g.n, g.cfg.box, psi1, psi2, pos, s));
   return LPT2_OK;
 }
 
@@ -1312,6 +1420,7 @@ lpt2_status lpt2_backward(lpt2_plan_t p, double a, const void* const* noise, con
     if (!noise[r] || !g_psi1[r] || !g_psi2[r] || !g_noise[r])
       return fail(p, LPT2_EINVAL, "null field pointer for realisation " + std::to_string(r));
   hipStream_t s = (hipStream_t)stream;
+  for (auto& g : p->grids) CHK(resolve_auto(p, g, a, noise[g.rfirst], s));
   for (int r = 0; r < nr; ++r) {
     Grid& g = p->grids[p->rgrid[r]];
     Tables* t = nullptr;
@@ -1352,6 +1461,9 @@ lpt2_status lpt2_growth_table(lpt2_plan_t p, double a, double* k, double* d1, do
   CHK(check_a(p, a));
   if (!k || !d1 || !d2) return fail(p, LPT2_EINVAL, "null pointer");
   Grid& g = p->grids[p->rgrid[0]];
+  if (g.cfg.factorisation == LPT2_D2_AUTO && auto_lookup(g, a) == kAutoNone)
+    return fail(p, LPT2_ESTATE, "AUTO factorisation not chosen at this a (run lpt2_displace or "
+                                "lpt2_choose_factorisation first)");
   Tables* t = nullptr;
   CHK(get_tables(p, g, a, false, nullptr, &t));
   const int n = g.cfg.nk_growth;

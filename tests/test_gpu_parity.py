@@ -154,6 +154,94 @@ def test_single_plane_wave_gives_no_psi2():
     assert float(p2.abs().max()) < 1e-13 * float(p1.abs().max())
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", F64_TOL), ("fp32", F32_TOL)])
+def test_displace_delta_matches_oracle(prec, tol):
+    # a density field in place of white noise (no shaping): the oracle's
+    # delta(k) path on F[delta]
+    print(f"displace from delta(x) {prec}", flush=True)
+    n = 32
+    plan, cfg = _plan(precision=prec, n=n, box=64.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1",
+                      nk_growth=64)
+    dx = 0.05 * white_noise(n, 11)
+    p1, p2 = plan.displace_delta(0.8, to_dev(dx, cfg.dtype))
+    torch.cuda.synchronize()
+    m = oracle_model(cfg)
+    dk = torch.fft.rfftn(torch.from_numpy(dx))
+    r1, r2 = fields.displace_from_delta_k(dk, m, 0.8, _tables(m, 0.8))
+    e1, e2 = normwise(p1, r1), normwise(p2, r2)
+    print(f"  psi1 {e1:.3e} psi2 {e2:.3e}", flush=True)
+    assert e1 < tol and e2 < tol
+
+
+def test_displace_delta_plane_wave_closed_form():
+    # delta = A cos(k.x): psi1 = -A D1 k/k^2 sin(k.x) exactly and psi2 = 0
+    print("displace from one plane wave", flush=True)
+    n, box = 16, 32.0
+    plan, cfg = _plan(n=n, box=box, gravity="gr", factorisation="eds")
+    c = np.arange(n)
+    X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
+    mvec = np.array([1, 2, -1])
+    ph = 2 * np.pi * (mvec[0] * X + mvec[1] * Y + mvec[2] * Z) / n
+    A = 0.01
+    p1, p2 = plan.displace_delta(1.0, to_dev(A * np.cos(ph), torch.float64))
+    _, d1, _ = plan.growth_table(1.0)
+    kv = 2 * np.pi / box * mvec
+    ref = np.stack([-A * d1[0] * kv[i] / (kv @ kv) * np.sin(ph) for i in range(3)])
+    assert normwise(p1, ref) < 1e-12
+    assert float(p2.abs().max()) < 1e-13 * float(p1.abs().max())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_positions_match_oracle(prec):
+    print(f"positions {prec}", flush=True)
+    n = 32
+    plan, cfg = _plan(precision=prec, n=n, box=64.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1",
+                      nk_growth=64)
+    p1, p2 = plan.displace(1.0, to_dev(white_noise(n, 2), cfg.dtype))
+    x = plan.positions(p1, p2)
+    torch.cuda.synchronize()
+    m = oracle_model(cfg)
+    ref = fields.positions(p1.double().cpu(), p2.double().cpu(), m)
+    d = (x.double().cpu() - ref).abs()
+    d = torch.minimum(d, cfg.box - d)          # periodic distance
+    tol = 1e-12 * cfg.box if prec == "fp64" else 1e-6 * cfg.box
+    assert float(d.max()) < tol
+    assert float(x.min()) >= 0.0 and float(x.max()) < cfg.box
+
+
+def test_auto_factorisation_plan():
+    print("AUTO factorisation plan", flush=True)
+    from paper_1909_06282_amd import LPT2Error, Plan
+    n = 64
+    kw = dict(n=n, box=256.0, gravity="fr_hs", fr0_abs=1e-4, nk_growth=64)
+    plan, cfg = _plan(factorisation="auto", **kw)
+    w = white_noise(n, 5)
+    wd = to_dev(w, torch.float64)
+    assert plan.auto_choice(0, 1.0) is None
+    p1, p2 = plan.displace(1.0, wd)
+    name = plan.auto_choice(0, 1.0)
+    m = oracle_model(gpu_config(factorisation="t1", **kw))
+    tab = _tables(m, 1.0)
+    km, cnt, mean, _ = mgsource.source_ratio(w, m, 1.0, n // 2, tab)
+    best, _ = mgsource.choose_triangle(km, cnt, mean, m, 1.0, 0.4, tab)
+    print(f"  AUTO chose {name} (oracle {best})", flush=True)
+    assert name == best
+    from paper_1909_06282_amd import factorisation_candidate
+    names = [factorisation_candidate(i)[0] for i in range(8)]
+    _, r, th, win = factorisation_candidate(names.index(name))
+    fk = dict(factorisation="winther") if win else (dict(factorisation="t1") if (r == 1.0 and th == 90.0) else
+                                                    dict(factorisation="triangle", tri_ratio=r, tri_theta_deg=th))
+    ref = Plan(gpu_config(**kw, **fk))
+    q1, q2 = ref.displace(1.0, wd)
+    torch.cuda.synchronize()
+    assert torch.equal(p1, q1)
+    assert normwise(p2, q2) < 1e-14     # T1 and a triangle at (1, 90) differ only in rounding
+    with pytest.raises(LPT2Error):      # no choice at a = 0.5 yet
+        plan.growth_table(0.5)
+    with pytest.raises(LPT2Error):
+        plan.displace_delta(0.5, wd)
+
+
 # ---------------------------------------------------------------- source spectrum
 @pytest.mark.parametrize("n,nbins", [(16, 8), (32, 16), (64, 32)])
 def test_source_power_spectrum_matches_oracle(n, nbins):
