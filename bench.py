@@ -132,6 +132,63 @@ def batched(steps: int, warmup: int):
             "kernels_eager": prof}
 
 
+def _timed(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def adjoint_timing(reps: int):
+    """The adjoint workload: 128^3 (L=256) f(R) |f_R0|=1e-5 FP32; loss = sum of
+    squared residuals of the CIC density against the density of seed 7; one
+    step = forward (displace, paint, loss) + backward (paint transpose,
+    lpt2_backward) for the noise of seed 1."""
+    import numpy as np
+    import torch
+    from paper_1909_06282_amd import Displace, LPT2Config, PaintCIC, Plan
+    from seeded_inputs import white_noise
+    plan = Plan(LPT2Config(n=128, box=256.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", precision="fp32"))
+    with torch.no_grad():
+        t1, t2 = plan.displace(1.0, torch.from_numpy(white_noise(128, 7, np.float32)).cuda())
+        target = plan.paint_cic(t1, t2).clone()
+    w = torch.from_numpy(white_noise(128, 1, np.float32)).cuda().requires_grad_(True)
+
+    def step():
+        w.grad = None
+        p1, p2 = Displace.apply(w, plan, 1.0)
+        loss = ((PaintCIC.apply(p1, p2, plan) - target) ** 2).sum()
+        loss.backward()
+
+    g1 = torch.randn((3, 128, 128, 128), device="cuda")
+    g2 = torch.randn_like(g1)
+    wd = w.detach()
+    return {"workload": "128^3 (L=256) f(R) |f_R0|=1e-5 FP32, CIC loss against seed 7, gradient for seed 1",
+            "ms_loss_and_gradient": round(_timed(step, reps), 4),
+            "ms_displace": round(_timed(lambda: plan.displace(1.0, wd), reps), 4),
+            "ms_backward": round(_timed(lambda: plan.backward(1.0, wd, g1, g2), reps), 4)}
+
+
+def choice_timing(reps: int):
+    """The factorisation choice at 256^3 (L=512) f(R) |f_R0|=1e-5 FP32, 128
+    shells: the full MG source, its ratio to the GR source, the fit."""
+    import numpy as np
+    import torch
+    from paper_1909_06282_amd import LPT2Config, Plan
+    from seeded_inputs import white_noise
+    plan = Plan(LPT2Config(n=256, box=512.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", precision="fp32"))
+    w = torch.from_numpy(white_noise(256, 1, np.float32)).cuda()
+    name = plan.choose_factorisation(1.0, w, nbins=128)[0]
+    return {"workload": "256^3 (L=512) f(R) |f_R0|=1e-5 FP32, 128 shells, k <= 0.4 h/Mpc", "chosen": name,
+            "ms_ratio_spectrum": round(_timed(lambda: plan.source_spectrum(1.0, w, 128, "ratio"), reps), 3),
+            "ms_power_spectrum": round(_timed(lambda: plan.source_spectrum(1.0, w, 128, "power"), reps), 3),
+            "ms_choice": round(_timed(lambda: plan.choose_factorisation(1.0, w, nbins=128), reps), 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +197,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 companion measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-mix measurement")
+    ap.add_argument("--no-extra", action="store_true", help="skip the adjoint and factorisation-choice timings")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -281,6 +339,11 @@ def main():
     if not args.no_batch:
         out["batched"] = batched(max(8, args.steps // 2), 3)
         torch.cuda.empty_cache()
+    if not args.no_extra:
+        out["adjoint"] = adjoint_timing(8)
+        out["factorisation_choice"] = choice_timing(3)
+        torch.cuda.empty_cache()
+    out["numpy"] = np.__version__
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(*combos[0][:1], 1.0, 1)
     print(json.dumps(out), flush=True)

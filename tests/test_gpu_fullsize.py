@@ -1,7 +1,8 @@
 """Parity at the workload sizes, in the launch configuration bench.py times.
 
   * C2: 256^3, L = 512, |f_R0| = 1e-5, z = 0: FP64 <= 1e-12 and FP32 <= 1e-5
-    against the full FP64 oracle; the 128-bin source spectrum;
+    against the full FP64 oracle; the 128-bin source spectrum; the 128-bin
+    S_MG/S_GR spectrum and the factorisation choice;
   * C3: 512^3, L = 1024, FP32 against the full FP64 oracle (one seed per
     (|f_R0|, z) corner is too slow for the oracle; seed 1 at F6 z = 0 and F4
     z = 1 are checked);
@@ -17,7 +18,7 @@ import pytest
 import torch
 
 import oracle
-from oracle import adjoint, cic, fields, growth, spectrum
+from oracle import adjoint, cic, fields, growth, mgsource, spectrum
 from seeded_inputs import cell_sample, white_noise
 from tests._util import gpu_config, normwise, oracle_model, to_dev
 
@@ -75,6 +76,31 @@ def test_c2_source_spectrum_128_bins():
     assert np.max(np.abs(got["mean"][nz] / mean[nz] - 1)) < 1e-10
     assert np.max(np.abs(got["std"][nz] / std[nz] - 1)) < 1e-8
     plan.close()
+
+
+def test_c2_source_ratio_and_factorisation_choice():
+    # the factorisation choice at the workload size: binned S_MG/S_GR in 128
+    # shells and the candidate fit against the oracle's on the same noise
+    print("C2 ratio spectrum and choice", flush=True)
+    plan, cfg = _plan(precision="fp64", **C2)
+    w = white_noise(cfg.n, 1)
+    wd = to_dev(w, torch.float64)
+    got = plan.source_spectrum(1.0, wd, 128, "ratio")
+    name, costs = plan.choose_factorisation(1.0, wd, nbins=128, kcut=0.4)
+    plan.close()
+    m = oracle_model(cfg)
+    tab = growth.tables(m, 1.0)
+    km, cnt, mean, std = mgsource.source_ratio(w, m, 1.0, 128, tab)
+    best, ocosts = mgsource.choose_triangle(km, cnt, mean, m, 1.0, 0.4, tab)
+    assert np.array_equal(got["count"], cnt)
+    nz = cnt > 0
+    err = np.max(np.abs(got["mean"][nz] - mean[nz]))
+    print(f"  ratio means max |gpu - oracle| {err:.3e}; chosen {name} (oracle {best})", flush=True)
+    print("  costs " + ", ".join(f"{k} {v:.6g}" for k, v in sorted(ocosts.items(), key=lambda kv: kv[1])), flush=True)
+    assert err < 1e-10
+    assert name == best
+    for k, v in ocosts.items():
+        assert abs(costs[k] - v) <= 1e-8 * max(1.0, abs(v)), k
 
 
 @pytest.mark.parametrize("fr0,z", [(1e-6, 0.0), (1e-4, 1.0)])
