@@ -173,6 +173,30 @@ def adjoint_timing(reps: int):
             "ms_backward": round(_timed(lambda: plan.backward(1.0, wd, g1, g2), reps), 4)}
 
 
+def epochs_timing(reps: int):
+    """Four output times (z = 0, 0.5, 1, 2) of one 512^3 realisation (L=1024,
+    |f_R0|=1e-6, FP32, seed 1) from one source, against four separate
+    lpt2_displace calls."""
+    import numpy as np
+    import torch
+    from paper_1909_06282_amd import LPT2Config, Plan
+    from seeded_inputs import white_noise
+    plan = Plan(LPT2Config(n=N, box=BOX, gravity="fr_hs", fr0_abs=1e-6, factorisation="t1", precision="fp32"))
+    w = torch.from_numpy(white_noise(N, 1, np.float32)).cuda()
+    a_list = [1.0, 1 / 1.5, 0.5, 1 / 3.0]
+    o1 = [[torch.empty((3, N, N, N), dtype=torch.float32, device="cuda")] for _ in a_list]
+    o2 = [[torch.empty((3, N, N, N), dtype=torch.float32, device="cuda")] for _ in a_list]
+    t_ep = _timed(lambda: plan.displace_epochs(a_list, w, o1, o2), reps)
+
+    def separate():
+        for j, a in enumerate(a_list):
+            plan.displace(a, w, o1[j][0], o2[j][0])
+    t_sep = _timed(separate, reps)
+    return {"workload": "512^3 (L=1024) |f_R0|=1e-6 FP32 seed 1 at z = 0, 0.5, 1, 2", "epochs": len(a_list),
+            "ms_epochs_call": round(t_ep, 3), "ms_separate_calls": round(t_sep, 3),
+            "value": len(a_list) * float(N) ** 3 / (t_ep / 1e3), "unit": "grid-cells/s"}
+
+
 def choice_timing(reps: int):
     """The factorisation choice at 256^3 (L=512) f(R) |f_R0|=1e-5 FP32, 128
     shells: the full MG source, its ratio to the GR source, the fit."""
@@ -342,6 +366,8 @@ def main():
     if not args.no_extra:
         out["adjoint"] = adjoint_timing(8)
         out["factorisation_choice"] = choice_timing(3)
+        torch.cuda.empty_cache()
+        out["epochs"] = epochs_timing(4)
         torch.cuda.empty_cache()
     out["numpy"] = np.__version__
     if not args.no_cpu:

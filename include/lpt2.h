@@ -142,6 +142,20 @@ lpt2_status lpt2_realisation_info(lpt2_plan_t plan, int r, int* n, int* precisio
 lpt2_status lpt2_displace(lpt2_plan_t plan, double a, const void* const* noise,
                           void* const* psi1, void* const* psi2, void* stream);
 
+/* Several output times from one source (Sec. 2.4: the factorised D2 makes
+ * S(k) independent of a).  psi1 and psi2 at each of a[0..n_a) for every
+ * realisation: the full chain runs once at a[0]; for a[1..] only the
+ * first-order x pass (from the kept F[w]) and the second-order x pass (from
+ * the kept F[S]) run again with that epoch's growth tables, with their y
+ * and z passes.  Outputs are epoch-major: psi1[j * R + r] is realisation r
+ * at a[j] (R = lpt2_realisations), [3][n][n][n] device arrays as in
+ * lpt2_displace, whose results they equal.  n_a in 1..LPT2_MAX_EPOCHS.
+ * Eager only (graph mode does not apply); growth tables as lpt2_displace. */
+#define LPT2_MAX_EPOCHS 16
+lpt2_status lpt2_displace_epochs(lpt2_plan_t plan, int n_a, const double* a,
+                                 const void* const* noise, void* const* psi1,
+                                 void* const* psi2, void* stream);
+
 /* Graph mode on (enable != 0) or off.  In graph mode lpt2_displace captures
  * its launches (all grids and batches, with their fork and join) into a
  * hipGraph on a stream of the plan, instantiates it, caches it under

@@ -47,6 +47,7 @@ EXPORTS = [
     "lpt2_strerror", "lpt2_last_error", "lpt2_set_graph", "lpt2_get_tiles", "lpt2_set_tiles",
     "lpt2_tile_options", "lpt2_autotune", "lpt2_factorisation_candidates", "lpt2_factorisation_candidate",
     "lpt2_choose_factorisation", "lpt2_auto_choice", "lpt2_displace_delta", "lpt2_positions",
+    "lpt2_displace_epochs",
 ]
 
 _lib = None
@@ -95,6 +96,7 @@ def load() -> C.CDLL:
     L.lpt2_auto_choice.argtypes = [plan_t, C.c_int, C.c_double, ip]
     L.lpt2_displace_delta.argtypes = [plan_t, C.c_double, vp, vp, vp, vp]
     L.lpt2_positions.argtypes = [plan_t, C.c_int, vp, vp, vp, vp]
+    L.lpt2_displace_epochs.argtypes = [plan_t, C.c_int, dp, vpp, vpp, vpp, vp]
     L.lpt2_strerror.argtypes = [C.c_int]
     L.lpt2_strerror.restype = C.c_char_p
     L.lpt2_last_error.argtypes = [plan_t]
@@ -104,7 +106,7 @@ def load() -> C.CDLL:
                  "lpt2_growth_table", "lpt2_fft3d", "lpt2_profile_enable", "lpt2_profile_reset",
                  "lpt2_profile_get", "lpt2_set_graph", "lpt2_get_tiles", "lpt2_set_tiles", "lpt2_tile_options",
                  "lpt2_autotune", "lpt2_factorisation_candidate", "lpt2_choose_factorisation", "lpt2_auto_choice",
-                 "lpt2_displace_delta", "lpt2_positions"):
+                 "lpt2_displace_delta", "lpt2_positions", "lpt2_displace_epochs"):
         getattr(L, name).restype = C.c_int
     L.lpt2_realisations.restype = C.c_int
     L.lpt2_profile_count.restype = C.c_int

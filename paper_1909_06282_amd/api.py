@@ -151,6 +151,39 @@ class Plan:
                                            _stream(stream)), self.handle)
         return (psi1[0], psi2[0]) if single else (psi1, psi2)
 
+    def displace_epochs(self, a_list, noise, psi1=None, psi2=None, stream=None):
+        """lpt2_displace_epochs: [(psi1, psi2) per a] (lists per realisation for multi-realisation plans)."""
+        single = isinstance(noise, torch.Tensor)
+        noise = self._lists(noise)
+        a_list = [float(x) for x in a_list]
+        R, E = len(self.sizes), len(a_list)
+        if len(noise) != R:
+            raise ValueError(f"plan holds {R} realisations")
+        for w, n in zip(noise, self.sizes):
+            self._check_field(w, (n, n, n), "noise")
+        if psi1 is None:
+            psi1 = [[torch.empty((3, n, n, n), dtype=self.dtype, device=w.device) for w, n in zip(noise, self.sizes)]
+                    for _ in range(E)]
+        if psi2 is None:
+            psi2 = [[torch.empty((3, n, n, n), dtype=self.dtype, device=w.device) for w, n in zip(noise, self.sizes)]
+                    for _ in range(E)]
+        flat1 = [t for per in psi1 for t in self._lists(per)]
+        flat2 = [t for per in psi2 for t in self._lists(per)]
+        if len(flat1) != E * R or len(flat2) != E * R:
+            raise ValueError("psi1/psi2 need one entry per (epoch, realisation)")
+        for i, (p1, p2) in enumerate(zip(flat1, flat2)):
+            n = self.sizes[i % R]
+            self._check_field(p1, (3, n, n, n), "psi1")
+            self._check_field(p2, (3, n, n, n), "psi2")
+        arr = (C.c_double * E)(*a_list)
+        _abi.check(self._lib.lpt2_displace_epochs(self.handle, E, arr, _ptrs(noise), _ptrs(flat1), _ptrs(flat2),
+                                                  _stream(stream)), self.handle)
+        out = []
+        for j in range(E):
+            o1, o2 = flat1[j * R:(j + 1) * R], flat2[j * R:(j + 1) * R]
+            out.append((o1[0], o2[0]) if single else (o1, o2))
+        return out
+
     def set_graph(self, enable: bool = True):
         """lpt2_set_graph: capture lpt2_displace into cached hipGraphs."""
         _abi.check(self._lib.lpt2_set_graph(self.handle, int(bool(enable))), self.handle)

@@ -453,6 +453,8 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
 //   MODE 0: tab = interleaved (PHI, PSI1) per |m|^2;
 //           out 0..2: U_p = F_x^-1[-m_x^p PHI X], out 3..4: V_p = F_x^-1[i m_x^p PSI1 X]
 //   MODE 1: tab = PSI2;  out 0..1: Q_p = F_x^-1[-i m_x^p PSI2 X]
+//   MODE 2: tab = the (PHI, PSI1) pair; out 0..1: V_p (first order only, for
+//           further epochs of the same realisation)
 // DC and Nyquist planes are zero in every output.  The column data are
 // loaded and stored non-temporally, so the table stays in L2 for the gathers
 // (measured 10% faster at n = 512).
@@ -474,9 +476,10 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
   in += blockIdx.y * FIELD;               // realisation blockIdx.y
   out += blockIdx.y * FIELD;
   Cx<T> va[C::E], y[C::E], pf[C::E];
-  // radial factors per slot: MODE 0 the (PHI, PSI1) pair, MODE 1 PSI2 in .x
-  Cx<T> rf[MODE == 0 ? C::E : 1];
-  T rq[MODE == 0 ? 1 : C::E];
+  // radial factors per slot: MODE 0, 2 the (PHI, PSI1) pair, MODE 1 PSI2
+  constexpr bool PAIR = MODE != 1;
+  Cx<T> rf[PAIR ? C::E : 1];
+  T rq[PAIR ? 1 : C::E];
   auto load = [&](long tile) {
     const long col = tile * C::W + c;
     const bool a = col < NCOL;
@@ -506,13 +509,13 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
         const int mx = ix < N / 2 ? ix : ix - N;
         const int n2 = mx * mx + n2yz;
         const bool keep = keep_y && ix != N / 2 && n2 != 0;
-        if constexpr (MODE == 0)
+        if constexpr (PAIR)
           rf[sl] = keep ? reinterpret_cast<const Cx<T>*>(tab)[n2] : zero<T>();
         else
           rq[sl] = keep ? tab[n2] : T(0);
       }
     };
-    constexpr bool EARLY = MODE == 0 || sizeof(T) == 8;
+    constexpr bool EARLY = PAIR || sizeof(T) == 8;
     if (EARLY) gather();
   #pragma unroll
     for (int sl = 0; sl < C::E; ++sl) va[sl] = pf[sl];
@@ -522,20 +525,21 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
     constexpr int NOUT = MODE == 0 ? 5 : 2;
   #pragma unroll 1
     for (int o = 0; o < NOUT; ++o) {
-      // MODE 0: o < 3 -> -m_x^o PHI X ; o = 3, 4 -> i m_x^(o-3) PSI1 X.  MODE 1: -i m_x^o PSI2 X
-      const bool second = MODE == 0 && o >= 3;
-      const int p = second ? o - 3 : o;
+      // MODE 0: o < 3 -> -m_x^o PHI X ; o = 3, 4 -> i m_x^(o-3) PSI1 X.  MODE 1: -i m_x^o PSI2 X.
+      // MODE 2: i m_x^o PSI1 X
+      const bool second = (MODE == 0 && o >= 3) || MODE == 2;
+      const int p = (MODE == 0 && o >= 3) ? o - 3 : o;
   #pragma unroll
       for (int sl = 0; sl < C::E; ++sl) {
         const int ix = slot_elem<C::L, C::E, C::RLF>(t, sl);
         const T f = mpow<T>(ix < N / 2 ? ix : ix - N, p);
         T r;
-        if constexpr (MODE == 0)
+        if constexpr (PAIR)
           r = second ? rf[sl].y : rf[sl].x;
         else
           r = rq[sl];
         const Cx<T> a = scale(va[sl], r);
-        if (MODE == 0)
+        if (PAIR)
           y[sl] = second ? mk(-a.y * f, a.x * f) : mk(-a.x * f, -a.y * f);
         else
           y[sl] = mk(a.y * f, -a.x * f);
@@ -895,14 +899,18 @@ static hipError_t xdisp_w(int nr, int mode, const void* in, void* out, long fso,
   const long ntiles = ((long)N * (N / 2) + C::W - 1) / C::W;  // per realisation
   static const long r0 = resident_blocks(reinterpret_cast<const void*>(&k_xdisp<T, N, WW, 0>), C::BLOCK);
   static const long r1 = resident_blocks(reinterpret_cast<const void*>(&k_xdisp<T, N, WW, 1>), C::BLOCK);
+  static const long r2 = resident_blocks(reinterpret_cast<const void*>(&k_xdisp<T, N, WW, 2>), C::BLOCK);
   // the resident blocks shared out over the realisations (grid.y)
-  const long per = ((mode == 0 ? r0 : r1) + nr - 1) / nr;
+  const long per = ((mode == 0 ? r0 : (mode == 1 ? r1 : r2)) + nr - 1) / nr;
   const dim3 grid((unsigned)min_l(per, ntiles), (unsigned)nr);
   if (mode == 0)
     hipLaunchKernelGGL((k_xdisp<T, N, WW, 0>), grid, dim3(C::BLOCK), 0, s, (const Cx<T>*)in, (Cx<T>*)out, fso,
                        (const T*)tab, (const Cx<T>*)tw);
-  else
+  else if (mode == 1)
     hipLaunchKernelGGL((k_xdisp<T, N, WW, 1>), grid, dim3(C::BLOCK), 0, s, (const Cx<T>*)in, (Cx<T>*)out, fso,
+                       (const T*)tab, (const Cx<T>*)tw);
+  else
+    hipLaunchKernelGGL((k_xdisp<T, N, WW, 2>), grid, dim3(C::BLOCK), 0, s, (const Cx<T>*)in, (Cx<T>*)out, fso,
                        (const T*)tab, (const Cx<T>*)tw);
   return hipGetLastError();
 }
@@ -917,14 +925,14 @@ static hipError_t xdisp_t(int w, int nr, int mode, const void* in, void* out, lo
 hipError_t launch_xdisp(int prec, int n, int nr, int mode, const void* in, size_t in_cap, void* out, size_t out_cap,
                         long out_fstride, const void* tab, size_t tab_cap, const void* tw, hipStream_t s, int w) {
   if (w == 0) w = default_width(prec, n, KIND_MULTI);
-  if (!pow2n(n) || !in || !out || !tab || !tw || out_fstride < 0 || (mode != 0 && mode != 1) || nr < 1)
+  if (!pow2n(n) || !in || !out || !tab || !tw || out_fstride < 0 || mode < 0 || mode > 2 || nr < 1)
     return hipErrorInvalidValue;
   const size_t cb = 2 * esize(prec), field = (size_t)nr * n * n * (n / 2);
   const int nout = mode == 0 ? 5 : 2;
   if (field * cb > in_cap || ((size_t)(nout - 1) * out_fstride + field) * cb > out_cap) return hipErrorInvalidValue;
   if (nr > 65535) return hipErrorInvalidValue;  // grid.y
   const size_t n2cnt = 3 * (size_t)(n / 2) * (n / 2) + 1;
-  if (n2cnt * esize(prec) * (mode == 0 ? 2 : 1) > tab_cap) return hipErrorInvalidValue;
+  if (n2cnt * esize(prec) * (mode == 1 ? 1 : 2) > tab_cap) return hipErrorInvalidValue;
 #define CALL(NN) return prec == PREC_F32 ? xdisp_t<float, NN>(w, nr, mode, in, out, out_fstride, tab, tw, s) : xdisp_t<double, NN>(w, nr, mode, in, out, out_fstride, tab, tw, s)
   LPT2_SWITCH_N(n, CALL)
 #undef CALL

@@ -82,7 +82,8 @@ int default_width(int prec, int n, int kind);
 hipError_t launch_ycombo(int prec, int n, int nr, const void* in, size_t in_cap, long in_fstride, void* out,
                          size_t out_cap, long out_fstride, const YOp& op, const void* tw, hipStream_t s, int w = 0);
 // displacement x pass: mode 0 (tab = interleaved PHI, PSI1 per |m|^2; five
-// outputs U0,U1,U2,V0,V1) or mode 1 (tab = PSI2; outputs Q0,Q1).  The table
+// outputs U0,U1,U2,V0,V1), mode 1 (tab = PSI2; outputs Q0,Q1) or mode 2
+// (tab = the PHI, PSI1 pair; outputs V0,V1).  The table
 // is in the working precision (pair: 2 values per |m|^2); tab_cap in bytes.
 // nr realisations one after the other (n^2 (n/2) complex each) in the input
 // and in every output field.

@@ -482,7 +482,7 @@ lpt2_status xdisp(Ctx& c, const char* name, int mode, const void* in, void* out,
   hipStream_t s = c.s;
   Grid& g = c.g;
   const bool f32 = p->prec == PREC_F32;
-  const int row = mode == 0 ? (f32 ? TAB_PAIR32 : TAB_PAIR64) : (f32 ? TAB_PSI2_32 : TAB_PSI2);
+  const int row = mode != 1 ? (f32 ? TAB_PAIR32 : TAB_PAIR64) : (f32 ? TAB_PSI2_32 : TAB_PSI2);
   const void* tab = t->radial + (size_t)row * g.n2cnt;
   const size_t cap = sizeof(double) * (size_t)(TAB_ROWS - row) * g.n2cnt;
   RUN(name, c.fields(mode == 0 ? 6 : 3),
@@ -552,7 +552,8 @@ YOp yop(int nin, int nout, const int* src, const int* pw) {
 // carry the nine fields:  U_p = F_x^-1[-k_x^p A/k^2 X] (p = 0,1,2),
 // V_p = F_x^-1[i k_x^p A D1/k^2 X] (p = 0,1), and e.g.
 // phi_yz = F_z^-1[k_z F_y^-1[k_y U_0]] (integer mode numbers throughout;
-// the (2 pi/L) factors sit in the radial tables).  Slots 0..14.
+// the (2 pi/L) factors sit in the radial tables).  Slots 0..15; on return
+// slot 0 still holds F_zy[w] and slot 15 F_zy[S] (for further epochs).
 lpt2_status displace_batch(Ctx& c, const Tables* t, const void* const* noise, void* const* psi1, void* const* psi2) {
   CHK(fwd_zy(c, "z_r2c_noise", "y_fwd_noise", c.batch(noise, 1), c.field(), c.slot(0)));
   CHK(xdisp(c, "x_fused_psi1_phi", 0, c.slot(0), c.slot(1), t));
@@ -566,11 +567,27 @@ lpt2_status displace_batch(Ctx& c, const Tables* t, const void* const* noise, vo
   // source pass order xx,yy,zz,xy,xz,yz: m_z powers and storage positions
   const int rzs[6] = {0, 0, 2, 0, 1, 1};
   const int fms[6] = {0, 3, 4, 1, 2, 5};
-  CHK(z_source(c, c.slot(9), c.slot(0), rzs, fms));
-  CHK(fwd_y(c, "y_fwd_source", c.slot(0), 1));
-  CHK(xdisp(c, "x_fused_psi2", 1, c.slot(0), c.slot(1), t));
+  CHK(z_source(c, c.slot(9), c.slot(15), rzs, fms));
+  CHK(fwd_y(c, "y_fwd_source", c.slot(15), 1));
+  CHK(xdisp(c, "x_fused_psi2", 1, c.slot(15), c.slot(1), t));
   const int src3[3] = {1, 0, 0};
   const int pw3[3] = {0, 1, 0};
+  CHK(ycombo(c, "y_inv_psi2", c.slot(1), c.slot(3), yop(2, 3, src3, pw3)));
+  CHK(z_c2r(c, "z_c2r_psi2", c.slot(3), c.batch(psi2, 3), 3 * c.field(), rz1));
+  return LPT2_OK;
+}
+
+// A further epoch of the batch whose displace_batch ran last on this context:
+// psi1 and psi2 at the a of `t` from F_zy[w] (slot 0) and F_zy[S] (slot 15),
+// which do not depend on a (the unevolved potential; Sec. 2.4 factorisation).
+lpt2_status epoch_batch(Ctx& c, const Tables* t, void* const* psi1, void* const* psi2) {
+  const int src3[3] = {1, 0, 0};  // V0, V1 (or Q0, Q1) -> x, y, z components
+  const int pw3[3] = {0, 1, 0};
+  const int rz1[3] = {0, 0, 1};
+  CHK(xdisp(c, "x_psi1_epoch", 2, c.slot(0), c.slot(1), t));
+  CHK(ycombo(c, "y_inv_psi1_epoch", c.slot(1), c.slot(3), yop(2, 3, src3, pw3)));
+  CHK(z_c2r(c, "z_c2r_psi1", c.slot(3), c.batch(psi1, 3), 3 * c.field(), rz1));
+  CHK(xdisp(c, "x_fused_psi2", 1, c.slot(15), c.slot(1), t));
   CHK(ycombo(c, "y_inv_psi2", c.slot(1), c.slot(3), yop(2, 3, src3, pw3)));
   CHK(z_c2r(c, "z_c2r_psi2", c.slot(3), c.batch(psi2, 3), 3 * c.field(), rz1));
   return LPT2_OK;
@@ -734,6 +751,48 @@ lpt2_status run_displace(lpt2_plan_t p, const std::vector<Tables*>& tabs, const 
     if (e != hipSuccess && st == LPT2_OK) st = hip_fail(p, e, "fork wait");
     if (st == LPT2_OK) st = run_grid(p, (int)i, tabs[i], noise, psi1, psi2, g.st);
     e = hipEventRecord(g.join, g.st);  // joined also after an error, so a capture can end
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, g.join, 0);
+    if (e != hipSuccess && st == LPT2_OK) st = hip_fail(p, e, "join");
+  }
+  return st;
+}
+
+// every realisation of grid gi at the n_a scale factors: the full chain at
+// a[0], then the epoch chain at a[1..]; psi arrays epoch-major (j * nr + r)
+lpt2_status run_grid_epochs(lpt2_plan_t p, int gi, int n_a, const double* a, const void* const* noise,
+                            void* const* psi1, void* const* psi2, hipStream_t st) {
+  Grid& g = p->grids[gi];
+  const int nr_all = (int)p->rgrid.size();
+  char* base = p->ws + g.ws_off;
+  char* end = base + (size_t)WS_FIELDS * g.bsub * g.n3 * p->es;
+  for (int r0 = 0; r0 < g.count; r0 += g.bsub) {
+    Ctx c{p, g, st, 2 * p->es, base, std::min(g.bsub, g.count - r0), end};
+    const int r = g.rfirst + r0;
+    for (int j = 0; j < n_a; ++j) {
+      Tables* t = nullptr;  // used at once: a later lookup may move the cache
+      CHK(get_tables(p, g, a[j], false, st, &t));
+      const size_t o = (size_t)j * nr_all + r;
+      if (j == 0)
+        CHK(displace_batch(c, t, noise + r, psi1 + o, psi2 + o));
+      else
+        CHK(epoch_batch(c, t, psi1 + o, psi2 + o));
+    }
+  }
+  return LPT2_OK;
+}
+
+lpt2_status run_epochs(lpt2_plan_t p, int n_a, const double* a, const void* const* noise, void* const* psi1,
+                       void* const* psi2, hipStream_t s) {
+  if (p->grids.size() == 1) return run_grid_epochs(p, 0, n_a, a, noise, psi1, psi2, s);
+  hipError_t e = hipEventRecord(p->fork, s);
+  if (e != hipSuccess) return hip_fail(p, e, "fork");
+  lpt2_status st = LPT2_OK;
+  for (size_t i = 0; i < p->grids.size(); ++i) {
+    Grid& g = p->grids[i];
+    e = hipStreamWaitEvent(g.st, p->fork, 0);
+    if (e != hipSuccess && st == LPT2_OK) st = hip_fail(p, e, "fork wait");
+    if (st == LPT2_OK) st = run_grid_epochs(p, (int)i, n_a, a, noise, psi1, psi2, g.st);
+    e = hipEventRecord(g.join, g.st);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, g.join, 0);
     if (e != hipSuccess && st == LPT2_OK) st = hip_fail(p, e, "join");
   }
@@ -1235,6 +1294,25 @@ lpt2_status lpt2_displace(lpt2_plan_t p, double a, const void* const* noise, voi
   hipError_t e = hipGraphLaunch(ge->exec, s);
   if (e != hipSuccess) return hip_fail(p, e, "graph launch");
   return LPT2_OK;
+}
+
+lpt2_status lpt2_displace_epochs(lpt2_plan_t p, int n_a, const double* a, const void* const* noise,
+                                 void* const* psi1, void* const* psi2, void* stream) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  if (n_a < 1 || n_a > LPT2_MAX_EPOCHS || !a) return fail(p, LPT2_EINVAL, "need 1..16 scale factors");
+  for (int j = 0; j < n_a; ++j) CHK(check_a(p, a[j]));
+  if (!noise || !psi1 || !psi2) return fail(p, LPT2_EINVAL, "null pointer array");
+  const int nr = (int)p->rgrid.size();
+  for (int r = 0; r < nr; ++r)
+    if (!noise[r]) return fail(p, LPT2_EINVAL, "null noise pointer for realisation " + std::to_string(r));
+  for (int i = 0; i < n_a * nr; ++i)
+    if (!psi1[i] || !psi2[i]) return fail(p, LPT2_EINVAL, "null output pointer at " + std::to_string(i));
+  hipStream_t s = (hipStream_t)stream;
+  for (int j = 0; j < n_a; ++j)
+    for (auto& g : p->grids) CHK(resolve_auto(p, g, a[j], noise[g.rfirst], s));
+  return run_epochs(p, n_a, a, noise, psi1, psi2, s);
 }
 
 lpt2_status lpt2_set_graph(lpt2_plan_t p, int enable) {

@@ -190,3 +190,22 @@ def test_autotune_picks_offered_tiles_and_caches_them(tmp_path):
     plan2 = Plan(cfgs, counts=[2, 1])
     assert plan2.autotune(1.0, noise, o1, o2, cache_path=str(cache)) == tiles
     assert cache.read_text().splitlines() == lines
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_epochs_equal_separate_displacements(prec):
+    # the extra epochs reuse F[w] and F[S]; each epoch must equal a
+    # separate lpt2_displace at its a (the same kernels and tables)
+    print(f"epochs 2x16^3 + 1x32^3 {prec}", flush=True)
+    plan, cfgs, per, noise = _mixed(prec, counts=(2, 1))
+    a_list = [1.0, 0.5, 0.25, 2.0 / 3.0]
+    outs = plan.displace_epochs(a_list, noise)
+    torch.cuda.synchronize()
+    for j, a in enumerate(a_list):
+        q1, q2 = plan.displace(a, noise)
+        torch.cuda.synchronize()
+        for i in range(len(noise)):
+            assert torch.equal(outs[j][0][i], q1[i]) and torch.equal(outs[j][1][i], q2[i]), (j, i)
+    from paper_1909_06282_amd import LPT2Error
+    with pytest.raises(LPT2Error):
+        plan.displace_epochs([1.0] * 17, noise)
