@@ -199,6 +199,18 @@ lpt2_status lpt2_autotune(lpt2_plan_t plan, double a, const void* const* noise,
 lpt2_status lpt2_displace_delta(lpt2_plan_t plan, double a, const void* delta, void* psi1,
                                 void* psi2, void* stream);
 
+/* Matter power spectrum of the displaced particles of realisation 0: their
+ * cloud-in-cell density (as lpt2_paint_cic) is transformed on the grid and
+ * q = V |F[delta]/n^3|^2 is binned in nbins shells as in
+ * lpt2_source_spectrum (integer-exact shells of width k_Nyq/nbins, DC and
+ * modes at or beyond k_Nyq left out).  deconvolve != 0 divides each mode by
+ * W^2, W = prod_i sinc^2(pi m_i / n) the CIC window.  No interlacing.  Host
+ * arrays of nbins values; the float atomics of the painting make the last
+ * bits vary from run to run.  nbins in 1..512.  Synchronises. */
+lpt2_status lpt2_matter_power(lpt2_plan_t plan, const void* psi1, const void* psi2, int nbins,
+                              int deconvolve, double* k_mean, double* count, double* mean,
+                              double* std_dev, void* stream);
+
 /* Eulerian particle positions (eq. position): x = (q + psi1 + psi2) mod L for
  * the particles of realisation r's grid, q = (ix, iy, iz) L/n; psi1, psi2
  * and pos are [3][n][n][n] device arrays in the plan's precision (pos may

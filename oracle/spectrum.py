@@ -73,3 +73,22 @@ def source_power(sk, m: Model, nbins: int):
     s = sk.detach().numpy() if hasattr(sk, "detach") else np.asarray(sk)
     q = m.volume * np.abs(s / m.n ** 3) ** 2
     return bin_shells(q, m, nbins)
+
+
+def cic_window(m: Model) -> np.ndarray:
+    """Fourier window of cloud-in-cell assignment on the half spectrum:
+    W(m) = prod_i sinc^2(pi m_i / n), the transform of the linear (triangle)
+    kernel along each axis (sinc x = sin x / x)."""
+    mx, my, mz = modes(m.n)
+    return (np.sinc(mx / m.n) * np.sinc(my / m.n) * np.sinc(mz / m.n)) ** 2
+
+
+def matter_power(delta, m: Model, nbins: int, deconvolve: bool = False):
+    """Shell-averaged power of a real density contrast on the grid,
+    q = V |F[delta]/n^3|^2, optionally divided by the CIC window squared."""
+    d = delta.detach().numpy() if hasattr(delta, "detach") else np.asarray(delta)
+    dk = np.fft.rfftn(np.asarray(d, dtype=np.float64))
+    q = m.volume * np.abs(dk / m.n ** 3) ** 2
+    if deconvolve:
+        q = q / cic_window(m) ** 2
+    return bin_shells(q, m, nbins)

@@ -169,8 +169,16 @@ __global__ __launch_bounds__(256) void k_bin1(const Cx<T>* __restrict__ A, const
         const Cx<T> a = A[line * M + iz];
         double q = 0.0;
         bool ok = true;
-        if (quantity == 0) {
+        if (quantity == 0 || quantity == 2) {
           q = qscale * ((double)a.x * (double)a.x + (double)a.y * (double)a.y);
+          if (quantity == 2) {  // divided by the squared CIC window prod_i sinc^2(pi m_i / N)
+            const double h = kPi / (double)N;
+            const double sx = mx == 0 ? 1.0 : sin(h * (double)mx) / (h * (double)mx);
+            const double sy = my == 0 ? 1.0 : sin(h * (double)my) / (h * (double)my);
+            const double sz = iz == 0 ? 1.0 : sin(h * (double)iz) / (h * (double)iz);
+            const double w = sx * sx * sy * sy * sz * sz;
+            q /= w * w;
+          }
         } else {
           const Cx<T> bb = B[line * M + iz];
           const double den = (double)bb.x * (double)bb.x + (double)bb.y * (double)bb.y;
@@ -257,9 +265,10 @@ static hipError_t bin_t(const void* A, const void* B, int quantity, double qscal
 
 hipError_t launch_bin(int prec, int n, const void* A, size_t a_cap, const void* B, size_t b_cap, int quantity,
                       double qscale, int nbins, double kf, double* partial, double* out4, hipStream_t s) {
-  if (nbins < 1 || nbins > BIN_MAXBINS || !A || !partial || !out4) return hipErrorInvalidValue;
+  if (nbins < 1 || nbins > BIN_MAXBINS || !A || !partial || !out4 || quantity < 0 || quantity > 2)
+    return hipErrorInvalidValue;
   const size_t field = (size_t)n * n * (n / 2) * 2 * (prec == PREC_F32 ? 4 : 8);
-  if (a_cap < field || (quantity != 0 && (!B || b_cap < field))) return hipErrorInvalidValue;
+  if (a_cap < field || (quantity == 1 && (!B || b_cap < field))) return hipErrorInvalidValue;
 #define CALL(NN)                                                                                      \
   return prec == PREC_F32 ? bin_t<float, NN>(A, B, quantity, qscale, nbins, kf, partial, out4, s)     \
                           : bin_t<double, NN>(A, B, quantity, qscale, nbins, kf, partial, out4, s)

@@ -137,7 +137,8 @@ hipError_t launch_radial(const RadialSetup& r, const double* d1n, const double* 
                          hipStream_t s);
 
 // deterministic shell binner: quantity 0 power (q = qscale |A|^2), 1 ratio
-// (q = Re(A conj B)/|B|^2 where |B| > 0).  partial: [nblk][nbins][4].
+// (q = Re(A conj B)/|B|^2 where |B| > 0), 2 power divided by the squared
+// CIC window.  partial: [nblk][nbins][4].
 constexpr int BIN_BLOCKS = 512;
 constexpr int BIN_MAXBINS = 512;
 hipError_t launch_bin(int prec, int n, const void* A, size_t a_cap, const void* B, size_t b_cap, int quantity,

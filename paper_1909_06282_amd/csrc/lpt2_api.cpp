@@ -1475,6 +1475,40 @@ lpt2_status lpt2_displace_delta(lpt2_plan_t p, double a, const void* delta, void
   return displace_batch(c, t, in, o1, o2);
 }
 
+lpt2_status lpt2_matter_power(lpt2_plan_t p, const void* psi1, const void* psi2, int nbins, int deconvolve,
+                              double* k_mean, double* count, double* mean, double* std_dev, void* stream) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  if (!psi1 || !psi2 || !k_mean || !count || !mean || !std_dev) return fail(p, LPT2_EINVAL, "null pointer");
+  if (nbins < 1 || nbins > BIN_MAXBINS) return fail(p, LPT2_EINVAL, "nbins must be in 1..512");
+  hipStream_t s = (hipStream_t)stream;
+  Grid& g = p->grids[p->rgrid[0]];
+  Ctx c{p, g, s, 2 * p->es, p->ws, 1};
+  // CIC density into slot 0 (as a real field), its 3D forward transform in place, the shells
+  RUN("cic_paint", 7.0 * (double)c.field(), launch_cic(p->prec, g.n, g.cfg.box, psi1, psi2, c.slot(0), s));
+  CHK(fwd_zy(c, "z_r2c_density", "y_fwd_density", c.one(c.slot(0), 1), c.cap(c.slot(0)), c.slot(0)));
+  RUN("x_fwd_density", 2.0 * (double)c.field(),
+      launch_colfft(p->prec, g.n, -1, c.slot(0), c.cap(c.slot(0)), 1, 0, (int)(g.n * g.m), g.n * g.m, g.tw, s,
+                    g.tiles[0]));
+  const double n3 = (double)g.n3, kf = 2.0 * kPi / g.cfg.box;
+  const double qs = g.cfg.box * g.cfg.box * g.cfg.box / (n3 * n3);
+  RUN("shell_bin", 0.0,
+      launch_bin(p->prec, g.n, c.slot(0), c.cap(c.slot(0)), nullptr, 0, deconvolve ? 2 : 0, qs, nbins, kf,
+                 p->bin_partial, p->bin_out, s));
+  std::vector<double> h(4 * (size_t)nbins);
+  hipError_t e = hipMemcpyAsync(h.data(), p->bin_out, sizeof(double) * 4 * nbins, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(p, e, "spectrum readback");
+  for (int i = 0; i < nbins; ++i) {
+    k_mean[i] = h[i];
+    count[i] = h[nbins + i];
+    mean[i] = h[2 * nbins + i];
+    std_dev[i] = h[3 * nbins + i];
+  }
+  return LPT2_OK;
+}
+
 lpt2_status lpt2_positions(lpt2_plan_t p, int r, const void* psi1, const void* psi2, void* pos, void* stream) {
   if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
   if (r < 0 || r >= (int)p->rgrid.size()) return fail(p, LPT2_EINVAL, "realisation index out of range");

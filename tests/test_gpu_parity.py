@@ -209,6 +209,27 @@ def test_positions_match_oracle(prec):
     assert float(x.min()) >= 0.0 and float(x.max()) < cfg.box
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+@pytest.mark.parametrize("deconvolve", [False, True])
+def test_matter_power_matches_oracle(prec, tol, deconvolve):
+    # the same displacements on both sides: CIC paint, FFT, shells
+    print(f"matter power {prec} deconvolve={deconvolve}", flush=True)
+    n, nb = 32, 16
+    plan, cfg = _plan(precision=prec, n=n, box=64.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1",
+                      nk_growth=64)
+    p1, p2 = plan.displace(1.0, to_dev(white_noise(n, 4), cfg.dtype))
+    got = plan.matter_power(p1, p2, nb, deconvolve)
+    m = oracle_model(cfg)
+    d = cic.paint(p1.double().cpu() + p2.double().cpu(), m)
+    km, cnt, mean, std = spectrum.matter_power(d, m, nb, deconvolve)
+    assert np.array_equal(got["count"], cnt)
+    nz = cnt > 0
+    err = np.max(np.abs(got["mean"][nz] / mean[nz] - 1))
+    print(f"  max relative bin error {err:.3e}", flush=True)
+    assert err < tol
+    assert np.max(np.abs(got["k_mean"][nz] / km[nz] - 1)) < 1e-12
+
+
 def test_auto_factorisation_plan():
     print("AUTO factorisation plan", flush=True)
     from paper_1909_06282_amd import LPT2Error, Plan

@@ -136,3 +136,33 @@ def test_fr_source_ratio_close_to_t1():
     assert np.all(rw > mean[sel]) and np.max(rw / mean[sel] - 1) < 0.06
     best, costs = mgsource.choose_triangle(km, cnt, mean, m, a, tab=tab)
     assert best == "T1"
+
+
+def test_matter_power_parseval_on_band_limited_field():
+    # sum over shells of count * mean / V equals the variance of a field whose
+    # modes all lie inside the shells (a few plane waves below k_Nyq)
+    m = oracle.Model(n=16, box=40.0)
+    c = np.arange(16)
+    X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
+    d = (0.3 * np.cos(2 * np.pi * (X + 2 * Y) / 16) + 0.2 * np.sin(2 * np.pi * (3 * Z - Y) / 16 + 0.4)
+         + 0.1 * np.cos(2 * np.pi * (2 * X + Y + Z) / 16 + 1.1))
+    km, cnt, mean, std = spectrum.matter_power(d, m, 8)
+    assert abs(np.sum(cnt * mean) / m.volume - np.mean(d * d)) < 1e-14
+    # the power sits in the shells of |m| = sqrt(5), sqrt(10), sqrt(6) (dk = k_Nyq / 8 = 1 mode unit)
+    occupied = set(np.nonzero(mean > 1e-12)[0])
+    assert occupied == {2, 3}
+
+
+def test_cic_window_is_the_transform_of_the_linear_kernel():
+    # W per axis (the amplitude window: the power is divided by W^2) against a
+    # quadrature of the triangle kernel's Fourier integral, in cell units
+    m = oracle.Model(n=16, box=16.0)
+    x = np.linspace(-1.0, 1.0, 200001)
+    tri = 1.0 - np.abs(x)
+    for mm in range(0, 9):
+        k = 2 * np.pi * mm / 16
+        ft = np.trapezoid(tri * np.cos(k * x), x)
+        w = spectrum.cic_window(oracle.Model(n=16, box=16.0))
+        mx, my, mz = oracle.fields.modes(16)
+        got = w[mm % 16, 0, 0] if mm < 8 else w[mm - 16, 0, 0]
+        assert abs(got - ft) < 1e-9, mm
