@@ -76,7 +76,7 @@ typedef enum {
 typedef enum { LPT2_SPEC_POWER = 0, LPT2_SPEC_RATIO = 1 } lpt2_spec_quantity;
 
 typedef struct {
-  int    n;               /* cells per side: a power of two, 8..512            */
+  int    n;               /* cells per side: 2^k in 8..512 or 3*2^k in 24..768 */
   double box;             /* side length L in Mpc/h, > 0                       */
   double omega_m;         /* flat background: Omega_L = 1 - Omega_m           */
   double h;               /* BBKS shape parameter Gamma = Omega_m h            */
@@ -102,7 +102,8 @@ void lpt2_config_default(lpt2_config* cfg);
 
 /* Create a plan for n_cfgs grid configurations; counts[i] >= 1 realisations
  * of cfgs[i] (counts may be NULL for one realisation each).  Validates every
- * field on the host before any device work: n not a power of two in 8..512,
+ * field on the host before any device work: n neither a power of two in
+ * 8..512 nor three times one in 24..768 (the paper's 768^3 grid),
  * hs_n != 1 or an unknown precision -> LPT2_EUNSUPPORTED; box <= 0,
  * fr0_abs <= 0 for f(R), bad growth grid or null out -> LPT2_EINVAL.
  * Allocates, on the current device, the twiddles and a workspace of 16

@@ -143,8 +143,9 @@ template <typename T, int N>
 __global__ __launch_bounds__(256) void k_bin1(const Cx<T>* __restrict__ A, const Cx<T>* __restrict__ B, int quantity,
                                               double qscale, int nbins, double kf, double* __restrict__ partial) {
   constexpr int M = N / 2;
-  constexpr int CH = M < 64 ? M : 64;
+  constexpr int CH = M <= 64 ? M : (M % 64 == 0 ? 64 : 48);  // chunk of a line: divides M
   constexpr int CPL = M / CH;  // chunks per line
+  static_assert(M % CH == 0, "a line must split into whole chunks");
   __shared__ double hist[4][BIN_MAXBINS][4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int i = threadIdx.x; i < 4 * BIN_MAXBINS * 4; i += blockDim.x) (&hist[0][0][0])[i] = 0.0;
@@ -275,6 +276,8 @@ hipError_t launch_bin(int prec, int n, const void* A, size_t a_cap, const void* 
   switch (n) {
     case 8: CALL(8); case 16: CALL(16); case 32: CALL(32); case 64: CALL(64);
     case 128: CALL(128); case 256: CALL(256); case 512: CALL(512);
+    case 24: CALL(24); case 48: CALL(48); case 96: CALL(96); case 192: CALL(192);
+    case 384: CALL(384); case 768: CALL(768);
     default: return hipErrorInvalidValue;
   }
 #undef CALL

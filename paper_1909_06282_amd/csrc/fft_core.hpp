@@ -1,8 +1,9 @@
 // Register/LDS Stockham FFT engine shared by the axis-pass kernels.
 //
-// One transform of length L (a power of two, 4..512) is carried by L/E
-// threads, each holding E complex values in registers.  A stage of radix R
-// (R in {4, 8}, R divides E) runs E/R butterflies per thread; between stages
+// One transform of length L (a power of two, 4..512, or three times one,
+// 12..384) is carried by L/E threads, each holding E complex values in
+// registers.  A stage of radix R (R in {2, 3, 4, 8}, R divides E) runs E/R
+// butterflies per thread; between stages
 // the values go through LDS once (write in the stage's output order, read in
 // the next stage's input order).  The Stockham ordering needs no bit
 // reversal: after the last stage thread t holds, in slot u*R+q, element
@@ -22,12 +23,19 @@
 namespace lpt2 {
 
 // ---- radix plans -----------------------------------------------------------
+// Lengths 2^k (4..512): radix-8/4 stages, 8 values per thread.
+// Lengths 3 * 2^k (12..384): one radix-3 stage first, then radix 4 (and one
+// radix 2 where the power of two is odd), 12 values per thread.
+constexpr bool is_pow2(int L) { return L > 0 && (L & (L - 1)) == 0; }
+constexpr int log2i(int L) { return L <= 1 ? 0 : 1 + log2i(L / 2); }
 constexpr int plan_stages(int L) {
-  return L == 4 ? 1 : L == 8 ? 1 : L == 16 ? 2 : L == 32 ? 2 : L == 64 ? 2 : L == 128 ? 3 : L == 256 ? 3 : 3;
+  return is_pow2(L) ? (L == 4 ? 1 : L == 8 ? 1 : L == 16 ? 2 : L == 32 ? 2 : L == 64 ? 2 : 3)
+                    : 1 + log2i(L / 3) / 2 + (log2i(L / 3) % 2);
 }
 // radix of forward stage s (0-based)
 constexpr int plan_radix_fwd(int L, int s) {
-  return L == 4     ? (s == 0 ? 4 : 0)
+  return !is_pow2(L)     ? (s == 0 ? 3 : (s >= plan_stages(L) ? 0 : ((log2i(L / 3) % 2) && s == plan_stages(L) - 1 ? 2 : 4)))
+         : L == 4   ? (s == 0 ? 4 : 0)
          : L == 8   ? (s == 0 ? 8 : 0)
          : L == 16  ? (s < 2 ? 4 : 0)
          : L == 32  ? (s == 0 ? 8 : s == 1 ? 4 : 0)
@@ -41,8 +49,16 @@ constexpr int plan_radix(int L, int s, bool inv) {
 }
 constexpr int plan_first(int L, bool inv) { return plan_radix(L, 0, inv); }
 constexpr int plan_last(int L, bool inv) { return plan_radix(L, plan_stages(L) - 1, inv); }
-// elements per thread: 8, except the single radix-4 length
-constexpr int elems_per_thread(int L) { return L == 4 ? 4 : 8; }
+// product of the radices of stages 0..s-1
+constexpr int plan_span(int L, int s, bool inv) { return s <= 0 ? 1 : plan_span(L, s - 1, inv) * plan_radix(L, s - 1, inv); }
+// elements per thread: 8 (12 for lengths 3 * 2^k), except the single radix-4 length
+constexpr int elems_per_thread(int L) { return L == 4 ? 4 : (is_pow2(L) ? 8 : 12); }
+// the plan multiplies out to L and every radix divides E
+constexpr bool plan_ok(int L) {
+  bool ok = plan_span(L, plan_stages(L), false) == L;
+  for (int s = 0; s < plan_stages(L); ++s) ok = ok && elems_per_thread(L) % plan_radix(L, s, false) == 0;
+  return ok;
+}
 
 // Element index held in `slot` of thread t for a pattern of radix R.
 template <int L, int E, int R>
@@ -59,6 +75,25 @@ __device__ __forceinline__ void dft4(Cx<T>& x0, Cx<T>& x1, Cx<T>& x2, Cx<T>& x3)
   x2 = t0 - t2;
   x1 = t1 + t3;
   x3 = t1 - t3;
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void dft2(Cx<T>& x0, Cx<T>& x1) {
+  const Cx<T> t = x0 - x1;
+  x0 = x0 + x1;
+  x1 = t;
+}
+
+// X_j = sum_m x_m w^(jm), w = exp(D 2 pi i / 3) = -1/2 + D i sqrt(3)/2
+template <int D, typename T>
+__device__ __forceinline__ void dft3(Cx<T>& x0, Cx<T>& x1, Cx<T>& x2) {
+  const T h = T(0.86602540378443864676372317075293618347140262690519);  // sqrt(3)/2
+  const Cx<T> s = x1 + x2, d = x1 - x2;
+  const Cx<T> m = mk(x0.x - T(0.5) * s.x, x0.y - T(0.5) * s.y);
+  const Cx<T> r = mk(-T(D) * h * d.y, T(D) * h * d.x);  // D i sqrt(3)/2 (x1 - x2)
+  x0 = x0 + s;
+  x1 = m + r;
+  x2 = m - r;
 }
 
 template <int D, typename T>
@@ -86,9 +121,13 @@ template <int R, int D, typename T>
 __device__ __forceinline__ void butterfly(Cx<T>* x) {
   if constexpr (R == 8) {
     dft8<D>(x);
-  } else {
-    static_assert(R == 4, "radix 4 or 8");
+  } else if constexpr (R == 4) {
     dft4<D>(x[0], x[1], x[2], x[3]);
+  } else if constexpr (R == 3) {
+    dft3<D>(x[0], x[1], x[2]);
+  } else {
+    static_assert(R == 2, "radix 2, 3, 4 or 8");
+    dft2<D>(x[0], x[1]);
   }
 }
 
@@ -103,7 +142,7 @@ __device__ __forceinline__ void stage(Cx<T>* v, int t, const Cx<T>* __restrict__
     Cx<T>* x = v + u * R;
     if constexpr (NS > 1) {
       const int b = t + u * TP;
-      const int k = b & (NS - 1);
+      const int k = (int)((unsigned)b % (unsigned)NS);
       const int step = k * (L / (NS * R)) * tws;
 #pragma unroll
       for (int j = 1; j < R; ++j) {
@@ -166,7 +205,7 @@ __device__ __forceinline__ void exchange(Cx<T>* v, int t, Cx<T>* lb, int pingstr
 #pragma unroll
   for (int u = 0; u < E / ROUT; ++u) {
     const int b = t + u * TP;
-    const int k = b & (NSOUT - 1);
+    const int k = (int)((unsigned)b % (unsigned)NSOUT);
     const int base = (b - k) * ROUT + k;
 #pragma unroll
     for (int q = 0; q < ROUT; ++q) lb[lds_index<PAD>(base + q * NSOUT) * ES] = v[u * ROUT + q];
@@ -179,6 +218,20 @@ __device__ __forceinline__ void exchange(Cx<T>* v, int t, Cx<T>* lb, int pingstr
 }
 
 // ---- full transform -----------------------------------------------------------
+// Stages S.. of a transform whose stage S-1 has just run.
+template <typename T, int L, int E, int D, int ES, int SY, bool PAD, int S>
+__device__ __forceinline__ void fft_from(Cx<T>* v, int t, const Cx<T>* __restrict__ tw, int tws, Cx<T>* lb,
+                                         int pingstride, int& ph) {
+  constexpr bool INV = D > 0;
+  if constexpr (S < plan_stages(L)) {
+    constexpr int RP = plan_radix(L, S - 1, INV), NSP = plan_span(L, S - 1, INV);
+    constexpr int R = plan_radix(L, S, INV);
+    exchange<T, L, E, RP, NSP, R, ES, SY, PAD>(v, t, lb, pingstride, ph);
+    stage<T, L, E, R, NSP * RP, D>(v, t, tw, tws);
+    fft_from<T, L, E, D, ES, SY, PAD, S + 1>(v, t, tw, tws, lb, pingstride, ph);
+  }
+}
+
 // In: slots in the first-stage pattern of the direction's plan.
 // Out: slots in the last-stage pattern.  D = -1 forward, +1 inverse.
 // For SY_PING, lb + pingstride is the second buffer and `phase` persists
@@ -187,22 +240,11 @@ template <typename T, int L, int D, int ES, int SY = SY_BLOCK, bool PAD = false,
 __device__ __forceinline__ void fft(Cx<T>* v, int t, const Cx<T>* __restrict__ tw, int tws, Cx<T>* lb,
                                     int pingstride = 0, int* phase = nullptr) {
   constexpr bool INV = D > 0;
-  static_assert(E % plan_radix(L, 0, INV) == 0 && L % E == 0, "E must be a multiple of every radix");
-  constexpr int NST = plan_stages(L);
-  constexpr int R0 = plan_radix(L, 0, INV);
-  constexpr int R1 = plan_radix(L, 1, INV);
-  constexpr int R2 = plan_radix(L, 2, INV);
+  static_assert(plan_ok(L) && L % E == 0, "every radix must divide E and the plan must multiply out to L");
   int dummy = 0;
   int& ph = phase ? *phase : dummy;
-  stage<T, L, E, R0, 1, D>(v, t, tw, tws);
-  if constexpr (NST > 1) {
-    exchange<T, L, E, R0, 1, R1, ES, SY, PAD>(v, t, lb, pingstride, ph);
-    stage<T, L, E, R1, R0, D>(v, t, tw, tws);
-  }
-  if constexpr (NST > 2) {
-    exchange<T, L, E, R1, R0, R2, ES, SY, PAD>(v, t, lb, pingstride, ph);
-    stage<T, L, E, R2, R0 * R1, D>(v, t, tw, tws);
-  }
+  stage<T, L, E, plan_radix(L, 0, INV), 1, D>(v, t, tw, tws);
+  fft_from<T, L, E, D, ES, SY, PAD, 1>(v, t, tw, tws, lb, pingstride, ph);
 }
 
 }  // namespace lpt2

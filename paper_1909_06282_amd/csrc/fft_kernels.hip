@@ -75,7 +75,7 @@ __device__ __forceinline__ void r2c_finish(Cx<T>* v, int t, Cx<T>* lb, const Cx<
   for (int s = 0; s < C::E; ++s) {
     const int k = t + s * C::TPL;
     const Cx<T> z = lb[lds_index<PAD>(k)];
-    const Cx<T> zc = conj(lb[lds_index<PAD>((C::L - k) & (C::L - 1))]);
+    const Cx<T> zc = conj(lb[lds_index<PAD>(k == 0 ? 0 : C::L - k)]);
     const Cx<T> a = scale(z + zc, T(0.5));
     const Cx<T> wb = stw[k] * scale(z - zc, T(0.5));
     if (act) dst[k] = mk(a.x + wb.y, a.y - wb.x);
@@ -647,6 +647,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xpass(const Cx<T>
 // ---------------------------------------------------------------------------
 // launchers (footprint checks, then the launch)
 // ---------------------------------------------------------------------------
+// grid sizes: powers of two 8..512 and three times a power of two 24..768
 #define LPT2_SWITCH_N(n, CALL)     \
   switch (n) {                     \
     case 8: CALL(8); break;        \
@@ -656,6 +657,12 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xpass(const Cx<T>
     case 128: CALL(128); break;    \
     case 256: CALL(256); break;    \
     case 512: CALL(512); break;    \
+    case 24: CALL(24); break;      \
+    case 48: CALL(48); break;      \
+    case 96: CALL(96); break;      \
+    case 192: CALL(192); break;    \
+    case 384: CALL(384); break;    \
+    case 768: CALL(768); break;    \
     default: return hipErrorInvalidValue; \
   }
 
@@ -669,6 +676,12 @@ int col_width(int prec, int n, int i) {
     case 128: W_(128);
     case 256: W_(256);
     case 512: W_(512);
+    case 24: W_(24);
+    case 48: W_(48);
+    case 96: W_(96);
+    case 192: W_(192);
+    case 384: W_(384);
+    case 768: W_(768);
   }
 #undef W_
   return 0;
@@ -692,7 +705,10 @@ static long resident_blocks(const void* kernel, int block) {
 static inline long min_l(long a, long b) { return a < b ? a : b; }
 
 static inline size_t esize(int prec) { return prec == PREC_F32 ? 4 : 8; }
-static inline bool pow2n(int n) { return n >= 8 && n <= 512 && (n & (n - 1)) == 0; }
+static inline bool pow2n(int n) {  // a supported grid size
+  const bool p2 = (n & (n - 1)) == 0, p3 = n % 3 == 0 && ((n / 3) & (n / 3 - 1)) == 0;
+  return n > 0 && ((p2 && n >= 8 && n <= 512) || (p3 && n >= 24 && n <= 768));
+}
 
 Batch batch_one(const void* ext, int nf, long ext_fstride, long ws_fstride) {
   Batch b;

@@ -117,7 +117,11 @@ struct Busy {
   }
 };
 
-bool pow2_in_range(int n) { return n >= 8 && n <= 512 && (n & (n - 1)) == 0; }
+// powers of two 8..512, or three times a power of two 24..768
+bool pow2_in_range(int n) {
+  const bool p2 = n > 0 && (n & (n - 1)) == 0, m = n % 3 == 0 && n > 0 && ((n / 3) & (n / 3 - 1)) == 0;
+  return (p2 && n >= 8 && n <= 512) || (m && n >= 24 && n <= 768);
+}
 
 // sigma8 normalisation: A = sigma8^2 / [(1/2 pi^2) Int k^3 k^ns T^2 W^2(8k) dln k],
 // composite Simpson on ln k in [ln 1e-5, ln 1e3] with 2^16 intervals.
@@ -140,7 +144,7 @@ double sigma8_amplitude(const Cosmo& c, double sigma8) {
 
 lpt2_status validate(const lpt2_config& c, std::string& why) {
   if (!pow2_in_range(c.n)) {
-    why = "n must be a power of two in 8..512";
+    why = "n must be a power of two in 8..512 or three times one in 24..768";
     return LPT2_EUNSUPPORTED;
   }
   if (c.precision != LPT2_FP64 && c.precision != LPT2_FP32) {

@@ -209,3 +209,15 @@ def test_epochs_equal_separate_displacements(prec):
     from paper_1909_06282_amd import LPT2Error
     with pytest.raises(LPT2Error):
         plan.displace_epochs([1.0] * 17, noise)
+
+
+def test_batched_mixed_radix_and_power_of_two():
+    # 3 x 96^3 (three times a power of two) beside 2 x 64^3, FP64
+    print("batched 3x96^3 + 2x64^3 fp64", flush=True)
+    plan, cfgs, per, noise = _mixed("fp64", counts=(3, 2), sizes=(96, 64))
+    p1, p2 = plan.displace(1.0, noise)
+    torch.cuda.synchronize()
+    for i in (0, 2, 3):
+        q1, q2 = _single(per[i], 1.0, noise[i])
+        torch.cuda.synchronize()
+        assert torch.equal(p1[i], q1) and torch.equal(p2[i], q2), f"realisation {i}"

@@ -48,7 +48,7 @@ def _tables(model, a):
 
 # ---------------------------------------------------------------- FFT
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("n", [8, 16, 32, 64, 128])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 24, 48, 96])
 def test_fft3d_forward_matches_dft(n, prec):
     print(f"fft3d forward n={n} {prec}", flush=True)
     plan, cfg = _plan(precision=prec, n=n, box=2.0 * n)
@@ -60,7 +60,7 @@ def test_fft3d_forward_matches_dft(n, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("n", [8, 16, 32, 64, 128])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 24, 48, 96])
 def test_fft3d_inverse_matches_dft(n, prec):
     print(f"fft3d inverse n={n} {prec}", flush=True)
     plan, cfg = _plan(precision=prec, n=n, box=2.0 * n)
@@ -114,7 +114,7 @@ def test_displace_c1_gr_fp64():
     _check_displace("fp64", 1.0, F64_TOL, n=32, box=128.0, gravity="gr", factorisation="eds")
 
 
-@pytest.mark.parametrize("n", [8, 16, 32, 64])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 24, 48, 96, 192])
 @pytest.mark.parametrize("a", [1.0, 0.5])
 def test_displace_fr_t1_fp64(n, a):
     print(f"displace f(R) T1 fp64 n={n} a={a}", flush=True)
@@ -122,7 +122,7 @@ def test_displace_fr_t1_fp64(n, a):
                     factorisation="t1", nk_growth=64)
 
 
-@pytest.mark.parametrize("n", [8, 32, 128])
+@pytest.mark.parametrize("n", [8, 32, 128, 96])
 def test_displace_fr_t1_fp32(n):
     print(f"displace f(R) T1 fp32 n={n}", flush=True)
     _check_displace("fp32", 1.0, F32_TOL, n=n, box=2.0 * n, gravity="fr_hs", fr0_abs=1e-5,
@@ -264,7 +264,7 @@ def test_auto_factorisation_plan():
 
 
 # ---------------------------------------------------------------- source spectrum
-@pytest.mark.parametrize("n,nbins", [(16, 8), (32, 16), (64, 32)])
+@pytest.mark.parametrize("n,nbins", [(16, 8), (32, 16), (64, 32), (48, 24), (192, 96)])
 def test_source_power_spectrum_matches_oracle(n, nbins):
     print(f"source power n={n}", flush=True)
     plan, cfg = _plan(n=n, box=2.0 * n, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=64)
