@@ -9,6 +9,8 @@
   * C4: the batched mix (64 x 128^3 + 32 x 64^3, seeds 100-195) as one
     tuned, graph-captured FP32 plan: every realisation against the batched
     FP64 GPU path, the first and last of each size against the oracle;
+  * mixed radix: 384^3 FP64 and FP32 against the oracle; the paper's 768^3
+    grid (L = 750) FP32 against the FP64 GPU path;
   * C5: the adjoint at 128^3: FP32 gradient against the FP64 oracle's
     autograd gradient, and the FP64 GPU gradient against central finite
     differences (eps = 1e-3) on 64 cells.
@@ -160,6 +162,35 @@ def test_c4_batched_graph_fp32_vs_fp64_and_oracle(tmp_path):
         e32 = max(normwise(o1[i], r1), normwise(o2[i], r2), normwise(o1[i].double() + o2[i].double(), r1 + r2))
         print(f"  realisation {i} n={cfg.n} seed {seeds[i]}: fp64 {e64:.3e} fp32 {e32:.3e}", flush=True)
         assert e64 < 1e-12 and e32 < 1e-5
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_mixed_radix_384_displacements(prec, tol):
+    # three times a power of two: 384^3 (L = 768, 2 Mpc/h cells) against the oracle
+    print(f"mixed radix 384^3 {prec}", flush=True)
+    _parity(prec, 1.0, 2, tol, n=384, box=768.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1")
+
+
+def test_mixed_radix_768_fp32_vs_fp64():
+    # the paper's grid size, 768^3 in 750 Mpc/h: FP32 against the FP64 GPU path
+    # (the FP64 path is held to the oracle at the mixed-radix sizes above)
+    print("mixed radix 768^3 fp32 vs fp64", flush=True)
+    kw = dict(n=768, box=750.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1")
+    w = white_noise(768, 1)
+    plan, cfg = _plan(precision="fp64", **kw)
+    q1, q2 = plan.displace(1.0, to_dev(w, torch.float64))
+    torch.cuda.synchronize()
+    plan.close()
+    plan, cfg = _plan(precision="fp32", **kw)
+    p1, p2 = plan.displace(1.0, to_dev(w, torch.float32))
+    torch.cuda.synchronize()
+    plan.close()
+    e1 = float((p1.double() - q1).abs().max() / q1.abs().max())
+    e2 = float((p2.double() - q2).abs().max() / q2.abs().max())
+    t64 = q1 + q2
+    et = float(((p1.double() + p2.double()) - t64).abs().max() / t64.abs().max())
+    print(f"  psi1 {e1:.3e} psi2 {e2:.3e} total {et:.3e}", flush=True)
+    assert e1 < 1e-5 and e2 < 1e-5 and et < 1e-5
 
 
 def _c5_loss_pieces(prec):
