@@ -167,10 +167,25 @@ def adjoint_timing(reps: int):
     g1 = torch.randn((3, 128, 128, 128), device="cuda")
     g2 = torch.randn_like(g1)
     wd = w.detach()
-    return {"workload": "128^3 (L=256) f(R) |f_R0|=1e-5 FP32, CIC loss against seed 7, gradient for seed 1",
-            "ms_loss_and_gradient": round(_timed(step, reps), 4),
-            "ms_displace": round(_timed(lambda: plan.displace(1.0, wd), reps), 4),
-            "ms_backward": round(_timed(lambda: plan.backward(1.0, wd, g1, g2), reps), 4)}
+    out = {"workload": "128^3 (L=256) f(R) |f_R0|=1e-5 FP32, CIC loss against seed 7, gradient for seed 1",
+           "ms_loss_and_gradient": round(_timed(step, reps), 4),
+           "ms_displace": round(_timed(lambda: plan.displace(1.0, wd), reps), 4),
+           "ms_backward": round(_timed(lambda: plan.backward(1.0, wd, g1, g2), reps), 4)}
+    plan.profile_reset()
+    plan.profile_enable(True)
+    for _ in range(reps):
+        plan.backward(1.0, wd, g1, g2)
+    torch.cuda.synchronize()
+    prof = plan.profile()
+    plan.profile_enable(False)
+    tot_ms = sum(t for _, _, t, _ in prof) / reps
+    tot_by = sum(by * l for _, l, _, by in prof) / reps
+    out["backward_kernels"] = {f"{name} [{by / 1e9:.3f} GB]": {"avg_ms": round(t / l, 4),
+                                                              "GBps": round(by / (t / l / 1e3) / 1e9, 1)}
+                               for name, l, t, by in prof if t > 0}
+    out["backward_algorithmic_GBps"] = round(tot_by / (tot_ms / 1e3) / 1e9, 1)
+    out["backward_bytes_per_cell"] = round(tot_by / 128 ** 3, 1)
+    return out
 
 
 def epochs_timing(reps: int):
