@@ -92,6 +92,51 @@ def test_null_arguments():
     assert L.lpt2_realisations(None) == 0
 
 
+def test_null_plan_on_every_plan_entry_point():
+    # each entry point that takes a plan refuses NULL on the host (no device work)
+    abi, L = _lib()
+    E = abi.EINVAL
+    d = C.c_double()
+    i = C.c_int()
+    t = (C.c_int * 3)()
+    arr = (C.c_double * 2)(1.0, 0.5)
+    assert L.lpt2_triangle_ratio(None, 1.0, 1.0, 90.0, 0, C.byref(d), 1, C.byref(d)) == E
+    assert L.lpt2_choose_factorisation(None, 1.0, None, 8, 0.4, 0, C.byref(i), None, None) == E
+    assert L.lpt2_auto_choice(None, 0, 1.0, C.byref(i)) == E
+    assert L.lpt2_displace_delta(None, 1.0, None, None, None, None) == E
+    assert L.lpt2_displace_epochs(None, 2, arr, None, None, None, None) == E
+    assert L.lpt2_positions(None, 0, None, None, None, None) == E
+    assert L.lpt2_matter_power(None, None, None, 8, 0, None, None, None, None, None) == E
+    assert L.lpt2_paint_cic(None, None, None, None, None) == E
+    assert L.lpt2_paint_cic_backward(None, None, None, None, None, None) == E
+    assert L.lpt2_growth_table(None, 1.0, None, None, None) == E
+    assert L.lpt2_fft3d(None, -1, None, None, None) == E
+    assert L.lpt2_set_graph(None, 1) == E
+    assert L.lpt2_get_tiles(None, 0, t) == E
+    assert L.lpt2_set_tiles(None, 0, t) == E
+    assert L.lpt2_tile_options(None, 0, t) == E
+    assert L.lpt2_autotune(None, 1.0, None, None, None, None, None) == E
+    assert L.lpt2_profile_enable(None, 1) == E
+    assert L.lpt2_profile_reset(None) == E
+    assert L.lpt2_workspace_bytes(None) == 0
+    assert L.lpt2_last_error(None)  # the plan-less error text is kept
+
+
+def test_factorisation_candidates_are_listed_without_a_plan():
+    abi, L = _lib()
+    n = L.lpt2_factorisation_candidates()
+    assert n == 8
+    names = []
+    for k in range(n):
+        nm, r, th, w = C.c_char_p(), C.c_double(), C.c_double(), C.c_int()
+        assert L.lpt2_factorisation_candidate(k, C.byref(nm), C.byref(r), C.byref(th), C.byref(w)) == abi.OK
+        names.append(nm.value.decode())
+        assert r.value > 0 and 0 < th.value < 180
+    assert names[0] == "T1" and names[-1] == "winther" and len(set(names)) == n
+    nm = C.c_char_p()
+    assert L.lpt2_factorisation_candidate(n, C.byref(nm), None, None, None) == abi.EINVAL
+
+
 def test_strerror():
     _, L = _lib()
     assert L.lpt2_strerror(0) == b"ok"
