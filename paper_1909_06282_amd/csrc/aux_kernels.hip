@@ -288,29 +288,59 @@ hipError_t launch_bin(int prec, int n, const void* A, size_t a_cap, const void* 
 // Particle p = (ix,iy,iz) moves to u = (ix,iy,iz) + (psi1 + psi2)/cell in
 // cell units; per axis the two nearest nodes get 1 - f and f, f = u - floor(u).
 // ---------------------------------------------------------------------------
+// Scatter: a workgroup takes a Lagrangian tile of CIC_T^3 particles and
+// accumulates their clouds in LDS over the tile's cells plus a halo of
+// CIC_H cells on every side; only the touched cells are then added to the
+// grid, one coalesced global atomic per cell in place of eight per particle
+// (device-scope atomics from every CU on neighbouring cells are what the
+// direct scatter waits on).  A corner outside the halo goes to the grid
+// directly, so any displacement is painted.
+constexpr int CIC_T = 8, CIC_H = 4, CIC_R = CIC_T + 2 * CIC_H;
 template <typename T>
-__global__ void k_cic(int n, double inv_cell, const T* __restrict__ p1, const T* __restrict__ p2, T* __restrict__ rho) {
+__global__ __launch_bounds__(256) void k_cic(int n, double inv_cell, const T* __restrict__ p1,
+                                             const T* __restrict__ p2, T* __restrict__ rho) {
+  constexpr int R3 = CIC_R * CIC_R * CIC_R;
+  __shared__ T acc[R3];
   const long n3 = (long)n * n * n;
-  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n3) return;
-  const int ix = (int)(p / ((long)n * n)), iy = (int)((p / n) % n), iz = (int)(p % n);
-  const int id[3] = {ix, iy, iz};
-  int i0[3];
-  double f[3];
-  for (int c = 0; c < 3; ++c) {
-    const double u = (double)id[c] + ((double)p1[c * n3 + p] + (double)p2[c * n3 + p]) * inv_cell;
-    if (!(fabs(u) < 1e15)) return;  // non-finite or absurd displacement: the particle is not painted
-    const double fl = floor(u);
-    f[c] = u - fl;
-    long ii = (long)fl % n;
-    if (ii < 0) ii += n;
-    i0[c] = (int)ii;
+  const int tpa = n / CIC_T;  // tiles per axis
+  const int bt = blockIdx.x;
+  const int tx = bt / (tpa * tpa), ty = (bt / tpa) % tpa, tz = bt % tpa;
+  const long o0[3] = {(long)tx * CIC_T - CIC_H, (long)ty * CIC_T - CIC_H, (long)tz * CIC_T - CIC_H};
+  for (int i = threadIdx.x; i < R3; i += blockDim.x) acc[i] = T(0);
+  __syncthreads();
+  auto wrap = [n](long g) { long r = g % n; return r < 0 ? r + n : r; };
+  for (int q = threadIdx.x; q < CIC_T * CIC_T * CIC_T; q += blockDim.x) {
+    const int id[3] = {tx * CIC_T + q / (CIC_T * CIC_T), ty * CIC_T + (q / CIC_T) % CIC_T, tz * CIC_T + q % CIC_T};
+    const long p = ((long)id[0] * n + id[1]) * n + id[2];
+    long i0[3];
+    double f[3];
+    bool ok = true;
+    for (int c = 0; c < 3; ++c) {
+      const double u = (double)id[c] + ((double)p1[c * n3 + p] + (double)p2[c * n3 + p]) * inv_cell;
+      ok = ok && fabs(u) < 1e15;  // non-finite or absurd displacement: the particle is not painted
+      const double fl = ok ? floor(u) : 0.0;
+      f[c] = ok ? u - fl : 0.0;
+      i0[c] = (long)fl;
+    }
+    if (!ok) continue;
+    for (int o = 0; o < 8; ++o) {
+      const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
+      const double w = (ox ? f[0] : 1.0 - f[0]) * (oy ? f[1] : 1.0 - f[1]) * (oz ? f[2] : 1.0 - f[2]);
+      const long gx = i0[0] + ox, gy = i0[1] + oy, gz = i0[2] + oz;
+      const long rx = gx - o0[0], ry = gy - o0[1], rz = gz - o0[2];
+      if (rx >= 0 && rx < CIC_R && ry >= 0 && ry < CIC_R && rz >= 0 && rz < CIC_R)
+        atomicAdd(&acc[(rx * CIC_R + ry) * CIC_R + rz], (T)w);
+      else
+        atomicAdd(&rho[(wrap(gx) * n + wrap(gy)) * n + wrap(gz)], (T)w);
+    }
   }
-  for (int o = 0; o < 8; ++o) {
-    const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
-    const double w = (ox ? f[0] : 1.0 - f[0]) * (oy ? f[1] : 1.0 - f[1]) * (oz ? f[2] : 1.0 - f[2]);
-    const int gx = (i0[0] + ox) % n, gy = (i0[1] + oy) % n, gz = (i0[2] + oz) % n;
-    atomicAdd(&rho[((long)gx * n + gy) * n + gz], (T)w);
+  __syncthreads();
+  for (int i = threadIdx.x; i < R3; i += blockDim.x) {
+    const T v = acc[i];
+    if (v != T(0)) {
+      const long gx = o0[0] + i / (CIC_R * CIC_R), gy = o0[1] + (i / CIC_R) % CIC_R, gz = o0[2] + i % CIC_R;
+      atomicAdd(&rho[(wrap(gx) * n + wrap(gy)) * n + wrap(gz)], v);
+    }
   }
 }
 
@@ -374,7 +404,8 @@ hipError_t launch_cic(int prec, int n, double box, const void* psi1, const void*
   hipError_t e = launch_fill(prec, delta, n3, -1.0, s);
   if (e != hipSuccess) return e;
   const double ic = n / box;
-  const unsigned blocks = (unsigned)((n3 + 255) / 256);
+  if (n % CIC_T != 0) return hipErrorInvalidValue;
+  const unsigned blocks = (unsigned)((long)(n / CIC_T) * (n / CIC_T) * (n / CIC_T));  // one per tile
   if (prec == PREC_F32)
     hipLaunchKernelGGL(k_cic<float>, dim3(blocks), dim3(256), 0, s, n, ic, (const float*)psi1, (const float*)psi2,
                        (float*)delta);
