@@ -31,12 +31,14 @@ CSRC = os.path.join(ROOT, "paper_1909_06282_amd", "csrc")
 COPY_BYTES = 512 << 20
 
 
-KERNEL_SOURCES = ("aux_kernels.hip", "cx.hpp", "fft_core.hpp", "fft_kernels.hip", "kernels.hpp", "physics.hpp")
+# the device code of the displacement passes (the counter readings describe
+# those kernels; the host code, the growth and table kernels, the binner and
+# the CIC kernels are left out)
+KERNEL_SOURCES = ("cx.hpp", "fft_core.hpp", "fft_kernels.hip", "kernels.hpp")
 
 
 def source_hash() -> str:
-    """Hash of the device-code sources (the host-side library code is left out:
-    the stored counter readings describe the kernels)."""
+    """Hash of the device code of the displacement passes."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(CSRC, f), "rb") as fh:
