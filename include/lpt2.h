@@ -28,7 +28,10 @@
  *   - no entry point throws; each returns an lpt2_status, and the message of
  *     the last failure on a plan is available from lpt2_last_error().
  *   - a plan may be used by one host thread / one stream at a time; a
- *     concurrent call on the same plan returns LPT2_ESTATE.
+ *     concurrent call on the same plan returns LPT2_ESTATE.  Every call of a
+ *     plan works in the plan's one workspace, so calls issued on different
+ *     streams must be ordered by the caller (events or synchronisation);
+ *     calls on one stream are ordered by the stream.
  */
 #ifndef LPT2_H
 #define LPT2_H
