@@ -266,10 +266,14 @@ __global__ __launch_bounds__(256) void k_zsource(const Cx<T>* __restrict__ phi, 
 
 // Adjoint of the source: with S_bar given per real value,
 //   phi_bar_ii = S_bar (tr phi - phi_ii), phi_bar_ij = -2 S_bar phi_ij (i < j),
-// each forward-transformed along z.  phi and out may be the same buffers.
+// each forward-transformed along z.  Logical field f of the six (xx, yy, zz,
+// xy, xz, yz) is read at field zp.fmap[f], multiplied by m_z^zp.r[f] before
+// its inverse transform, and its phi_bar is written at field zp.fmap[f] of
+// `out` (so phi and out may be the same buffers: every line is read before
+// it is written).
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_zprodrule(const Cx<T>* phi, long fstride, const T* __restrict__ sbar,
-                                                   Cx<T>* out, long ofstride, long nlines,
+                                                   Cx<T>* out, long ofstride, long nlines, ZPow zp,
                                                    const Cx<T>* __restrict__ tw) {
   using C = LineCfg<N>;
   __shared__ Cx<T> lds[C::G * C::SPAN];
@@ -283,33 +287,33 @@ __global__ __launch_bounds__(256) void k_zprodrule(const Cx<T>* phi, long fstrid
   Cx<T> sb[C::E], d0[C::E], d1[C::E], d2[C::E], v[C::E];
   load_real_line<T, N>(sbar + lsafe * N, sb, t, act);
   const Cx<T>* src = phi + lsafe * C::L;
-  c2r_prepare<T, N>(src, 0, d0, t, lb, stw, act);
+  c2r_prepare<T, N>(src + zp.fmap[0] * fstride, zp.r[0], d0, t, lb, stw, act);
   fft<T, C::L, +1, 1, SY_WAVE, true>(d0, t, stw, 2, lb);
-  c2r_prepare<T, N>(src + fstride, 0, d1, t, lb, stw, act);
+  c2r_prepare<T, N>(src + zp.fmap[1] * fstride, zp.r[1], d1, t, lb, stw, act);
   fft<T, C::L, +1, 1, SY_WAVE, true>(d1, t, stw, 2, lb);
-  c2r_prepare<T, N>(src + 2 * fstride, 0, d2, t, lb, stw, act);
+  c2r_prepare<T, N>(src + zp.fmap[2] * fstride, zp.r[2], d2, t, lb, stw, act);
   fft<T, C::L, +1, 1, SY_WAVE, true>(d2, t, stw, 2, lb);
   Cx<T>* dst = out + lsafe * C::L;
 #pragma unroll
   for (int i = 0; i < C::E; ++i) v[i] = mk(sb[i].x * (d1[i].x + d2[i].x), sb[i].y * (d1[i].y + d2[i].y));
   fft<T, C::L, -1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
-  r2c_finish<T, N>(v, t, lb, stw, dst, act);
+  r2c_finish<T, N>(v, t, lb, stw, dst + zp.fmap[0] * ofstride, act);
 #pragma unroll
   for (int i = 0; i < C::E; ++i) v[i] = mk(sb[i].x * (d0[i].x + d2[i].x), sb[i].y * (d0[i].y + d2[i].y));
   fft<T, C::L, -1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
-  r2c_finish<T, N>(v, t, lb, stw, dst + ofstride, act);
+  r2c_finish<T, N>(v, t, lb, stw, dst + zp.fmap[1] * ofstride, act);
 #pragma unroll
   for (int i = 0; i < C::E; ++i) v[i] = mk(sb[i].x * (d0[i].x + d1[i].x), sb[i].y * (d0[i].y + d1[i].y));
   fft<T, C::L, -1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
-  r2c_finish<T, N>(v, t, lb, stw, dst + 2 * ofstride, act);
+  r2c_finish<T, N>(v, t, lb, stw, dst + zp.fmap[2] * ofstride, act);
 #pragma unroll 1
   for (int f = 3; f < 6; ++f) {
-    c2r_prepare<T, N>(src + f * fstride, 0, v, t, lb, stw, act);
+    c2r_prepare<T, N>(src + zp.fmap[f] * fstride, zp.r[f], v, t, lb, stw, act);
     fft<T, C::L, +1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
 #pragma unroll
     for (int i = 0; i < C::E; ++i) v[i] = mk(T(-2) * sb[i].x * v[i].x, T(-2) * sb[i].y * v[i].y);
     fft<T, C::L, -1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
-    r2c_finish<T, N>(v, t, lb, stw, dst + f * ofstride, act);
+    r2c_finish<T, N>(v, t, lb, stw, dst + zp.fmap[f] * ofstride, act);
   }
 }
 
@@ -443,6 +447,72 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
   }
 }
 
+// Fused y pass of the adjoint chain: output o sums its terms k (first[o] to
+// first[o+1]-1), each the forward y-FFT of input field src[k] times
+// m_y^py[k] m_z^pz[k] (m_z is the column's z mode, constant along it), over
+// `nplanes` x planes.  Persistent over column tiles; the column of the next
+// term, or of the next tile's first term, loads while the current one
+// transforms.
+template <typename T, int N, int WW>
+__global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_yfanin(const Cx<T>* __restrict__ in, long fsi,
+                                                                  Cx<T>* __restrict__ out, long fso, YFan op,
+                                                                  long nplanes, const Cx<T>* __restrict__ tw) {
+  using C = ColCfg<T, N, WW>;
+  constexpr int M = N / 2;
+  constexpr int BPP = (M + C::W - 1) / C::W;
+  const long NTILES = nplanes * BPP;
+  __shared__ Cx<T> lds[2 * C::L * C::W];  // two exchange buffers
+  __shared__ Cx<T> stw[N];
+  stage_twiddles<T, N>(stw, tw);
+  int phase = 0;
+  const int c = threadIdx.x % C::W, t = threadIdx.x / C::W;
+  Cx<T> v[C::E], acc[C::E], pf[C::E];
+  auto load = [&](long tile, int src) {
+    const long plane = tile / BPP;
+    const int col = (int)(tile % BPP) * C::W + c;
+    const bool a = col < M;
+    const Cx<T>* b = in + src * fsi + plane * (long)N * M + (a ? col : 0);
+#pragma unroll
+    for (int sl = 0; sl < C::E; ++sl) pf[sl] = a ? b[slot_elem<C::L, C::E, C::R0F>(t, sl) * M] : zero<T>();
+  };
+  long tile = blockIdx.x;
+  if (tile < NTILES) load(tile, op.src[0]);
+#pragma unroll 1
+  for (; tile < NTILES; tile += gridDim.x) {
+    const long plane = tile / BPP;
+    const int col = (int)(tile % BPP) * C::W + c;
+    const bool act = col < M;
+    const long off = plane * (long)N * M + (act ? col : 0);
+    int o = 0;
+#pragma unroll 1
+    for (int k = 0; k < op.nterm; ++k) {
+#pragma unroll
+      for (int sl = 0; sl < C::E; ++sl) v[sl] = pf[sl];
+      if (k + 1 < op.nterm)
+        load(tile, op.src[k + 1]);
+      else if (tile + gridDim.x < NTILES)
+        load(tile + gridDim.x, op.src[0]);
+      fft<T, C::L, -1, C::W, SY_PING>(v, t, stw, 1, lds + c, C::L * C::W, &phase);
+      const T fz = mpow<T>(col, op.pz[k]);
+      const bool start = k == op.first[o];
+#pragma unroll
+      for (int sl = 0; sl < C::E; ++sl) {
+        const int iy = slot_elem<C::L, C::E, C::RLF>(t, sl);
+        const Cx<T> u = scale(v[sl], mpow<T>(iy < N / 2 ? iy : iy - N, op.py[k]) * fz);
+        acc[sl] = start ? u : acc[sl] + u;
+      }
+      if (k + 1 == op.first[o + 1]) {
+        if (act) {
+          Cx<T>* d = out + o * fso + off;
+#pragma unroll
+          for (int sl = 0; sl < C::E; ++sl) d[slot_elem<C::L, C::E, C::RLF>(t, sl) * M] = acc[sl];
+        }
+        ++o;
+      }
+    }
+  }
+}
+
 // Displacement x pass (the hot path's two x passes).  One input column X
 // (z and y already forward-transformed), forward x-FFT, then one gather per
 // mode of the radial table(s) (built in FP64, stored rounded once to T), then the outputs
@@ -455,6 +525,8 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
 //   MODE 1: tab = PSI2;  out 0..1: Q_p = F_x^-1[-i m_x^p PSI2 X]
 //   MODE 2: tab = the (PHI, PSI1) pair; out 0..1: V_p (first order only, for
 //           further epochs of the same realisation)
+//   MODE 3: tab = the (PHI, PSI1) pair; out 0..2: U_p (the potential only, for
+//           the adjoint)
 // DC and Nyquist planes are zero in every output.  The column data are
 // loaded and stored non-temporally, so the table stays in L2 for the gathers
 // (measured 10% faster at n = 512).
@@ -522,7 +594,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
     if (tile + gridDim.x < NTILES) load(tile + gridDim.x);  // next tile's column, in flight meanwhile
     fft<T, C::L, -1, C::W, SY_PING>(va, t, stw, 1, lds + c, C::L * C::W, &phase);
     if (!EARLY) gather();
-    constexpr int NOUT = MODE == 0 ? 5 : 2;
+    constexpr int NOUT = MODE == 0 ? 5 : (MODE == 3 ? 3 : 2);
   #pragma unroll 1
     for (int o = 0; o < NOUT; ++o) {
       // MODE 0: o < 3 -> -m_x^o PHI X ; o = 3, 4 -> i m_x^(o-3) PSI1 X.  MODE 1: -i m_x^o PSI2 X.
@@ -812,24 +884,29 @@ hipError_t launch_zsource(int prec, int n, const void* phi, size_t phi_cap, long
 
 template <typename T, int N>
 static hipError_t zprod_t(const void* phi, long fstride, const void* sbar, void* out, long ofs, long nlines,
-                          const void* tw, hipStream_t s) {
+                          const ZPow& zp, const void* tw, hipStream_t s) {
   using C = LineCfg<N>;
   const long blocks = (nlines + C::G - 1) / C::G;
   hipLaunchKernelGGL((k_zprodrule<T, N>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)phi, fstride,
-                     (const T*)sbar, (Cx<T>*)out, ofs, nlines, (const Cx<T>*)tw);
+                     (const T*)sbar, (Cx<T>*)out, ofs, nlines, zp, (const Cx<T>*)tw);
   return hipGetLastError();
 }
 hipError_t launch_zprodrule(int prec, int n, const void* phi, size_t phi_cap, long fstride, const void* sbar,
-                            size_t sbar_cap, void* out, size_t out_cap, long out_fstride, long nlines, const void* tw,
-                            hipStream_t s) {
+                            size_t sbar_cap, void* out, size_t out_cap, long out_fstride, long nlines, const ZPow& zp,
+                            const void* tw, hipStream_t s) {
   if (nlines <= 0) return hipSuccess;
-  if (!pow2n(n) || !phi || !sbar || !out || !tw || fstride < 0 || out_fstride < 0) return hipErrorInvalidValue;
+  if (!pow2n(n) || !phi || !sbar || !out || !tw || fstride < 0 || out_fstride < 0 || !zpow_ok(zp))
+    return hipErrorInvalidValue;
+  // every line is read before it is written only if the six fields are distinct
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < i; ++j)
+      if (zp.fmap[i] == zp.fmap[j]) return hipErrorInvalidValue;
   const size_t cb = 2 * esize(prec), lc = (size_t)n / 2;
   if ((5 * (size_t)fstride + (size_t)nlines * lc) * cb > phi_cap ||
       (size_t)nlines * n * esize(prec) > sbar_cap ||
       (5 * (size_t)out_fstride + (size_t)nlines * lc) * cb > out_cap)
     return hipErrorInvalidValue;
-#define CALL(NN) return prec == PREC_F32 ? zprod_t<float, NN>(phi, fstride, sbar, out, out_fstride, nlines, tw, s) : zprod_t<double, NN>(phi, fstride, sbar, out, out_fstride, nlines, tw, s)
+#define CALL(NN) return prec == PREC_F32 ? zprod_t<float, NN>(phi, fstride, sbar, out, out_fstride, nlines, zp, tw, s) : zprod_t<double, NN>(phi, fstride, sbar, out, out_fstride, nlines, zp, tw, s)
   LPT2_SWITCH_N(n, CALL)
 #undef CALL
   return hipErrorInvalidValue;
@@ -909,26 +986,72 @@ hipError_t launch_ycombo(int prec, int n, int nr, const void* in, size_t in_cap,
 }
 
 template <typename T, int N, int WW>
-static hipError_t xdisp_w(int nr, int mode, const void* in, void* out, long fso, const void* tab, const void* tw,
+static hipError_t yfanin_w(int nr, const void* in, long fsi, void* out, long fso, const YFan& op, const void* tw,
+                           hipStream_t s) {
+  using C = ColCfg<T, N, WW>;
+  constexpr int M = N / 2;
+  static const long res = resident_blocks(reinterpret_cast<const void*>(&k_yfanin<T, N, WW>), C::BLOCK);
+  const long nplanes = (long)nr * N;
+  const long blocks = min_l(res, nplanes * ((M + C::W - 1) / C::W));
+  hipLaunchKernelGGL((k_yfanin<T, N, WW>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in, fsi,
+                     (Cx<T>*)out, fso, op, nplanes, (const Cx<T>*)tw);
+  return hipGetLastError();
+}
+template <typename T, int N>
+static hipError_t yfanin_t(int w, int nr, const void* in, long fsi, void* out, long fso, const YFan& op, const void* tw,
+                           hipStream_t s) {
+  if (w == col_w<T>(N, 0)) return yfanin_w<T, N, col_w<T>(N, 0)>(nr, in, fsi, out, fso, op, tw, s);
+  if (w == col_w<T>(N, 1)) return yfanin_w<T, N, col_w<T>(N, 1)>(nr, in, fsi, out, fso, op, tw, s);
+  if (w == col_w<T>(N, 2)) return yfanin_w<T, N, col_w<T>(N, 2)>(nr, in, fsi, out, fso, op, tw, s);
+  return hipErrorInvalidValue;
+}
+static bool yfan_ok(const YFan& op) {
+  if (op.nin < 1 || op.nout < 1 || op.nin > YFAN_MAX || op.nout > YFAN_MAX || op.nterm < op.nout ||
+      op.nterm > YFAN_MAX || op.first[0] != 0 || op.first[op.nout] != op.nterm)
+    return false;
+  for (int o = 0; o < op.nout; ++o)
+    if (op.first[o + 1] <= op.first[o]) return false;
+  for (int k = 0; k < op.nterm; ++k)
+    if (op.src[k] < 0 || op.src[k] >= op.nin || op.py[k] < 0 || op.py[k] > 2 || op.pz[k] < 0 || op.pz[k] > 2)
+      return false;
+  return true;
+}
+hipError_t launch_yfanin(int prec, int n, int nr, const void* in, size_t in_cap, long in_fstride, void* out,
+                         size_t out_cap, long out_fstride, const YFan& op, const void* tw, hipStream_t s, int w) {
+  if (w == 0) w = default_width(prec, n, KIND_MULTI);
+  if (!yfan_ok(op) || nr < 1) return hipErrorInvalidValue;
+  if (!pow2n(n) || !in || !out || !tw || in_fstride < 0 || out_fstride < 0) return hipErrorInvalidValue;
+  const size_t cb = 2 * esize(prec), field = (size_t)nr * n * n * (n / 2);
+  if (((size_t)(op.nin - 1) * in_fstride + field) * cb > in_cap) return hipErrorInvalidValue;
+  if (((size_t)(op.nout - 1) * out_fstride + field) * cb > out_cap) return hipErrorInvalidValue;
+#define CALL(NN) return prec == PREC_F32 ? yfanin_t<float, NN>(w, nr, in, in_fstride, out, out_fstride, op, tw, s) : yfanin_t<double, NN>(w, nr, in, in_fstride, out, out_fstride, op, tw, s)
+  LPT2_SWITCH_N(n, CALL)
+#undef CALL
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int N, int WW, int MODE>
+static hipError_t xdisp_m(int nr, const void* in, void* out, long fso, const void* tab, const void* tw,
                           hipStream_t s) {
   using C = ColCfg<T, N, WW>;
   const long ntiles = ((long)N * (N / 2) + C::W - 1) / C::W;  // per realisation
-  static const long r0 = resident_blocks(reinterpret_cast<const void*>(&k_xdisp<T, N, WW, 0>), C::BLOCK);
-  static const long r1 = resident_blocks(reinterpret_cast<const void*>(&k_xdisp<T, N, WW, 1>), C::BLOCK);
-  static const long r2 = resident_blocks(reinterpret_cast<const void*>(&k_xdisp<T, N, WW, 2>), C::BLOCK);
+  static const long res = resident_blocks(reinterpret_cast<const void*>(&k_xdisp<T, N, WW, MODE>), C::BLOCK);
   // the resident blocks shared out over the realisations (grid.y)
-  const long per = ((mode == 0 ? r0 : (mode == 1 ? r1 : r2)) + nr - 1) / nr;
-  const dim3 grid((unsigned)min_l(per, ntiles), (unsigned)nr);
-  if (mode == 0)
-    hipLaunchKernelGGL((k_xdisp<T, N, WW, 0>), grid, dim3(C::BLOCK), 0, s, (const Cx<T>*)in, (Cx<T>*)out, fso,
-                       (const T*)tab, (const Cx<T>*)tw);
-  else if (mode == 1)
-    hipLaunchKernelGGL((k_xdisp<T, N, WW, 1>), grid, dim3(C::BLOCK), 0, s, (const Cx<T>*)in, (Cx<T>*)out, fso,
-                       (const T*)tab, (const Cx<T>*)tw);
-  else
-    hipLaunchKernelGGL((k_xdisp<T, N, WW, 2>), grid, dim3(C::BLOCK), 0, s, (const Cx<T>*)in, (Cx<T>*)out, fso,
-                       (const T*)tab, (const Cx<T>*)tw);
+  const dim3 grid((unsigned)min_l((res + nr - 1) / nr, ntiles), (unsigned)nr);
+  hipLaunchKernelGGL((k_xdisp<T, N, WW, MODE>), grid, dim3(C::BLOCK), 0, s, (const Cx<T>*)in, (Cx<T>*)out, fso,
+                     (const T*)tab, (const Cx<T>*)tw);
   return hipGetLastError();
+}
+template <typename T, int N, int WW>
+static hipError_t xdisp_w(int nr, int mode, const void* in, void* out, long fso, const void* tab, const void* tw,
+                          hipStream_t s) {
+  switch (mode) {
+    case 0: return xdisp_m<T, N, WW, 0>(nr, in, out, fso, tab, tw, s);
+    case 1: return xdisp_m<T, N, WW, 1>(nr, in, out, fso, tab, tw, s);
+    case 2: return xdisp_m<T, N, WW, 2>(nr, in, out, fso, tab, tw, s);
+    case 3: return xdisp_m<T, N, WW, 3>(nr, in, out, fso, tab, tw, s);
+  }
+  return hipErrorInvalidValue;
 }
 template <typename T, int N>
 static hipError_t xdisp_t(int w, int nr, int mode, const void* in, void* out, long fso, const void* tab,
@@ -941,10 +1064,10 @@ static hipError_t xdisp_t(int w, int nr, int mode, const void* in, void* out, lo
 hipError_t launch_xdisp(int prec, int n, int nr, int mode, const void* in, size_t in_cap, void* out, size_t out_cap,
                         long out_fstride, const void* tab, size_t tab_cap, const void* tw, hipStream_t s, int w) {
   if (w == 0) w = default_width(prec, n, KIND_MULTI);
-  if (!pow2n(n) || !in || !out || !tab || !tw || out_fstride < 0 || mode < 0 || mode > 2 || nr < 1)
+  if (!pow2n(n) || !in || !out || !tab || !tw || out_fstride < 0 || mode < 0 || mode > 3 || nr < 1)
     return hipErrorInvalidValue;
   const size_t cb = 2 * esize(prec), field = (size_t)nr * n * n * (n / 2);
-  const int nout = mode == 0 ? 5 : 2;
+  const int nout = mode == 0 ? 5 : (mode == 3 ? 3 : 2);
   if (field * cb > in_cap || ((size_t)(nout - 1) * out_fstride + field) * cb > out_cap) return hipErrorInvalidValue;
   if (nr > 65535) return hipErrorInvalidValue;  // grid.y
   const size_t n2cnt = 3 * (size_t)(n / 2) * (n / 2) + 1;

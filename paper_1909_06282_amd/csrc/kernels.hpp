@@ -81,9 +81,21 @@ int default_width(int prec, int n, int kind);
 // (nr realisations stored one after the other inside every field slot)
 hipError_t launch_ycombo(int prec, int n, int nr, const void* in, size_t in_cap, long in_fstride, void* out,
                          size_t out_cap, long out_fstride, const YOp& op, const void* tw, hipStream_t s, int w = 0);
+// fan-in y pass of the adjoint: output o sums terms first[o] .. first[o+1]-1;
+// term k is the forward y-FFT of input field src[k] times m_y^py[k] m_z^pz[k]
+// (powers 0..2; first[0] = 0, first[nout] = nterm, every output has a term)
+constexpr int YFAN_MAX = 16;
+struct YFan {
+  int nin, nout, nterm;
+  int first[YFAN_MAX + 1];
+  int src[YFAN_MAX], py[YFAN_MAX], pz[YFAN_MAX];
+};
+hipError_t launch_yfanin(int prec, int n, int nr, const void* in, size_t in_cap, long in_fstride, void* out,
+                         size_t out_cap, long out_fstride, const YFan& op, const void* tw, hipStream_t s, int w = 0);
 // displacement x pass: mode 0 (tab = interleaved PHI, PSI1 per |m|^2; five
-// outputs U0,U1,U2,V0,V1), mode 1 (tab = PSI2; outputs Q0,Q1) or mode 2
-// (tab = the PHI, PSI1 pair; outputs V0,V1).  The table
+// outputs U0,U1,U2,V0,V1), mode 1 (tab = PSI2; outputs Q0,Q1), mode 2
+// (tab = the PHI, PSI1 pair; outputs V0,V1) or mode 3 (the pair; outputs
+// U0,U1,U2).  The table
 // is in the working precision (pair: 2 values per |m|^2); tab_cap in bytes.
 // nr realisations one after the other (n^2 (n/2) complex each) in the input
 // and in every output field.
@@ -97,9 +109,11 @@ hipError_t launch_xpass(int prec, int n, const void* in, size_t in_cap, long in_
 hipError_t launch_zsource(int prec, int n, const void* phi, size_t phi_cap, long fstride, const ZPow& zp, void* sk,
                           size_t sk_cap, long nlines, const void* tw, hipStream_t s);
 // z pass of the adjoint: 6 phi lines + real S_bar line -> 6 phi_bar half-spectrum lines
+// (logical field f = xx,yy,zz,xy,xz,yz read and written at field zp.fmap[f],
+// multiplied by m_z^zp.r[f] before its inverse transform)
 hipError_t launch_zprodrule(int prec, int n, const void* phi, size_t phi_cap, long fstride, const void* sbar,
-                            size_t sbar_cap, void* out, size_t out_cap, long out_fstride, long nlines, const void* tw,
-                            hipStream_t s);
+                            size_t sbar_cap, void* out, size_t out_cap, long out_fstride, long nlines, const ZPow& zp,
+                            const void* tw, hipStream_t s);
 
 // ---- auxiliary kernels (aux_kernels.hip) ----
 struct GrowthSetup {

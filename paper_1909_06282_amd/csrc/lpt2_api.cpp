@@ -489,7 +489,7 @@ lpt2_status xdisp(Ctx& c, const char* name, int mode, const void* in, void* out,
   const int row = mode != 1 ? (f32 ? TAB_PAIR32 : TAB_PAIR64) : (f32 ? TAB_PSI2_32 : TAB_PSI2);
   const void* tab = t->radial + (size_t)row * g.n2cnt;
   const size_t cap = sizeof(double) * (size_t)(TAB_ROWS - row) * g.n2cnt;
-  RUN(name, c.fields(mode == 0 ? 6 : 3),
+  RUN(name, c.fields(mode == 0 ? 6 : (mode == 3 ? 4 : 3)),
       launch_xdisp(p->prec, g.n, c.nr, mode, in, c.cap(in), out, c.cap(out), c.sstride(), tab, cap, g.tw, s,
                    g.tiles[2]));
   return LPT2_OK;
@@ -677,38 +677,103 @@ lpt2_status mg_source_k(Ctx& c, const Tables* t, const void* noise) {
   return LPT2_OK;
 }
 
-// slots 0..10
+// fan-in y pass over the c.nr realisations of each of op.nin slots at `in`
+lpt2_status yfan(Ctx& c, const char* name, const void* in, void* out, const YFan& op) {
+  lpt2_plan_t p = c.p;
+  hipStream_t s = c.s;
+  Grid& g = c.g;
+  RUN(name, c.fields(op.nterm + op.nout),
+      launch_yfanin(p->prec, g.n, c.nr, in, c.cap(in), c.sstride(), out, c.cap(out), c.sstride(), op, g.tw, s,
+                    g.tiles[1]));
+  return LPT2_OK;
+}
+// terms (src, m_y power, m_z power) of the outputs one after the other, nper[o] for output o
+YFan yfan_op(int nin, int nout, const int* nper, const int (*terms)[3]) {
+  YFan op;
+  std::memset(&op, 0, sizeof(op));
+  op.nin = nin;
+  op.nout = nout;
+  int k = 0;
+  for (int o = 0; o < nout; ++o) {
+    op.first[o] = k;
+    for (int j = 0; j < nper[o]; ++j, ++k) {
+      op.src[k] = terms[k][0];
+      op.py[k] = terms[k][1];
+      op.pz[k] = terms[k][2];
+    }
+  }
+  op.first[nout] = k;
+  op.nterm = k;
+  return op;
+}
+
+// Gradient of a loss with respect to the noise of one realisation, from the
+// gradients psi1_bar, psi2_bar of its displacements (the transpose of the
+// linear maps of displace_batch, with S linearised about the noise).  The
+// axis split of the forward chain runs backwards: z and y passes take the
+// m_z, m_y powers and sum the fields that share a k_x power, so the x passes
+// see one field per power.
+//   S_bar = F^-1[i PSI2 (F_x Q0 + m_x F_x Q1)],
+//     Q0 = m_y F_zy psi2_bar_y + m_z F_zy psi2_bar_z, Q1 = F_zy psi2_bar_x;
+//   phi_bar_ij from S_bar and phi (product rule of S), phi by the forward split;
+//   w_bar = F^-1[-PHI sum_p m_x^p F_x Ubar_p - i PSI1 sum_p m_x^p F_x Vbar_p],
+//     Ubar_p, Vbar_p: the phi_bar_ij, psi1_bar_i of k_x power p, each times
+//     its m_y, m_z powers after F_zy.
+// Slots 0..14 of one realisation.
 lpt2_status backward_one(Ctx& c, const Tables* t, const void* noise, const void* g1, const void* g2, void* gw) {
   lpt2_plan_t p = c.p;
   hipStream_t s = c.s;
   Grid& g = c.g;
   const double fb = (double)c.field();
-  // S_bar = F^-1[ sum_i conj(-i m_i PSI2) F psi2_bar_i ]
-  CHK(fwd_zy(c, "z_r2c_gpsi2", "y_fwd_gpsi2", c.one(g2, 3), 3 * c.field(), c.slot(1)));
-  XOp o1 = op_blank(3, 1, 1);
+  // S_bar into slot 10 (real)
+  RUN("z_r2c_gpsi2", 2.0 * fb * 3,
+      launch_zr2c(p->prec, g.n, c.one(g2, 3), 3 * c.field(), c.slot(1), c.cap(c.slot(1)), g.tw, s));
+  const int nq[2] = {2, 1};
+  const int tq[3][3] = {{1, 1, 0}, {2, 0, 1}, {0, 0, 0}};  // Q0: y, z; Q1: x
+  CHK(yfan(c, "y_fan_gpsi2", c.slot(1), c.slot(4), yfan_op(3, 2, nq, tq)));
+  XOp o1 = op_blank(2, 1, 1);
   op_tables(o1, g, t);
-  for (int i = 0; i < 3; ++i) op_set(o1, i, MUL_PI, i, -1, TAB_PSI2, 1.0);
-  CHK(xp(c, "x_adj_psi2", c.slot(1), c.slot(10), o1));
+  op_set(o1, 0, MUL_PI, -1, -1, TAB_PSI2, 1.0);
+  op_set(o1, 1, MUL_PI, 0, -1, TAB_PSI2, 1.0);
+  CHK(xp(c, "x_adj_psi2", c.slot(4), c.slot(10), o1));
   CHK(inv_y(c, "y_inv_sbar", c.slot(10), 1));
   CHK(z_c2r_ws(c, "z_c2r_sbar", c.slot(10), 1));
-  // phi_,ij recomputed from the noise
+  // phi recomputed from the noise: U_p (slots 1..3), then phi stored as
+  // xx,xy,xz,yy,zz,yz in slots 4..9; phi_bar overwrites it there
   CHK(fwd_zy(c, "z_r2c_noise", "y_fwd_noise", c.one(noise, 1), c.field(), c.slot(0)));
-  XOp o2 = op_blank(1, 6, 1);
-  op_tables(o2, g, t);
-  for (int q = 0; q < 6; ++q) op_set(o2, q, MUL_REAL, PI_[q], PJ_[q], TAB_PHI, -1.0);
-  CHK(xp(c, "x_fused_phi", c.slot(0), c.slot(1), o2));
-  CHK(inv_y(c, "y_inv_phi", c.slot(1), 6));
-  RUN("z_adj_prodrule", fb * 14.0,
-      launch_zprodrule(p->prec, g.n, c.slot(1), c.cap(c.slot(1)), g.nnm, c.slot(10), c.cap(c.slot(10)), c.slot(1),
-                       c.cap(c.slot(1)), g.nnm, (long)g.n * g.n, g.tw, s));
+  CHK(xdisp(c, "x_phi_adj", 3, c.slot(0), c.slot(1), t));
+  const int src6[6] = {2, 1, 1, 0, 0, 0};
+  const int pw6[6] = {0, 1, 0, 2, 0, 1};
+  CHK(ycombo(c, "y_inv_phi_adj", c.slot(1), c.slot(4), yop(3, 6, src6, pw6)));
+  // product-rule pass order xx,yy,zz,xy,xz,yz: m_z powers and storage positions
+  ZPow zp = zpow_none();
+  const int rzs[6] = {0, 0, 2, 0, 1, 1};
+  const int fms[6] = {0, 3, 4, 1, 2, 5};
+  for (int f = 0; f < 6; ++f) {
+    zp.r[f] = rzs[f];
+    zp.fmap[f] = fms[f];
+  }
+  RUN("z_adj_prodrule", fb * 13.0,
+      launch_zprodrule(p->prec, g.n, c.slot(4), c.cap(c.slot(4)), g.nnm, c.slot(10), c.cap(c.slot(10)), c.slot(4),
+                       c.cap(c.slot(4)), g.nnm, (long)g.n * g.n, zp, g.tw, s));
   RUN("z_r2c_gpsi1", 2.0 * fb * 3,
-      launch_zr2c(p->prec, g.n, c.one(g1, 3), 3 * c.field(), c.slot(7), c.cap(c.slot(7)), g.tw, s));
-  CHK(fwd_y(c, "y_fwd_adj", c.slot(1), 9));
-  XOp o3 = op_blank(9, 1, 1);
+      launch_zr2c(p->prec, g.n, c.one(g1, 3), 3 * c.field(), c.slot(1), c.cap(c.slot(1)), g.tw, s));
+  // slots 1..9: psi1_bar x,y,z, phi_bar xx,xy,xz,yy,zz,yz -> Ubar0..2, Vbar0..1 in slots 10..14
+  const int nu[5] = {3, 2, 1, 2, 1};
+  const int tu[9][3] = {{6, 2, 0}, {7, 0, 2}, {8, 1, 1},  // Ubar0: yy, zz, yz
+                        {4, 1, 0}, {5, 0, 1},             // Ubar1: xy, xz
+                        {3, 0, 0},                        // Ubar2: xx
+                        {1, 1, 0}, {2, 0, 1},             // Vbar0: psi1 y, z
+                        {0, 0, 0}};                       // Vbar1: psi1 x
+  CHK(yfan(c, "y_fan_adj", c.slot(1), c.slot(10), yfan_op(9, 5, nu, tu)));
+  XOp o3 = op_blank(5, 1, 1);
   op_tables(o3, g, t);
-  for (int q = 0; q < 6; ++q) op_set(o3, q, MUL_REAL, PI_[q], PJ_[q], TAB_PHI, -1.0);
-  for (int i = 0; i < 3; ++i) op_set(o3, 6 + i, MUL_MI, i, -1, TAB_PSI1, 1.0);
-  CHK(xp(c, "x_adj_noise", c.slot(1), c.slot(0), o3));
+  op_set(o3, 0, MUL_REAL, -1, -1, TAB_PHI, -1.0);
+  op_set(o3, 1, MUL_REAL, 0, -1, TAB_PHI, -1.0);
+  op_set(o3, 2, MUL_REAL, 0, 0, TAB_PHI, -1.0);
+  op_set(o3, 3, MUL_MI, -1, -1, TAB_PSI1, 1.0);
+  op_set(o3, 4, MUL_MI, 0, -1, TAB_PSI1, 1.0);
+  CHK(xp(c, "x_adj_noise", c.slot(10), c.slot(0), o3));
   CHK(inv_y(c, "y_inv_gnoise", c.slot(0), 1));
   CHK(z_c2r(c, "z_c2r_gnoise", c.slot(0), c.one(gw, 1), c.field()));
   return LPT2_OK;

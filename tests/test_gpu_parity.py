@@ -353,7 +353,7 @@ def test_triangle_ratio_matches_oracle():
 
 
 # ---------------------------------------------------------------- adjoint and CIC
-@pytest.mark.parametrize("n", [8, 16])
+@pytest.mark.parametrize("n", [8, 16, 48, 96])
 def test_backward_matches_oracle_autograd(n):
     print(f"backward fp64 n={n}", flush=True)
     plan, cfg = _plan(n=n, box=2.0 * n, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=64)
@@ -366,10 +366,10 @@ def test_backward_matches_oracle_autograd(n):
     assert normwise(got, ref) < 1e-11
 
 
-def test_backward_fp32_matches_fp64_gpu():
-    print("backward fp32", flush=True)
-    n = 32
-    kw = dict(n=n, box=64.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=64)
+@pytest.mark.parametrize("n", [32, 48])
+def test_backward_fp32_matches_fp64_gpu(n):
+    print(f"backward fp32 n={n}", flush=True)
+    kw = dict(n=n, box=2.0 * n, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=64)
     p64, _ = _plan(precision="fp64", **kw)
     p32, _ = _plan(precision="fp32", **kw)
     w = white_noise(n, 4)
