@@ -171,12 +171,12 @@ lpt2_status lpt2_set_graph(lpt2_plan_t plan, int enable);
 
 /* Tile widths (columns per workgroup) of configuration `grid`'s strided
  * passes: tiles[0] the single y (and x) FFT passes, tiles[1] the fused y
- * pass, tiles[2] the fused x pass.  lpt2_tile_options writes the three
- * widths offered for that grid's n and precision (64-, 128- and 256-byte row
- * runs, clamped to the workgroup and LDS limits; entries may repeat).
- * lpt2_set_tiles takes widths from that list, or 0 for the default
- * (128-byte runs); anything else is LPT2_EINVAL.  Synchronises if the
- * tiles change. */
+ * passes, tiles[2] the fused x passes.  lpt2_tile_options writes 9 ints,
+ * widths[3*k + i] = option i of pass kind k: the widths giving 64-, 128- and
+ * 256-byte row runs, clamped to the workgroup and LDS limits of that kind
+ * (entries may repeat).  lpt2_set_tiles takes for each kind a width from its
+ * list, or 0 for the default (option 1); anything else is LPT2_EINVAL.
+ * Synchronises if the tiles change. */
 lpt2_status lpt2_get_tiles(lpt2_plan_t plan, int grid, int* tiles);
 lpt2_status lpt2_set_tiles(lpt2_plan_t plan, int grid, const int* tiles);
 lpt2_status lpt2_tile_options(lpt2_plan_t plan, int grid, int* widths);

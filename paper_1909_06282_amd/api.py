@@ -189,9 +189,10 @@ class Plan:
         _abi.check(self._lib.lpt2_set_graph(self.handle, int(bool(enable))), self.handle)
 
     def tile_options(self, grid: int = 0):
-        w = (C.c_int * 3)()
+        """[[widths of kind 0], [kind 1], [kind 2]]: the widths set_tiles accepts per pass kind."""
+        w = (C.c_int * 9)()
         _abi.check(self._lib.lpt2_tile_options(self.handle, int(grid), w), self.handle)
-        return list(w)
+        return [list(w[3 * k:3 * k + 3]) for k in range(3)]
 
     def get_tiles(self, grid: int = 0):
         w = (C.c_int * 3)()

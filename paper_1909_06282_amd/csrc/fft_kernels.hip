@@ -82,98 +82,20 @@ __device__ __forceinline__ void r2c_finish(Cx<T>* v, int t, Cx<T>* lb, const Cx<
   }
 }
 
-// Load a half-spectrum line X_0..X_{n/2-1}, each mode multiplied by m_z^r,
-// and form the packed spectrum Z_k = E_k + i O_k, E_k = X_k + X*_{L-k},
-// O_k = (X_k - X*_{L-k}) conj(W^k), with X_{n/2} = 0 and Im X_0 ignored, in
-// the inverse first-stage slots.  The unnormalised inverse FFT of Z then
-// gives n x_{2j} + i n x_{2j+1}.
-template <typename T, int N, bool PAD = true>
-__device__ __forceinline__ void c2r_prepare(const Cx<T>* src, int r, Cx<T>* v, int t, Cx<T>* lb, const Cx<T>* stw,
-                                            bool act) {
-  using C = LineCfg<N>;
-  wave_sync();
-#pragma unroll
-  for (int s = 0; s < C::E; ++s) {
-    const int k = t + s * C::TPL;
-    lb[lds_index<PAD>(k)] = act ? scale(src[k], mpow<T>(k, r)) : zero<T>();
-  }
-  wave_sync();
-#pragma unroll
-  for (int sl = 0; sl < C::E; ++sl) {
-    const int e = slot_elem<C::L, C::E, C::R0I>(t, sl);
-    Cx<T> x = lb[lds_index<PAD>(e)];
-    Cx<T> xc;
-    if (e == 0) {
-      x.y = T(0);
-      xc = zero<T>();
-    } else {
-      xc = conj(lb[lds_index<PAD>(C::L - e)]);
-    }
-    const Cx<T> ek = x + xc;
-    const Cx<T> ok = (x - xc) * conj(stw[e]);
-    v[sl] = mk(ek.x - ok.y, ek.y + ok.x);
-  }
-}
-
-// Line `line` of a Batch (f-major, then realisation, then line): where it
-// sits in the caller's buffer (reals) and in the workspace (complex).
-template <int N>
-__device__ __forceinline__ void batch_line(const Batch& b, long line, int& f, int& r, long& ext_off, long& ws_off) {
-  constexpr long NN = (long)N * N;
-  const int fr = (int)(line / NN);  // < nf * nr
-  const long l = line - (long)fr * NN;
-  f = fr / b.nr;
-  r = fr - f * b.nr;
-  ext_off = f * b.ext_fstride + l * N;
-  ws_off = f * b.ws_fstride + r * b.ws_rstride + l * (N / 2);
-}
-
+// A half-spectrum line X_0..X_{n/2-1} into registers (raw[s] = X_{t + s*TPL}).
+// Every load is issued before any is used, so they are in flight together;
+// callers pass an address inside the buffer also for an inactive line.
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_zr2c(Batch b, Cx<T>* ws, long nlines, const Cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void load_cx_line(const Cx<T>* src, Cx<T>* raw, int t) {
   using C = LineCfg<N>;
-  __shared__ Cx<T> lds[C::G * C::SPAN];
-  __shared__ Cx<T> stw[N];
-  stage_twiddles<T, N>(stw, tw);
-  const int t = threadIdx.x % C::TPL, g = threadIdx.x / C::TPL;
-  const long line = (long)blockIdx.x * C::G + g;
-  const bool act = line < nlines;
-  int f, r;
-  long eo, wo;
-  batch_line<N>(b, act ? line : 0, f, r, eo, wo);
-  Cx<T>* lb = lds + g * C::SPAN;
-  Cx<T> v[C::E];
-  load_real_line<T, N>(static_cast<const T*>(b.ext[r]) + eo, v, t, act);
-  fft<T, C::L, -1, 1, SY_WAVE, false>(v, t, stw, 2, lb);
-  r2c_finish<T, N, false>(v, t, lb, stw, ws + wo, act);
-}
-
-// field f of the batch is multiplied by m_z^zp.r[f] before the transform
-template <typename T, int N>
-__global__ __launch_bounds__(256) void k_zc2r(const Cx<T>* ws, Batch b, long nlines, ZPow zp,
-                                              const Cx<T>* __restrict__ tw) {
-  using C = LineCfg<N>;
-  __shared__ Cx<T> lds[C::G * C::SPAN];
-  __shared__ Cx<T> stw[N];
-  stage_twiddles<T, N>(stw, tw);
-  const int t = threadIdx.x % C::TPL, g = threadIdx.x / C::TPL;
-  const long line = (long)blockIdx.x * C::G + g;
-  const bool act = line < nlines;
-  int f, r;
-  long eo, wo;
-  batch_line<N>(b, act ? line : 0, f, r, eo, wo);
-  const int rp = f < ZPOW_MAX ? zp.r[f] : 0;
-  Cx<T>* lb = lds + g * C::SPAN;
-  Cx<T> v[C::E];
-  c2r_prepare<T, N, false>(ws + wo, rp, v, t, lb, stw, act);
-  fft<T, C::L, +1, 1, SY_WAVE, false>(v, t, stw, 2, lb);
-  Cx<T>* d2 = reinterpret_cast<Cx<T>*>(static_cast<T*>(const_cast<void*>(b.ext[r])) + eo);
-  if (act) {
 #pragma unroll
-    for (int sl = 0; sl < C::E; ++sl) d2[slot_elem<C::L, C::E, C::RLI>(t, sl)] = v[sl];
-  }
+  for (int s = 0; s < C::E; ++s) raw[s] = src[t + s * C::TPL];
 }
 
-// c2r_prepare for a line already held in registers (raw[s] = X_{t + s*TPL}).
+// From a line in registers, each mode multiplied by m_z^r, form the packed
+// spectrum Z_k = E_k + i O_k, E_k = X_k + X*_{L-k}, O_k = (X_k - X*_{L-k})
+// conj(W^k), with X_{n/2} = 0 and Im X_0 ignored, in the inverse first-stage
+// slots.  The unnormalised inverse FFT of Z then gives n x_{2j} + i n x_{2j+1}.
 template <typename T, int N, bool PAD = true>
 __device__ __forceinline__ void c2r_prepare_regs(const Cx<T>* raw, int r, Cx<T>* v, int t, Cx<T>* lb,
                                                  const Cx<T>* stw) {
@@ -201,6 +123,70 @@ __device__ __forceinline__ void c2r_prepare_regs(const Cx<T>* raw, int r, Cx<T>*
     v[sl] = mk(ek.x - ok.y, ek.y + ok.x);
   }
 }
+
+// Line `line` of a Batch (f-major, then realisation, then line): where it
+// sits in the caller's buffer (reals) and in the workspace (complex).
+// With G lines per block and G dividing n^2, a block's lines never straddle
+// a field, so (f, r) follow from the block index alone (scalar registers, and
+// the pointer table and per-field powers are read as scalars).  The caller
+// passes the block's first line for a line past the end.
+template <int N, int G>
+__device__ __forceinline__ void batch_line(const Batch& b, long line, int& f, int& r, long& ext_off, long& ws_off) {
+  constexpr long NN = (long)N * N;
+  const int fr = NN % G == 0 ? (int)(((long)blockIdx.x * G) / NN) : (int)(line / NN);  // < nf * nr
+  const long l = line - (long)fr * NN;
+  f = fr / b.nr;
+  r = fr - f * b.nr;
+  ext_off = f * b.ext_fstride + l * N;
+  ws_off = f * b.ws_fstride + r * b.ws_rstride + l * (N / 2);
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_zr2c(Batch b, Cx<T>* ws, long nlines, const Cx<T>* __restrict__ tw) {
+  using C = LineCfg<N>;
+  __shared__ Cx<T> lds[C::G * C::SPAN];
+  __shared__ Cx<T> stw[N];
+  stage_twiddles<T, N>(stw, tw);
+  const int t = threadIdx.x % C::TPL, g = threadIdx.x / C::TPL;
+  const long line = (long)blockIdx.x * C::G + g;
+  const bool act = line < nlines;
+  int f, r;
+  long eo, wo;
+  batch_line<N, C::G>(b, act ? line : (long)blockIdx.x * C::G, f, r, eo, wo);
+  Cx<T>* lb = lds + g * C::SPAN;
+  Cx<T> v[C::E];
+  load_real_line<T, N>(static_cast<const T*>(b.ext[r]) + eo, v, t, act);
+  fft<T, C::L, -1, 1, SY_WAVE, false>(v, t, stw, 2, lb);
+  r2c_finish<T, N, false>(v, t, lb, stw, ws + wo, act);
+}
+
+// field f of the batch is multiplied by m_z^zp.r[f] before the transform
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_zc2r(const Cx<T>* ws, Batch b, long nlines, ZPow zp,
+                                              const Cx<T>* __restrict__ tw) {
+  using C = LineCfg<N>;
+  __shared__ Cx<T> lds[C::G * C::SPAN];
+  __shared__ Cx<T> stw[N];
+  stage_twiddles<T, N>(stw, tw);
+  const int t = threadIdx.x % C::TPL, g = threadIdx.x / C::TPL;
+  const long line = (long)blockIdx.x * C::G + g;
+  const bool act = line < nlines;
+  int f, r;
+  long eo, wo;
+  batch_line<N, C::G>(b, act ? line : (long)blockIdx.x * C::G, f, r, eo, wo);
+  const int rp = f < ZPOW_MAX ? zp.r[f] : 0;
+  Cx<T>* lb = lds + g * C::SPAN;
+  Cx<T> v[C::E], raw[C::E];
+  load_cx_line<T, N>(ws + wo, raw, t);  // line 0 stands in for an inactive line
+  c2r_prepare_regs<T, N, false>(raw, rp, v, t, lb, stw);
+  fft<T, C::L, +1, 1, SY_WAVE, false>(v, t, stw, 2, lb);
+  Cx<T>* d2 = reinterpret_cast<Cx<T>*>(static_cast<T*>(const_cast<void*>(b.ext[r])) + eo);
+  if (act) {
+#pragma unroll
+    for (int sl = 0; sl < C::E; ++sl) d2[slot_elem<C::L, C::E, C::RLI>(t, sl)] = v[sl];
+  }
+}
+
 // S = phi_xx phi_yy + (phi_xx + phi_yy) phi_zz - phi_xy^2 - phi_xz^2 - phi_yz^2
 // per real value (logical field f of the six, stored at field zp.fmap[f],
 // multiplied by m_z^zp.r[f] first), then
@@ -285,13 +271,16 @@ __global__ __launch_bounds__(256) void k_zprodrule(const Cx<T>* phi, long fstrid
   const long lsafe = act ? line : 0;
   Cx<T>* lb = lds + g * C::SPAN;
   Cx<T> sb[C::E], d0[C::E], d1[C::E], d2[C::E], v[C::E];
-  load_real_line<T, N>(sbar + lsafe * N, sb, t, act);
+  load_real_line<T, N>(sbar + lsafe * N, sb, t, true);
   const Cx<T>* src = phi + lsafe * C::L;
-  c2r_prepare<T, N>(src + zp.fmap[0] * fstride, zp.r[0], d0, t, lb, stw, act);
+  load_cx_line<T, N>(src + zp.fmap[0] * fstride, v, t);
+  c2r_prepare_regs<T, N>(v, zp.r[0], d0, t, lb, stw);
   fft<T, C::L, +1, 1, SY_WAVE, true>(d0, t, stw, 2, lb);
-  c2r_prepare<T, N>(src + zp.fmap[1] * fstride, zp.r[1], d1, t, lb, stw, act);
+  load_cx_line<T, N>(src + zp.fmap[1] * fstride, v, t);
+  c2r_prepare_regs<T, N>(v, zp.r[1], d1, t, lb, stw);
   fft<T, C::L, +1, 1, SY_WAVE, true>(d1, t, stw, 2, lb);
-  c2r_prepare<T, N>(src + zp.fmap[2] * fstride, zp.r[2], d2, t, lb, stw, act);
+  load_cx_line<T, N>(src + zp.fmap[2] * fstride, v, t);
+  c2r_prepare_regs<T, N>(v, zp.r[2], d2, t, lb, stw);
   fft<T, C::L, +1, 1, SY_WAVE, true>(d2, t, stw, 2, lb);
   Cx<T>* dst = out + lsafe * C::L;
 #pragma unroll
@@ -308,7 +297,9 @@ __global__ __launch_bounds__(256) void k_zprodrule(const Cx<T>* phi, long fstrid
   r2c_finish<T, N>(v, t, lb, stw, dst + zp.fmap[2] * ofstride, act);
 #pragma unroll 1
   for (int f = 3; f < 6; ++f) {
-    c2r_prepare<T, N>(src + zp.fmap[f] * fstride, zp.r[f], v, t, lb, stw, act);
+    Cx<T> raw[C::E];
+    load_cx_line<T, N>(src + zp.fmap[f] * fstride, raw, t);
+    c2r_prepare_regs<T, N>(raw, zp.r[f], v, t, lb, stw);
     fft<T, C::L, +1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
 #pragma unroll
     for (int i = 0; i < C::E; ++i) v[i] = mk(T(-2) * sb[i].x * v[i].x, T(-2) * sb[i].y * v[i].y);
@@ -321,25 +312,30 @@ __global__ __launch_bounds__(256) void k_zprodrule(const Cx<T>* phi, long fstrid
 // strided column kernels: a block takes W adjacent columns of one plane
 // (lane = column fastest), so every row access is W contiguous complex.
 // ---------------------------------------------------------------------------
-// WW: columns per block; a block is WW * (N/8) threads.  Each (precision,
-// grid size) offers three widths for the tile tuner: half, one and two
-// times the width that gives 128-byte row runs, clamped to blocks of 64..1024
-// threads and to double-buffered tiles that fit the 160 KB LDS.
+// WW: columns per block; a block is WW * (N/E) threads.  Each (precision,
+// grid size, pass kind) offers three widths for the tile tuner: half, one
+// and two times the width that gives 128-byte row runs, clamped to blocks of
+// 64..1024 threads and to tiles whose LDS fits in 150 KB -- two exchange
+// buffers for the column FFT and x passes, one for the fused y passes (which
+// keep two where they fit; at n = 768 in FP32 only one does at 128 bytes).
 constexpr int col_tpc(int N) { return N / elems_per_thread(N); }
 constexpr int pow2_floor(int x) { return x >= 1024 ? 1024 : x >= 512 ? 512 : x >= 256 ? 256 : x >= 128 ? 128 : x >= 64 ? 64 : x >= 32 ? 32 : x >= 16 ? 16 : x >= 8 ? 8 : x >= 4 ? 4 : x >= 2 ? 2 : 1; }
 template <typename T>
 constexpr int col_wlo(int N) { return 64 / col_tpc(N) > 1 ? 64 / col_tpc(N) : 1; }
 template <typename T>
-constexpr int col_whi(int N) {
+constexpr int col_whi(int N, int kind) {
   const int byblock = 1024 / col_tpc(N);
-  const int bylds = pow2_floor((150 * 1024) / (2 * N * (int)sizeof(Cx<T>)));
+  const int bylds = pow2_floor((150 * 1024) / ((kind == KIND_MULTI ? 1 : 2) * N * (int)sizeof(Cx<T>)));
   return byblock < bylds ? byblock : bylds;
 }
 template <typename T>
-constexpr int clampw(int N, int w) { return w < col_wlo<T>(N) ? col_wlo<T>(N) : (w > col_whi<T>(N) ? col_whi<T>(N) : w); }
+constexpr int clampw(int N, int w, int kind) {
+  return w < col_wlo<T>(N) ? col_wlo<T>(N) : (w > col_whi<T>(N, kind) ? col_whi<T>(N, kind) : w);
+}
 template <typename T>
-constexpr int col_w(int N, int i) {
-  return clampw<T>(N, i == 0 ? 64 / (int)sizeof(Cx<T>) : (i == 1 ? 128 / (int)sizeof(Cx<T>) : 256 / (int)sizeof(Cx<T>)));
+constexpr int col_w(int N, int i, int kind) {
+  return clampw<T>(N, i == 0 ? 64 / (int)sizeof(Cx<T>) : (i == 1 ? 128 / (int)sizeof(Cx<T>) : 256 / (int)sizeof(Cx<T>)),
+                   kind);
 }
 
 template <typename T, int N, int WW>
@@ -353,7 +349,26 @@ struct ColCfg {
   static constexpr int R0F = plan_first(L, false), RLF = plan_last(L, false);
   static constexpr int R0I = plan_first(L, true), RLI = plan_last(L, true);
   static_assert(RLF == R0I && RLI == R0F, "reversed plans");
+  // the multi-transform passes keep two exchange buffers where they fit
+  static constexpr bool ONE = 2 * L * W * (int)sizeof(Cx<T>) > 150 * 1024;
+  // tiles of under 128 bytes per row share cache lines with their
+  // neighbours: those are dealt XCD by XCD (xcd_block)
+  static constexpr bool XCD = W * (int)sizeof(Cx<T>) < 128;
 };
+
+// Logical block index.  Workgroups are dealt to the 8 XCDs (each with its
+// own L2) round robin, block b to XCD b % 8; this numbers them so that each
+// XCD's blocks take one contiguous range, and neighbouring tiles meet in the
+// same L2 (measured at n = 768, 64-byte rows: y passes 10-25% faster; with
+// 128-byte rows the plain order was faster).
+__device__ __forceinline__ long xcd_block(long b, long g) {
+  const long q = g / 8;
+  return b < 8 * q ? (b % 8) * q + b / 8 : b;
+}
+template <typename C>
+__device__ __forceinline__ long block_index() {
+  return C::XCD ? xcd_block(blockIdx.x, gridDim.x) : (long)blockIdx.x;
+}
 
 template <typename T, int N, int WW, int D>
 __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_colfft(Cx<T>* __restrict__ data, int ncols, int bpp,
@@ -364,8 +379,9 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_colfft(Cx<T>* __r
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
   const int c = threadIdx.x % C::W, t = threadIdx.x / C::W;
-  const long plane = blockIdx.x / bpp;
-  const int col = (blockIdx.x % bpp) * C::W + c;
+  const long bx = block_index<C>();
+  const long plane = bx / bpp;
+  const int col = (int)(bx % bpp) * C::W + c;
   const bool act = col < ncols;
   Cx<T>* base = data + plane * plane_stride + (act ? col : 0);
   constexpr int RIN = (D < 0) ? C::R0F : C::R0I;
@@ -385,6 +401,9 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_colfft(Cx<T>* __r
 // several realisations follow each other).  Persistent over column tiles (the
 // grid holds the resident blocks): the column of the next source, or of the
 // next tile's first source, is loaded while the current outputs transform.
+// Two LDS exchange buffers where they fit, else one (n = 768 FP32: the
+// nine-output pass takes 7.3 ms with one buffer and 128-byte rows, 8.4 ms
+// with two and 64-byte rows).
 template <typename T, int N, int WW>
 __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T>* __restrict__ in, long fsi,
                                                                   Cx<T>* __restrict__ out, long fso, YOp op,
@@ -393,7 +412,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
   constexpr int M = N / 2;
   constexpr int BPP = (M + C::W - 1) / C::W;
   const long NTILES = nplanes * BPP;
-  __shared__ Cx<T> lds[2 * C::L * C::W];  // two exchange buffers
+  __shared__ Cx<T> lds[(C::ONE ? 1 : 2) * C::L * C::W];  // exchange buffers
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
   int phase = 0;
@@ -413,7 +432,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
 #pragma unroll
     for (int sl = 0; sl < C::E; ++sl) pf[sl] = a ? b[slot_elem<C::L, C::E, C::R0I>(t, sl) * M] : zero<T>();
   };
-  long tile = blockIdx.x;
+  long tile = block_index<C>();
   if (tile < NTILES) load(tile, op.src[0]);
 #pragma unroll 1
   for (; tile < NTILES; tile += gridDim.x) {
@@ -437,7 +456,10 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
         const int iy = slot_elem<C::L, C::E, C::R0I>(t, sl);
         y[sl] = scale(v[sl], mpow<T>(iy < N / 2 ? iy : iy - N, pw));
       }
-      fft<T, C::L, +1, C::W, SY_PING>(y, t, stw, 1, lds + c, C::L * C::W, &phase);
+      if constexpr (C::ONE)
+        fft<T, C::L, +1, C::W, SY_BLOCK>(y, t, stw, 1, lds + c);
+      else
+        fft<T, C::L, +1, C::W, SY_PING>(y, t, stw, 1, lds + c, C::L * C::W, &phase);
       if (act) {
         Cx<T>* d = out + o * fso + off;
 #pragma unroll
@@ -461,7 +483,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_yfanin(const Cx<T
   constexpr int M = N / 2;
   constexpr int BPP = (M + C::W - 1) / C::W;
   const long NTILES = nplanes * BPP;
-  __shared__ Cx<T> lds[2 * C::L * C::W];  // two exchange buffers
+  __shared__ Cx<T> lds[(C::ONE ? 1 : 2) * C::L * C::W];  // exchange buffers
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
   int phase = 0;
@@ -475,7 +497,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_yfanin(const Cx<T
 #pragma unroll
     for (int sl = 0; sl < C::E; ++sl) pf[sl] = a ? b[slot_elem<C::L, C::E, C::R0F>(t, sl) * M] : zero<T>();
   };
-  long tile = blockIdx.x;
+  long tile = block_index<C>();
   if (tile < NTILES) load(tile, op.src[0]);
 #pragma unroll 1
   for (; tile < NTILES; tile += gridDim.x) {
@@ -492,7 +514,10 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_yfanin(const Cx<T
         load(tile, op.src[k + 1]);
       else if (tile + gridDim.x < NTILES)
         load(tile + gridDim.x, op.src[0]);
-      fft<T, C::L, -1, C::W, SY_PING>(v, t, stw, 1, lds + c, C::L * C::W, &phase);
+      if constexpr (C::ONE)
+        fft<T, C::L, -1, C::W, SY_BLOCK>(v, t, stw, 1, lds + c);
+      else
+        fft<T, C::L, -1, C::W, SY_PING>(v, t, stw, 1, lds + c, C::L * C::W, &phase);
       const T fz = mpow<T>(col, op.pz[k]);
       const bool start = k == op.first[o];
 #pragma unroll
@@ -539,6 +564,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
   constexpr int M = N / 2;
   constexpr long NCOL = (long)N * M;
   constexpr long FIELD = (long)N * NCOL;  // one realisation's half spectrum
+  static_assert(!C::ONE, "x-pass widths keep two exchange buffers");
   __shared__ Cx<T> lds[2 * C::L * C::W];  // two exchange buffers
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
@@ -559,7 +585,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
 #pragma unroll
     for (int sl = 0; sl < C::E; ++sl) pf[sl] = a ? ld_nt(&in[cs + slot_elem<C::L, C::E, C::R0F>(t, sl) * NCOL]) : zero<T>();
   };
-  long tile = blockIdx.x;
+  long tile = block_index<C>();
   if (tile < NTILES) load(tile);
 #pragma unroll 1
   for (; tile < NTILES; tile += gridDim.x) {
@@ -652,7 +678,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xpass(const Cx<T>
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
   const int c = threadIdx.x % C::W, t = threadIdx.x / C::W;
-  const long col = (long)blockIdx.x * C::W + c;
+  const long col = block_index<C>() * C::W + c;
   const bool act = col < NCOL;
   const long cs = act ? col : 0;
   const int iy = (int)(cs / M), iz = (int)(cs % M);
@@ -738,8 +764,9 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xpass(const Cx<T>
     default: return hipErrorInvalidValue; \
   }
 
-int col_width(int prec, int n, int i) {
-#define W_(NN) return prec == PREC_F32 ? col_w<float>(NN, i) : col_w<double>(NN, i)
+int col_width(int prec, int n, int kind, int i) {
+  if (kind < KIND_COL || kind > KIND_X) return 0;
+#define W_(NN) return prec == PREC_F32 ? col_w<float>(NN, i, kind) : col_w<double>(NN, i, kind)
   switch (n) {
     case 8: W_(8);
     case 16: W_(16);
@@ -758,12 +785,9 @@ int col_width(int prec, int n, int i) {
 #undef W_
   return 0;
 }
-// 128-byte row runs (measured on MI355X: narrower tiles lose more to the
-// access granularity than they gain from extra blocks per CU)
-int default_width(int prec, int n, int kind) {
-  (void)kind;
-  return col_width(prec, n, 1);
-}
+// 128-byte row runs where offered (measured on MI355X: narrower tiles lose
+// more to the access granularity than they gain from extra blocks per CU)
+int default_width(int prec, int n, int kind) { return col_width(prec, n, kind, 1); }
 
 // Blocks of a persistent kernel that can be resident at once (occupancy of
 // this kernel x compute units); the grid is this, at most one per tile.
@@ -930,9 +954,10 @@ static hipError_t colfft_w(int dir, void* data, long nplanes, long plane_stride,
 template <typename T, int N>
 static hipError_t colfft_t(int w, int dir, void* data, long nplanes, long plane_stride, int ncols, long rowstride,
                            const void* tw, hipStream_t s) {
-  if (w == col_w<T>(N, 0)) return colfft_w<T, N, col_w<T>(N, 0)>(dir, data, nplanes, plane_stride, ncols, rowstride, tw, s);
-  if (w == col_w<T>(N, 1)) return colfft_w<T, N, col_w<T>(N, 1)>(dir, data, nplanes, plane_stride, ncols, rowstride, tw, s);
-  if (w == col_w<T>(N, 2)) return colfft_w<T, N, col_w<T>(N, 2)>(dir, data, nplanes, plane_stride, ncols, rowstride, tw, s);
+  constexpr int K = KIND_COL;
+  if (w == col_w<T>(N, 0, K)) return colfft_w<T, N, col_w<T>(N, 0, K)>(dir, data, nplanes, plane_stride, ncols, rowstride, tw, s);
+  if (w == col_w<T>(N, 1, K)) return colfft_w<T, N, col_w<T>(N, 1, K)>(dir, data, nplanes, plane_stride, ncols, rowstride, tw, s);
+  if (w == col_w<T>(N, 2, K)) return colfft_w<T, N, col_w<T>(N, 2, K)>(dir, data, nplanes, plane_stride, ncols, rowstride, tw, s);
   return hipErrorInvalidValue;
 }
 hipError_t launch_colfft(int prec, int n, int dir, void* data, size_t cap, long nplanes, long plane_stride,
@@ -964,9 +989,10 @@ static hipError_t ycombo_w(int nr, const void* in, long fsi, void* out, long fso
 template <typename T, int N>
 static hipError_t ycombo_t(int w, int nr, const void* in, long fsi, void* out, long fso, const YOp& op, const void* tw,
                            hipStream_t s) {
-  if (w == col_w<T>(N, 0)) return ycombo_w<T, N, col_w<T>(N, 0)>(nr, in, fsi, out, fso, op, tw, s);
-  if (w == col_w<T>(N, 1)) return ycombo_w<T, N, col_w<T>(N, 1)>(nr, in, fsi, out, fso, op, tw, s);
-  if (w == col_w<T>(N, 2)) return ycombo_w<T, N, col_w<T>(N, 2)>(nr, in, fsi, out, fso, op, tw, s);
+  constexpr int K = KIND_MULTI;
+  if (w == col_w<T>(N, 0, K)) return ycombo_w<T, N, col_w<T>(N, 0, K)>(nr, in, fsi, out, fso, op, tw, s);
+  if (w == col_w<T>(N, 1, K)) return ycombo_w<T, N, col_w<T>(N, 1, K)>(nr, in, fsi, out, fso, op, tw, s);
+  if (w == col_w<T>(N, 2, K)) return ycombo_w<T, N, col_w<T>(N, 2, K)>(nr, in, fsi, out, fso, op, tw, s);
   return hipErrorInvalidValue;
 }
 hipError_t launch_ycombo(int prec, int n, int nr, const void* in, size_t in_cap, long in_fstride, void* out,
@@ -1000,9 +1026,10 @@ static hipError_t yfanin_w(int nr, const void* in, long fsi, void* out, long fso
 template <typename T, int N>
 static hipError_t yfanin_t(int w, int nr, const void* in, long fsi, void* out, long fso, const YFan& op, const void* tw,
                            hipStream_t s) {
-  if (w == col_w<T>(N, 0)) return yfanin_w<T, N, col_w<T>(N, 0)>(nr, in, fsi, out, fso, op, tw, s);
-  if (w == col_w<T>(N, 1)) return yfanin_w<T, N, col_w<T>(N, 1)>(nr, in, fsi, out, fso, op, tw, s);
-  if (w == col_w<T>(N, 2)) return yfanin_w<T, N, col_w<T>(N, 2)>(nr, in, fsi, out, fso, op, tw, s);
+  constexpr int K = KIND_MULTI;
+  if (w == col_w<T>(N, 0, K)) return yfanin_w<T, N, col_w<T>(N, 0, K)>(nr, in, fsi, out, fso, op, tw, s);
+  if (w == col_w<T>(N, 1, K)) return yfanin_w<T, N, col_w<T>(N, 1, K)>(nr, in, fsi, out, fso, op, tw, s);
+  if (w == col_w<T>(N, 2, K)) return yfanin_w<T, N, col_w<T>(N, 2, K)>(nr, in, fsi, out, fso, op, tw, s);
   return hipErrorInvalidValue;
 }
 static bool yfan_ok(const YFan& op) {
@@ -1056,14 +1083,15 @@ static hipError_t xdisp_w(int nr, int mode, const void* in, void* out, long fso,
 template <typename T, int N>
 static hipError_t xdisp_t(int w, int nr, int mode, const void* in, void* out, long fso, const void* tab,
                           const void* tw, hipStream_t s) {
-  if (w == col_w<T>(N, 0)) return xdisp_w<T, N, col_w<T>(N, 0)>(nr, mode, in, out, fso, tab, tw, s);
-  if (w == col_w<T>(N, 1)) return xdisp_w<T, N, col_w<T>(N, 1)>(nr, mode, in, out, fso, tab, tw, s);
-  if (w == col_w<T>(N, 2)) return xdisp_w<T, N, col_w<T>(N, 2)>(nr, mode, in, out, fso, tab, tw, s);
+  constexpr int K = KIND_X;
+  if (w == col_w<T>(N, 0, K)) return xdisp_w<T, N, col_w<T>(N, 0, K)>(nr, mode, in, out, fso, tab, tw, s);
+  if (w == col_w<T>(N, 1, K)) return xdisp_w<T, N, col_w<T>(N, 1, K)>(nr, mode, in, out, fso, tab, tw, s);
+  if (w == col_w<T>(N, 2, K)) return xdisp_w<T, N, col_w<T>(N, 2, K)>(nr, mode, in, out, fso, tab, tw, s);
   return hipErrorInvalidValue;
 }
 hipError_t launch_xdisp(int prec, int n, int nr, int mode, const void* in, size_t in_cap, void* out, size_t out_cap,
                         long out_fstride, const void* tab, size_t tab_cap, const void* tw, hipStream_t s, int w) {
-  if (w == 0) w = default_width(prec, n, KIND_MULTI);
+  if (w == 0) w = default_width(prec, n, KIND_X);
   if (!pow2n(n) || !in || !out || !tab || !tw || out_fstride < 0 || mode < 0 || mode > 3 || nr < 1)
     return hipErrorInvalidValue;
   const size_t cb = 2 * esize(prec), field = (size_t)nr * n * n * (n / 2);
@@ -1081,7 +1109,7 @@ hipError_t launch_xdisp(int prec, int n, int nr, int mode, const void* in, size_
 template <typename T, int N>
 static hipError_t xpass_t(const void* in, long fsi, void* out, long fso, const XOp& op, const void* tw,
                           hipStream_t s) {
-  constexpr int WW = col_w<T>(N, 1);
+  constexpr int WW = col_w<T>(N, 1, KIND_X);
   using C = ColCfg<T, N, WW>;
   const long ncol = (long)N * (N / 2);
   const long blocks = (ncol + C::W - 1) / C::W;

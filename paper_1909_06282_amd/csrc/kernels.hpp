@@ -74,8 +74,10 @@ hipError_t launch_zc2r(int prec, int n, const void* ws, size_t ws_cap, const Bat
 // w: columns per block, one of col_width(n, 0..2); 0 picks default_width
 hipError_t launch_colfft(int prec, int n, int dir, void* data, size_t cap, long nplanes, long plane_stride,
                          int ncols, long rowstride, const void* tw, hipStream_t s, int w = 0);
-enum { KIND_COL = 0, KIND_MULTI = 1 };
-int col_width(int prec, int n, int i);       // the three tile widths offered for (precision, grid size)
+// pass kinds with a tile width of their own: single column FFTs, fused y
+// passes, fused x passes (the index into a grid's tiles[])
+enum { KIND_COL = 0, KIND_MULTI = 1, KIND_X = 2 };
+int col_width(int prec, int n, int kind, int i);  // the three widths offered for (precision, n, kind); 0 if none
 int default_width(int prec, int n, int kind);
 // fused inverse y pass over the nr*n planes x n/2 columns of each field
 // (nr realisations stored one after the other inside every field slot)

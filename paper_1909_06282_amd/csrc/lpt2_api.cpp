@@ -916,7 +916,7 @@ lpt2_status graph_for(lpt2_plan_t p, double a, const std::vector<Tables*>& tabs,
 lpt2_status set_tiles(lpt2_plan_t p, Grid& g, const int* tiles) {
   for (int k = 0; k < 3; ++k) {
     bool ok = tiles[k] == 0;
-    for (int i = 0; i < 3; ++i) ok = ok || tiles[k] == col_width(p->prec, g.n, i);
+    for (int i = 0; i < 3; ++i) ok = ok || tiles[k] == col_width(p->prec, g.n, k, i);
     if (!ok) return fail(p, LPT2_EINVAL, "tile width " + std::to_string(tiles[k]) + " not offered for this grid");
   }
   bool same = true;
@@ -1004,19 +1004,20 @@ lpt2_status autotune(lpt2_plan_t p, const std::vector<Tables*>& tabs, const void
     const std::string key = tune_key(p, g);
     int tiles[3];
     if (tune_lookup(path, key, tiles) && set_tiles(p, g, tiles) == LPT2_OK) continue;
-    int opt[3], nopt = 0;
-    for (int i = 0; i < 3; ++i) {
-      const int w = col_width(p->prec, g.n, i);
-      bool dup = false;
-      for (int j = 0; j < nopt; ++j) dup = dup || opt[j] == w;
-      if (!dup) opt[nopt++] = w;
-    }
+    int opt[3][3], nopt[3] = {0, 0, 0};  // distinct widths per pass kind
+    for (int k = 0; k < 3; ++k)
+      for (int i = 0; i < 3; ++i) {
+        const int w = col_width(p->prec, g.n, k, i);
+        bool dup = false;
+        for (int j = 0; j < nopt[k]; ++j) dup = dup || opt[k][j] == w;
+        if (!dup) opt[k][nopt[k]++] = w;
+      }
     float best = 1e30f;
     int bt[3] = {0, 0, 0};
-    for (int i0 = 0; i0 < nopt && st == LPT2_OK; ++i0)
-      for (int i1 = 0; i1 < nopt && st == LPT2_OK; ++i1)
-        for (int i2 = 0; i2 < nopt && st == LPT2_OK; ++i2) {
-          const int tt[3] = {opt[i0], opt[i1], opt[i2]};
+    for (int i0 = 0; i0 < nopt[0] && st == LPT2_OK; ++i0)
+      for (int i1 = 0; i1 < nopt[1] && st == LPT2_OK; ++i1)
+        for (int i2 = 0; i2 < nopt[2] && st == LPT2_OK; ++i2) {
+          const int tt[3] = {opt[0][i0], opt[1][i1], opt[2][i2]};
           st = set_tiles(p, g, tt);
           float ms = 0.f;
           if (st == LPT2_OK) st = time_grid(p, (int)gi, tabs[gi], noise, psi1, psi2, s, 3, &ms);
@@ -1407,14 +1408,15 @@ lpt2_status lpt2_get_tiles(lpt2_plan_t p, int grid, int* tiles) {
   if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
   if (!tiles || grid < 0 || grid >= (int)p->grids.size()) return fail(p, LPT2_EINVAL, "bad grid index or NULL");
   const Grid& g = p->grids[grid];
-  for (int k = 0; k < 3; ++k) tiles[k] = g.tiles[k] ? g.tiles[k] : default_width(p->prec, g.n, k == 0 ? KIND_COL : KIND_MULTI);
+  for (int k = 0; k < 3; ++k) tiles[k] = g.tiles[k] ? g.tiles[k] : default_width(p->prec, g.n, k);
   return LPT2_OK;
 }
 
 lpt2_status lpt2_tile_options(lpt2_plan_t p, int grid, int* widths) {
   if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
   if (!widths || grid < 0 || grid >= (int)p->grids.size()) return fail(p, LPT2_EINVAL, "bad grid index or NULL");
-  for (int i = 0; i < 3; ++i) widths[i] = col_width(p->prec, p->grids[grid].n, i);
+  for (int k = 0; k < 3; ++k)
+    for (int i = 0; i < 3; ++i) widths[3 * k + i] = col_width(p->prec, p->grids[grid].n, k, i);
   return LPT2_OK;
 }
 

@@ -143,9 +143,9 @@ def test_tile_widths_do_not_change_results(prec):
     ref1 = [x.clone() for x in ref1]
     ref2 = [x.clone() for x in ref2]
     for g in range(2):
-        opts = sorted(set(plan.tile_options(g)))
-        for w in opts:
-            for k in range(3):
+        opts = plan.tile_options(g)
+        for k in range(3):
+            for w in sorted(set(opts[k])):
                 t = plan.get_tiles(g)
                 t[k] = w
                 plan.set_tiles(g, t)
@@ -159,7 +159,7 @@ def test_tile_widths_do_not_change_results(prec):
 def test_set_tiles_rejects_widths_not_offered():
     from paper_1909_06282_amd import LPT2Error, Plan
     plan = Plan(_cfg(32, "fp32"))
-    bad = max(plan.tile_options(0)) * 2 + 1
+    bad = max(max(o) for o in plan.tile_options(0)) * 2 + 1
     with pytest.raises(LPT2Error):
         plan.set_tiles(0, [bad, 0, 0])
     with pytest.raises(LPT2Error):
@@ -181,7 +181,7 @@ def test_autotune_picks_offered_tiles_and_caches_them(tmp_path):
     lines = cache.read_text().splitlines()
     assert len(lines) == 2 and all(ln.startswith("lpt2-tiles ") for ln in lines)
     for g, t in enumerate(tiles):
-        assert all(x in plan.tile_options(g) for x in t)
+        assert all(x in opts for x, opts in zip(t, plan.tile_options(g)))
     q1, q2 = plan.displace(1.0, noise)
     torch.cuda.synchronize()
     for i in range(len(noise)):

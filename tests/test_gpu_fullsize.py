@@ -166,9 +166,46 @@ def test_c4_batched_graph_fp32_vs_fp64_and_oracle(tmp_path):
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
 def test_mixed_radix_384_displacements(prec, tol):
-    # three times a power of two: 384^3 (L = 768, 2 Mpc/h cells) against the oracle
+    # three times a power of two: 384^3 (L = 768, 2 Mpc/h cells) against the
+    # oracle, with the default tiles and with the widest fused-y tile (whose
+    # two LDS exchange buffers do not fit: one buffer, block-wide barriers)
     print(f"mixed radix 384^3 {prec}", flush=True)
-    _parity(prec, 1.0, 2, tol, n=384, box=768.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1")
+    plan, cfg = _plan(precision=prec, n=384, box=768.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1")
+    m = oracle_model(cfg)
+    w = white_noise(cfg.n, 2)
+    r1, r2 = fields.displace(w, m, 1.0, growth.tables(m, 1.0))
+    wide = max(plan.tile_options(0)[1])
+    for tiles in ([0, 0, 0], [0, wide, 0]):
+        plan.set_tiles(0, tiles)
+        p1, p2 = plan.displace(1.0, to_dev(w, cfg.dtype))
+        torch.cuda.synchronize()
+        g1, g2 = p1.cpu().double(), p2.cpu().double()
+        del p1, p2
+        e1, e2, et = normwise(g1, r1), normwise(g2, r2), normwise(g1 + g2, r1 + r2)
+        print(f"  tiles {plan.get_tiles(0)}: psi1 {e1:.3e} psi2 {e2:.3e} total {et:.3e}", flush=True)
+        assert e1 < tol and e2 < tol and et < tol
+    plan.close()
+
+
+def test_backward_384_wide_fan_in_tile_agrees():
+    # the adjoint's fan-in y pass with one LDS exchange buffer (widest tile)
+    # against the same gradient with the default tiles (pinned to the oracle
+    # at n <= 96 in the parity tests)
+    print("backward 384^3 fp32 wide fused-y tile", flush=True)
+    n = 384
+    plan, cfg = _plan(precision="fp32", n=n, box=768.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1")
+    w = to_dev(white_noise(n, 3), torch.float32)
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    g1 = torch.randn((3, n, n, n), generator=gen, device="cuda")
+    g2 = torch.randn((3, n, n, n), generator=gen, device="cuda")
+    a = plan.backward(1.0, w, g1, g2).clone()
+    plan.set_tiles(0, [0, max(plan.tile_options(0)[1]), 0])
+    b = plan.backward(1.0, w, g1, g2)
+    torch.cuda.synchronize()
+    e = float((b - a).norm() / a.norm())
+    print(f"  tiles {plan.get_tiles(0)}: relative L2 {e:.3e}", flush=True)
+    assert e < 1e-5
+    plan.close()
 
 
 def test_mixed_radix_768_fp32_vs_fp64():
