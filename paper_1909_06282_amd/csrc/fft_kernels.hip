@@ -196,13 +196,11 @@ __global__ __launch_bounds__(256) void k_zc2r(const Cx<T>* ws, Batch b, long nli
 // S = phi_xx phi_yy + (phi_xx + phi_yy) phi_zz - phi_xy^2 - phi_xz^2 - phi_yz^2
 // per real value (logical field f of the six, stored at field zp.fmap[f],
 // multiplied by m_z^zp.r[f] first), then
-// the forward R2C of the S line.  The line of field f+1 is loaded while
-// field f is transformed, so the load latency hides behind the transform.
-// The field loop is not unrolled: unrolled, the six transforms with the
-// prefetch in flight need ~240 VGPRs (two waves per SIMD) in FP32, rolled
-// ~170 (three), and measured 15% faster at n = 512.  In FP64 the prefetch
-// alone would leave one wave per SIMD, so FP64 loads each field in turn
-// (measured 35% faster at n = 512).
+// the forward R2C of the S line.  The field loop is not unrolled: unrolled,
+// the six transforms need ~240 VGPRs (two waves per SIMD) in FP32, rolled
+// ~165 (three), and measured 15% faster at n = 512.  Every load of a line is
+// issued before any is used (the compiler then waits once per line, not per
+// element).
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_zsource(const Cx<T>* __restrict__ phi, long fstride, ZPow zp,
                                                  Cx<T>* __restrict__ sk, long nlines, const Cx<T>* __restrict__ tw) {
@@ -215,18 +213,22 @@ __global__ __launch_bounds__(256) void k_zsource(const Cx<T>* __restrict__ phi, 
   const bool act = line < nlines;
   const long lsafe = act ? line : 0;
   Cx<T>* lb = lds + g * C::SPAN;
-  constexpr bool PF = sizeof(T) == 4;  // prefetch the next field (FP32 only: FP64 runs out of VGPRs)
-  Cx<T> a[C::E], s[C::E], v[C::E], raw[C::E], nxt[C::E];
-  const Cx<T>* src = phi + lsafe * C::L;
+  // FP32 loads the next field's line into raw as soon as raw has gone to
+  // LDS, so it is in flight during this field's transform; FP64 loads it
+  // after the transform (in flight during it, FP64 needs 256 VGPRs and ran
+  // 11% slower at n = 512)
+  constexpr bool PF = sizeof(T) == 4;
+  Cx<T> a[C::E], s[C::E], v[C::E], raw[C::E];
+  const Cx<T>* src = phi + lsafe * C::L;  // line 0 stands in for an inactive line
+  auto load_field = [&](int f) {
 #pragma unroll
-  for (int q = 0; q < C::E; ++q) raw[q] = act ? src[zp.fmap[0] * fstride + t + q * C::TPL] : zero<T>();
+    for (int q = 0; q < C::E; ++q) raw[q] = src[zp.fmap[f] * fstride + t + q * C::TPL];
+  };
+  load_field(0);
 #pragma unroll 1
   for (int f = 0; f < 6; ++f) {
-    if (PF && f < 5) {
-#pragma unroll
-      for (int q = 0; q < C::E; ++q) nxt[q] = act ? src[zp.fmap[f + 1] * fstride + t + q * C::TPL] : zero<T>();
-    }
     c2r_prepare_regs<T, N>(raw, zp.r[f], v, t, lb, stw);
+    if (PF && f < 5) load_field(f + 1);
     fft<T, C::L, +1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
     if (f == 0) {
 #pragma unroll
@@ -244,13 +246,7 @@ __global__ __launch_bounds__(256) void k_zsource(const Cx<T>* __restrict__ phi, 
 #pragma unroll
       for (int i = 0; i < C::E; ++i) s[i] = mk(s[i].x - v[i].x * v[i].x, s[i].y - v[i].y * v[i].y);
     }
-    if (PF) {
-#pragma unroll
-      for (int q = 0; q < C::E; ++q) raw[q] = nxt[q];
-    } else if (f < 5) {
-#pragma unroll
-      for (int q = 0; q < C::E; ++q) raw[q] = act ? src[zp.fmap[f + 1] * fstride + t + q * C::TPL] : zero<T>();
-    }
+    if (!PF && f < 5) load_field(f + 1);
   }
   fft<T, C::L, -1, 1, SY_WAVE, true>(s, t, stw, 2, lb);
   r2c_finish<T, N>(s, t, lb, stw, sk + lsafe * C::L, act);
