@@ -216,7 +216,7 @@ def epochs_timing(reps: int):
 
 def grid768_timing(reps: int):
     """The paper's own grid size: one 768^3 realisation in 750 Mpc/h (three
-    times a power of two: radix-3 stages), |f_R0| = 1e-5, z = 0, FP32."""
+    times a power of two: a radix-12 first stage), |f_R0| = 1e-5, z = 0, FP32."""
     import numpy as np
     import torch
     from paper_1909_06282_amd import LPT2Config, Plan
@@ -236,6 +236,25 @@ def grid768_timing(reps: int):
     return {"workload": "768^3 (L=750 Mpc/h) |f_R0|=1e-5 z=0 FP32 seed 1", "ms_per_step": round(ms, 3),
             "value": float(n) ** 3 / (ms / 1e3), "unit": "grid-cells/s",
             "algorithmic_GBps": round(53 * 4 * float(n) ** 3 / (ms / 1e3) / 1e9, 1), "kernels": prof}
+
+
+def matter_power_timing(reps: int):
+    """The matter power spectrum of the displaced particles at 512^3 (L=1024,
+    |f_R0|=1e-6, z=0, FP32, seed 1): CIC paint of q + psi1 + psi2, forward 3D
+    FFT, 256 shells with the CIC window divided out."""
+    import numpy as np
+    import torch
+    from paper_1909_06282_amd import LPT2Config, Plan
+    from seeded_inputs import white_noise
+    plan = Plan(LPT2Config(n=N, box=BOX, gravity="fr_hs", fr0_abs=1e-6, factorisation="t1", precision="fp32"))
+    w = torch.from_numpy(white_noise(N, 1, np.float32)).cuda()
+    p1, p2 = plan.displace(1.0, w)
+    delta = torch.empty((N, N, N), dtype=torch.float32, device="cuda")
+    t_pk = _timed(lambda: plan.matter_power(p1, p2, 256, deconvolve=True), reps)
+    t_paint = _timed(lambda: plan.paint_cic(p1, p2, delta), reps)
+    return {"workload": "512^3 (L=1024) |f_R0|=1e-6 z=0 FP32 seed 1, 256 shells, CIC window divided out",
+            "ms_matter_power": round(t_pk, 3), "ms_cic_paint": round(t_paint, 3),
+            "value": float(N) ** 3 / (t_pk / 1e3), "unit": "particles/s"}
 
 
 def choice_timing(reps: int):
@@ -407,6 +426,7 @@ def main():
     if not args.no_extra:
         out["adjoint"] = adjoint_timing(8)
         out["factorisation_choice"] = choice_timing(3)
+        out["matter_power"] = matter_power_timing(3)
         torch.cuda.empty_cache()
         out["epochs"] = epochs_timing(4)
         torch.cuda.empty_cache()
