@@ -380,13 +380,17 @@ def test_backward_fp32_matches_fp64_gpu(n):
     assert normwise(b, a) < F32_TOL
 
 
-def test_cic_paint_and_transpose_match_oracle():
-    print("cic", flush=True)
-    n = 16
-    plan, cfg = _plan(n=n, box=32.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=64)
+@pytest.mark.parametrize("n,stretch", [(16, 1.0), (8, 1.0), (24, 1.0), (48, 1.0), (32, 6.0)])
+def test_cic_paint_and_transpose_match_oracle(n, stretch):
+    # n = 8: one tile per axis (both regions covering a cell are the same
+    # tile); 24, 48: an odd number of tiles; stretch 6: most particles leave
+    # their tile's halo and are added with atomics
+    print(f"cic n={n} stretch={stretch}", flush=True)
+    plan, cfg = _plan(n=n, box=2.0 * n, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=64)
     m = oracle_model(cfg)
     w = white_noise(n, 7)
     p1, p2 = plan.displace(1.0, to_dev(w, torch.float64))
+    p1, p2 = p1 * stretch, p2 * stretch
     d = plan.paint_cic(p1, p2)
     ref = cic.paint(p1.cpu() + p2.cpu(), m)
     assert float((d.cpu() - ref).abs().max()) < 1e-12
