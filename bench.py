@@ -282,10 +282,15 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 companion measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-mix measurement")
     ap.add_argument("--no-extra", action="store_true", help="skip the adjoint and factorisation-choice timings")
+    ap.add_argument("--only-768", action="store_true",
+                    help="time only the 768^3 grid (for profiling it) and print its record")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.only_768:
+        print(json.dumps({"grid_768": grid768_timing(max(1, args.steps))}), flush=True)
+        return
 
     import numpy as np
     import torch
