@@ -286,7 +286,7 @@ def main():
                     help="time only the 768^3 grid (for profiling it) and print its record")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.only_768:
         print(json.dumps({"grid_768": grid768_timing(max(1, args.steps))}), flush=True)
