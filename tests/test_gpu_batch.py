@@ -209,6 +209,15 @@ def test_epochs_equal_separate_displacements(prec):
     from paper_1909_06282_amd import LPT2Error
     with pytest.raises(LPT2Error):
         plan.displace_epochs([1.0] * 17, noise)
+    # the largest number of epochs per call
+    a16 = [1.0 / (1.0 + 0.2 * j) for j in range(16)]
+    outs = plan.displace_epochs(a16, noise)
+    torch.cuda.synchronize()
+    for j in (0, 7, 15):
+        q1, q2 = plan.displace(a16[j], noise)
+        torch.cuda.synchronize()
+        for i in range(len(noise)):
+            assert torch.equal(outs[j][0][i], q1[i]) and torch.equal(outs[j][1][i], q2[i]), (j, i)
 
 
 def test_batched_mixed_radix_and_power_of_two():
