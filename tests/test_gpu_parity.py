@@ -143,6 +143,18 @@ def test_displace_batched_plan_matches_single():
         assert normwise(q1, r1) < F64_TOL and normwise(q2, r2) < F64_TOL
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_zero_noise_gives_zero_displacements(prec):
+    # the degenerate input: every mode is zero, so are psi1, psi2 (exactly)
+    print(f"zero noise {prec}", flush=True)
+    plan, cfg = _plan(precision=prec, n=24, box=48.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1",
+                      nk_growth=64)
+    w = torch.zeros((24, 24, 24), dtype=cfg.dtype, device="cuda")
+    p1, p2 = plan.displace(1.0, w)
+    torch.cuda.synchronize()
+    assert not torch.any(p1) and not torch.any(p2)
+
+
 def test_single_plane_wave_gives_no_psi2():
     print("plane wave", flush=True)
     plan, cfg = _plan(n=16, box=32.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=64)
