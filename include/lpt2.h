@@ -207,12 +207,21 @@ lpt2_status lpt2_displace_delta(lpt2_plan_t plan, double a, const void* delta, v
  * cloud-in-cell density (as lpt2_paint_cic) is transformed on the grid and
  * q = V |F[delta]/n^3|^2 is binned in nbins shells as in
  * lpt2_source_spectrum (integer-exact shells of width k_Nyq/nbins, DC and
- * modes at or beyond k_Nyq left out).  deconvolve != 0 divides each mode by
- * W^2, W = prod_i sinc^2(pi m_i / n) the CIC window.  No interlacing.  Host
- * arrays of nbins values; the float atomics of the painting make the last
- * bits vary from run to run.  nbins in 1..512.  Synchronises. */
+ * modes at or beyond k_Nyq left out).  flags (an OR of):
+ *   LPT2_POWER_DECONVOLVE  divide each mode by W^2, W = prod_i sinc^2(pi m_i/n)
+ *                          the CIC window;
+ *   LPT2_POWER_INTERLACE   interlacing: the particles are painted a second
+ *                          time moved by half a cell along every axis, that
+ *                          transform is multiplied by exp(i pi (m_x+m_y+m_z)/n)
+ *                          and averaged with the first, which cancels the
+ *                          alias images with an odd index sum.
+ * Other bits are LPT2_EINVAL.  Host arrays of nbins values; the float atomics
+ * of the painting make the last bits vary from run to run.  nbins in 1..512.
+ * Synchronises. */
+#define LPT2_POWER_DECONVOLVE 1
+#define LPT2_POWER_INTERLACE 2
 lpt2_status lpt2_matter_power(lpt2_plan_t plan, const void* psi1, const void* psi2, int nbins,
-                              int deconvolve, double* k_mean, double* count, double* mean,
+                              int flags, double* k_mean, double* count, double* mean,
                               double* std_dev, void* stream);
 
 /* Eulerian particle positions (eq. position): x = (q + psi1 + psi2) mod L for

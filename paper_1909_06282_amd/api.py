@@ -286,15 +286,18 @@ class Plan:
         return psi1, psi2
 
     def matter_power(self, psi1: torch.Tensor, psi2: torch.Tensor, nbins: int, deconvolve: bool = False,
-                     stream=None):
-        """lpt2_matter_power -> dict of numpy arrays (k_mean, count, mean, std)."""
+                     stream=None, interlace: bool = False):
+        """lpt2_matter_power -> dict of numpy arrays (k_mean, count, mean, std);
+        deconvolve divides out the CIC window, interlace averages with the
+        painting half a cell over."""
         n = self.sizes[0]
         self._check_field(psi1, (3, n, n, n), "psi1")
         self._check_field(psi2, (3, n, n, n), "psi2")
         out = [np.zeros(nbins) for _ in range(4)]
         ptr = [o.ctypes.data_as(C.POINTER(C.c_double)) for o in out]
         _abi.check(self._lib.lpt2_matter_power(self.handle, C.c_void_p(psi1.data_ptr()), C.c_void_p(psi2.data_ptr()),
-                                               int(nbins), int(bool(deconvolve)), *ptr, _stream(stream)), self.handle)
+                                               int(nbins), int(bool(deconvolve)) | (2 if interlace else 0), *ptr,
+                                               _stream(stream)), self.handle)
         return dict(zip(("k_mean", "count", "mean", "std"), out))
 
     def positions(self, psi1: torch.Tensor, psi2: torch.Tensor, r: int = 0, out=None, stream=None):

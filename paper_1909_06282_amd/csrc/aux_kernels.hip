@@ -297,7 +297,7 @@ hipError_t launch_bin(int prec, int n, const void* A, size_t a_cap, const void* 
 // directly, so any displacement is painted.
 constexpr int CIC_T = 8, CIC_H = 4, CIC_R = CIC_T + 2 * CIC_H;
 template <typename T>
-__global__ __launch_bounds__(256) void k_cic(int n, double inv_cell, const T* __restrict__ p1,
+__global__ __launch_bounds__(256) void k_cic(int n, double inv_cell, double shift, const T* __restrict__ p1,
                                              const T* __restrict__ p2, T* __restrict__ rho) {
   constexpr int R3 = CIC_R * CIC_R * CIC_R;
   __shared__ T acc[R3];
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(256) void k_cic(int n, double inv_cell, const T* __
     double f[3];
     bool ok = true;
     for (int c = 0; c < 3; ++c) {
-      const double u = (double)id[c] + ((double)p1[c * n3 + p] + (double)p2[c * n3 + p]) * inv_cell;
+      const double u = (double)id[c] + ((double)p1[c * n3 + p] + (double)p2[c * n3 + p]) * inv_cell + shift;
       ok = ok && fabs(u) < 1e15;  // non-finite or absurd displacement: the particle is not painted
       const double fl = ok ? floor(u) : 0.0;
       f[c] = ok ? u - fl : 0.0;
@@ -399,7 +399,8 @@ hipError_t launch_fill(int prec, void* x, long count, double value, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_cic(int prec, int n, double box, const void* psi1, const void* psi2, void* delta, hipStream_t s) {
+hipError_t launch_cic(int prec, int n, double box, const void* psi1, const void* psi2, void* delta, hipStream_t s,
+                      double shift) {
   const long n3 = (long)n * n * n;
   hipError_t e = launch_fill(prec, delta, n3, -1.0, s);
   if (e != hipSuccess) return e;
@@ -407,11 +408,43 @@ hipError_t launch_cic(int prec, int n, double box, const void* psi1, const void*
   if (n % CIC_T != 0) return hipErrorInvalidValue;
   const unsigned blocks = (unsigned)((long)(n / CIC_T) * (n / CIC_T) * (n / CIC_T));  // one per tile
   if (prec == PREC_F32)
-    hipLaunchKernelGGL(k_cic<float>, dim3(blocks), dim3(256), 0, s, n, ic, (const float*)psi1, (const float*)psi2,
+    hipLaunchKernelGGL(k_cic<float>, dim3(blocks), dim3(256), 0, s, n, ic, shift, (const float*)psi1, (const float*)psi2,
                        (float*)delta);
   else
-    hipLaunchKernelGGL(k_cic<double>, dim3(blocks), dim3(256), 0, s, n, ic, (const double*)psi1, (const double*)psi2,
+    hipLaunchKernelGGL(k_cic<double>, dim3(blocks), dim3(256), 0, s, n, ic, shift, (const double*)psi1, (const double*)psi2,
                        (double*)delta);
+  return hipGetLastError();
+}
+
+// Interlacing: a = (a + b exp(i pi (m_x + m_y + m_z) / n)) / 2 over the half
+// spectrum (x, y, then m_z = 0 .. n/2 - 1), where b is the transform of the
+// density painted with every particle moved by half a cell along each axis:
+// the phase undoes that move and the alias images with an odd index sum
+// cancel in the average.
+template <typename T>
+__global__ void k_interlace(int n, Cx<T>* __restrict__ a, const Cx<T>* __restrict__ b) {
+  const long m = n / 2, count = (long)n * n * m;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x) {
+    const int ix = (int)(i / ((long)n * m)), iy = (int)((i / m) % n), iz = (int)(i % m);
+    const int sm = (ix < n / 2 ? ix : ix - n) + (iy < n / 2 ? iy : iy - n) + iz;  // in (-n, n)
+    double sn, cs;
+    sincos(kPi * (double)sm / (double)n, &sn, &cs);
+    const Cx<T> u = a[i], v = b[i];
+    a[i] = mk(T(0.5 * ((double)u.x + cs * (double)v.x - sn * (double)v.y)),
+              T(0.5 * ((double)u.y + cs * (double)v.y + sn * (double)v.x)));
+  }
+}
+
+hipError_t launch_interlace(int prec, int n, void* a, size_t a_cap, const void* b, size_t b_cap, hipStream_t s) {
+  const long count = (long)n * n * (n / 2);
+  const size_t bytes = (size_t)count * 2 * (prec == PREC_F32 ? 4 : 8);
+  if (n < 2 || !a || !b || bytes > a_cap || bytes > b_cap) return hipErrorInvalidValue;
+  if (prec == PREC_F32)
+    hipLaunchKernelGGL(k_interlace<float>, dim3(grid_for(count)), dim3(256), 0, s, n, (Cx<float>*)a,
+                       (const Cx<float>*)b);
+  else
+    hipLaunchKernelGGL(k_interlace<double>, dim3(grid_for(count)), dim3(256), 0, s, n, (Cx<double>*)a,
+                       (const Cx<double>*)b);
   return hipGetLastError();
 }
 

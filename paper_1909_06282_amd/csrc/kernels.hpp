@@ -160,7 +160,11 @@ constexpr int BIN_MAXBINS = 512;
 hipError_t launch_bin(int prec, int n, const void* A, size_t a_cap, const void* B, size_t b_cap, int quantity,
                       double qscale, int nbins, double kf, double* partial, double* out4, hipStream_t s);
 
-hipError_t launch_cic(int prec, int n, double box, const void* psi1, const void* psi2, void* delta, hipStream_t s);
+// (every particle moved by `shift` cells along each axis before painting)
+hipError_t launch_cic(int prec, int n, double box, const void* psi1, const void* psi2, void* delta, hipStream_t s,
+                      double shift = 0.0);
+// interlacing of two half-spectrum density transforms into a
+hipError_t launch_interlace(int prec, int n, void* a, size_t a_cap, const void* b, size_t b_cap, hipStream_t s);
 // x = (q + psi1 + psi2) mod box per particle and component ([3][n][n][n] each)
 hipError_t launch_positions(int prec, int n, double box, const void* psi1, const void* psi2, void* pos, hipStream_t s);
 hipError_t launch_cic_back(int prec, int n, double box, const void* psi1, const void* psi2, const void* gdelta,

@@ -1546,22 +1546,35 @@ lpt2_status lpt2_displace_delta(lpt2_plan_t p, double a, const void* delta, void
   return displace_batch(c, t, in, o1, o2);
 }
 
-lpt2_status lpt2_matter_power(lpt2_plan_t p, const void* psi1, const void* psi2, int nbins, int deconvolve,
+lpt2_status lpt2_matter_power(lpt2_plan_t p, const void* psi1, const void* psi2, int nbins, int flags,
                               double* k_mean, double* count, double* mean, double* std_dev, void* stream) {
   if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
   Busy b(p);
   if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
   if (!psi1 || !psi2 || !k_mean || !count || !mean || !std_dev) return fail(p, LPT2_EINVAL, "null pointer");
   if (nbins < 1 || nbins > BIN_MAXBINS) return fail(p, LPT2_EINVAL, "nbins must be in 1..512");
+  if (flags & ~(LPT2_POWER_DECONVOLVE | LPT2_POWER_INTERLACE)) return fail(p, LPT2_EINVAL, "unknown flags");
+  const bool deconvolve = (flags & LPT2_POWER_DECONVOLVE) != 0, interlace = (flags & LPT2_POWER_INTERLACE) != 0;
   hipStream_t s = (hipStream_t)stream;
   Grid& g = p->grids[p->rgrid[0]];
   Ctx c{p, g, s, 2 * p->es, p->ws, 1};
-  // CIC density into slot 0 (as a real field), its 3D forward transform in place, the shells
-  RUN("cic_paint", 7.0 * (double)c.field(), launch_cic(p->prec, g.n, g.cfg.box, psi1, psi2, c.slot(0), s));
-  CHK(fwd_zy(c, "z_r2c_density", "y_fwd_density", c.one(c.slot(0), 1), c.cap(c.slot(0)), c.slot(0)));
-  RUN("x_fwd_density", 2.0 * (double)c.field(),
-      launch_colfft(p->prec, g.n, -1, c.slot(0), c.cap(c.slot(0)), 1, 0, (int)(g.n * g.m), g.n * g.m, g.tw, s,
-                    g.tiles[0]));
+  // CIC density into slot k (as a real field, particles moved by `shift`
+  // cells), its 3D forward transform in place
+  auto density_k = [&](int k, double shift) -> lpt2_status {
+    RUN("cic_paint", 7.0 * (double)c.field(),
+        launch_cic(p->prec, g.n, g.cfg.box, psi1, psi2, c.slot(k), s, shift));
+    CHK(fwd_zy(c, "z_r2c_density", "y_fwd_density", c.one(c.slot(k), 1), c.cap(c.slot(k)), c.slot(k)));
+    RUN("x_fwd_density", 2.0 * (double)c.field(),
+        launch_colfft(p->prec, g.n, -1, c.slot(k), c.cap(c.slot(k)), 1, 0, (int)(g.n * g.m), g.n * g.m, g.tw, s,
+                      g.tiles[0]));
+    return LPT2_OK;
+  };
+  CHK(density_k(0, 0.0));
+  if (interlace) {  // the second painting half a cell over, combined into slot 0
+    CHK(density_k(1, 0.5));
+    RUN("interlace", 3.0 * (double)c.field(),
+        launch_interlace(p->prec, g.n, c.slot(0), c.cap(c.slot(0)), c.slot(1), c.cap(c.slot(1)), s));
+  }
   const double n3 = (double)g.n3, kf = 2.0 * kPi / g.cfg.box;
   const double qs = g.cfg.box * g.cfg.box * g.cfg.box / (n3 * n3);
   RUN("shell_bin", 0.0,

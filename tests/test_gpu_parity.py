@@ -222,18 +222,21 @@ def test_positions_match_oracle(prec):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
-@pytest.mark.parametrize("deconvolve", [False, True])
-def test_matter_power_matches_oracle(prec, tol, deconvolve):
-    # the same displacements on both sides: CIC paint, FFT, shells
-    print(f"matter power {prec} deconvolve={deconvolve}", flush=True)
+@pytest.mark.parametrize("deconvolve,interlace", [(False, False), (True, False), (False, True), (True, True)])
+def test_matter_power_matches_oracle(prec, tol, deconvolve, interlace):
+    # the same displacements on both sides: CIC paint(s), FFT, shells
+    print(f"matter power {prec} deconvolve={deconvolve} interlace={interlace}", flush=True)
     n, nb = 32, 16
     plan, cfg = _plan(precision=prec, n=n, box=64.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1",
                       nk_growth=64)
     p1, p2 = plan.displace(1.0, to_dev(white_noise(n, 4), cfg.dtype))
-    got = plan.matter_power(p1, p2, nb, deconvolve)
+    got = plan.matter_power(p1, p2, nb, deconvolve, interlace=interlace)
     m = oracle_model(cfg)
-    d = cic.paint(p1.double().cpu() + p2.double().cpu(), m)
-    km, cnt, mean, std = spectrum.matter_power(d, m, nb, deconvolve)
+    disp = p1.double().cpu() + p2.double().cpu()
+    if interlace:
+        km, cnt, mean, std = spectrum.matter_power_interlaced(disp, m, nb, deconvolve)
+    else:
+        km, cnt, mean, std = spectrum.matter_power(cic.paint(disp, m), m, nb, deconvolve)
     assert np.array_equal(got["count"], cnt)
     nz = cnt > 0
     err = np.max(np.abs(got["mean"][nz] / mean[nz] - 1))
@@ -430,3 +433,12 @@ def test_invalid_arguments_raise():
         plan.displace(1.0, w.float())
     with pytest.raises(ValueError):
         plan.displace(1.0, to_dev(white_noise(16, 1), torch.float64))
+    # matter power: a flag bit that is not defined
+    import ctypes
+    from paper_1909_06282_amd import _abi
+    p1, p2 = plan.displace(1.0, w)
+    out = [np.zeros(4) for _ in range(4)]
+    ptr = [o.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for o in out]
+    st = plan._lib.lpt2_matter_power(plan.handle, ctypes.c_void_p(p1.data_ptr()), ctypes.c_void_p(p2.data_ptr()), 4,
+                                     4, *ptr, None)
+    assert st == _abi.EINVAL
