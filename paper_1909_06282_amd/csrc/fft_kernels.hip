@@ -654,6 +654,99 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
   }
 }
 
+// Adjoint x passes, the transposes of k_xdisp: NIN input columns (z and y
+// already forward-transformed), each forward x-transformed and multiplied by
+// its factor, summed, and the sum inverse x-transformed into one output.
+//   MODE 0: tab = the (PHI, PSI1) pair; in 0..2: Ubar_p, factor -m_x^p PHI;
+//           in 3..4: Vbar_p, factor -i m_x^p PSI1
+//   MODE 1: tab = PSI2; in 0..1: Qbar_p, factor i m_x^p PSI2
+// DC and Nyquist planes get no contribution.  Persistent over column tiles;
+// the next input's column (or the next tile's first) loads while the
+// current one transforms.
+template <typename T, int N, int WW, int MODE>
+__global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xadj(const Cx<T>* __restrict__ in, long fsi,
+                                                                Cx<T>* __restrict__ out,
+                                                                const T* __restrict__ tab,
+                                                                const Cx<T>* __restrict__ tw) {
+  using C = ColCfg<T, N, WW>;
+  constexpr int M = N / 2;
+  constexpr long NCOL = (long)N * M;
+  constexpr int NIN = MODE == 0 ? 5 : 2;
+  constexpr bool PAIR = MODE == 0;
+  static_assert(!C::ONE, "x-pass widths keep two exchange buffers");
+  __shared__ Cx<T> lds[2 * C::L * C::W];  // two exchange buffers
+  __shared__ Cx<T> stw[N];
+  stage_twiddles<T, N>(stw, tw);
+  int phase = 0;
+  const int c = threadIdx.x % C::W, t = threadIdx.x / C::W;
+  constexpr long NTILES = (NCOL + C::W - 1) / C::W;
+  Cx<T> v[C::E], acc[C::E], pf[C::E];
+  Cx<T> rf[PAIR ? C::E : 1];
+  T rq[PAIR ? 1 : C::E];
+  auto load = [&](long tile, int k) {
+    const long col = tile * C::W + c;
+    const bool a = col < NCOL;
+    const long cs = a ? col : 0;
+#pragma unroll
+    for (int sl = 0; sl < C::E; ++sl)
+      pf[sl] = a ? ld_nt(&in[k * fsi + cs + slot_elem<C::L, C::E, C::R0F>(t, sl) * NCOL]) : zero<T>();
+  };
+  long tile = block_index<C>();
+  if (tile < NTILES) load(tile, 0);
+#pragma unroll 1
+  for (; tile < NTILES; tile += gridDim.x) {
+    const long col = tile * C::W + c;
+    const bool act = col < NCOL;
+    const long cs = act ? col : 0;
+    const int iy = (int)(cs / M), iz = (int)(cs % M);
+    const int my = iy < N / 2 ? iy : iy - N;
+    const bool keep_y = iy != N / 2;
+    const int n2yz = my * my + iz * iz;
+#pragma unroll
+    for (int sl = 0; sl < C::E; ++sl) {
+      const int ix = slot_elem<C::L, C::E, C::RLF>(t, sl);
+      const int mx = ix < N / 2 ? ix : ix - N;
+      const int n2 = mx * mx + n2yz;
+      const bool keep = keep_y && ix != N / 2 && n2 != 0;
+      if constexpr (PAIR)
+        rf[sl] = keep ? reinterpret_cast<const Cx<T>*>(tab)[n2] : zero<T>();
+      else
+        rq[sl] = keep ? tab[n2] : T(0);
+    }
+#pragma unroll 1
+    for (int k = 0; k < NIN; ++k) {
+#pragma unroll
+      for (int sl = 0; sl < C::E; ++sl) v[sl] = pf[sl];
+      if (k + 1 < NIN)
+        load(tile, k + 1);
+      else if (tile + gridDim.x < NTILES)
+        load(tile + gridDim.x, 0);
+      fft<T, C::L, -1, C::W, SY_PING>(v, t, stw, 1, lds + c, C::L * C::W, &phase);
+      const bool second = PAIR && k >= 3;
+      const int pw = second ? k - 3 : k;
+#pragma unroll
+      for (int sl = 0; sl < C::E; ++sl) {
+        const int ix = slot_elem<C::L, C::E, C::RLF>(t, sl);
+        T r;
+        if constexpr (PAIR)
+          r = second ? rf[sl].y : rf[sl].x;
+        else
+          r = rq[sl];
+        const T f = mpow<T>(ix < N / 2 ? ix : ix - N, pw) * r;
+        // MODE 0: -f v (U) or -i f v (V); MODE 1: i f v
+        const Cx<T> u = PAIR ? (second ? mk(v[sl].y * f, -v[sl].x * f) : mk(-v[sl].x * f, -v[sl].y * f))
+                             : mk(-v[sl].y * f, v[sl].x * f);
+        acc[sl] = k == 0 ? u : acc[sl] + u;
+      }
+    }
+    fft<T, C::L, +1, C::W, SY_PING>(acc, t, stw, 1, lds + c, C::L * C::W, &phase);
+    if (act) {
+#pragma unroll
+      for (int sl = 0; sl < C::E; ++sl) st_nt(&out[cs + slot_elem<C::L, C::E, C::RLI>(t, sl) * NCOL], acc[sl]);
+    }
+  }
+}
+
 // Fused x pass: forward x-FFT of each input column, multiply by the codes of
 // `op` (FP64, rounded once), then (op.inverse) inverse x-FFT, store.
 template <typename T>
@@ -1103,6 +1196,45 @@ hipError_t launch_xdisp(int prec, int n, int nr, int mode, const void* in, size_
   const size_t n2cnt = 3 * (size_t)(n / 2) * (n / 2) + 1;
   if (n2cnt * esize(prec) * (mode == 1 ? 1 : 2) > tab_cap) return hipErrorInvalidValue;
 #define CALL(NN) return prec == PREC_F32 ? xdisp_t<float, NN>(w, nr, mode, in, out, out_fstride, tab, tw, s) : xdisp_t<double, NN>(w, nr, mode, in, out, out_fstride, tab, tw, s)
+  LPT2_SWITCH_N(n, CALL)
+#undef CALL
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int N, int WW, int MODE>
+static hipError_t xadj_m(const void* in, long fsi, void* out, const void* tab, const void* tw, hipStream_t s) {
+  using C = ColCfg<T, N, WW>;
+  const long ntiles = ((long)N * (N / 2) + C::W - 1) / C::W;
+  static const long res = resident_blocks(reinterpret_cast<const void*>(&k_xadj<T, N, WW, MODE>), C::BLOCK);
+  hipLaunchKernelGGL((k_xadj<T, N, WW, MODE>), dim3((unsigned)min_l(res, ntiles)), dim3(C::BLOCK), 0, s,
+                     (const Cx<T>*)in, fsi, (Cx<T>*)out, (const T*)tab, (const Cx<T>*)tw);
+  return hipGetLastError();
+}
+template <typename T, int N, int WW>
+static hipError_t xadj_w(int mode, const void* in, long fsi, void* out, const void* tab, const void* tw,
+                         hipStream_t s) {
+  return mode == 0 ? xadj_m<T, N, WW, 0>(in, fsi, out, tab, tw, s) : xadj_m<T, N, WW, 1>(in, fsi, out, tab, tw, s);
+}
+template <typename T, int N>
+static hipError_t xadj_t(int w, int mode, const void* in, long fsi, void* out, const void* tab, const void* tw,
+                         hipStream_t s) {
+  constexpr int K = KIND_X;
+  if (w == col_w<T>(N, 0, K)) return xadj_w<T, N, col_w<T>(N, 0, K)>(mode, in, fsi, out, tab, tw, s);
+  if (w == col_w<T>(N, 1, K)) return xadj_w<T, N, col_w<T>(N, 1, K)>(mode, in, fsi, out, tab, tw, s);
+  if (w == col_w<T>(N, 2, K)) return xadj_w<T, N, col_w<T>(N, 2, K)>(mode, in, fsi, out, tab, tw, s);
+  return hipErrorInvalidValue;
+}
+hipError_t launch_xadj(int prec, int n, int mode, const void* in, size_t in_cap, long in_fstride, void* out,
+                       size_t out_cap, const void* tab, size_t tab_cap, const void* tw, hipStream_t s, int w) {
+  if (w == 0) w = default_width(prec, n, KIND_X);
+  if (!pow2n(n) || !in || !out || !tab || !tw || in_fstride < 0 || mode < 0 || mode > 1) return hipErrorInvalidValue;
+  const int nin = mode == 0 ? 5 : 2;
+  const size_t cb = 2 * esize(prec), field = (size_t)n * n * (n / 2);
+  if (((size_t)(nin - 1) * in_fstride + field) * cb > in_cap || field * cb > out_cap) return hipErrorInvalidValue;
+  // table entries up to |m|^2 = 3 (n/2)^2: pairs for mode 0, single values for mode 1
+  const size_t n2cnt = 3 * (size_t)(n / 2) * (n / 2) + 1;
+  if (n2cnt * esize(prec) * (mode == 0 ? 2 : 1) > tab_cap) return hipErrorInvalidValue;
+#define CALL(NN) return prec == PREC_F32 ? xadj_t<float, NN>(w, mode, in, in_fstride, out, tab, tw, s) : xadj_t<double, NN>(w, mode, in, in_fstride, out, tab, tw, s)
   LPT2_SWITCH_N(n, CALL)
 #undef CALL
   return hipErrorInvalidValue;

@@ -83,6 +83,11 @@ int default_width(int prec, int n, int kind);
 // (nr realisations stored one after the other inside every field slot)
 hipError_t launch_ycombo(int prec, int n, int nr, const void* in, size_t in_cap, long in_fstride, void* out,
                          size_t out_cap, long out_fstride, const YOp& op, const void* tw, hipStream_t s, int w = 0);
+// adjoint x pass: mode 0 (tab = the PHI, PSI1 pair; inputs Ubar0..2, Vbar0..1)
+// or mode 1 (tab = PSI2; inputs Qbar0..1), nin input fields in_fstride
+// complex apart -> one output field (the transpose of the displacement x pass)
+hipError_t launch_xadj(int prec, int n, int mode, const void* in, size_t in_cap, long in_fstride, void* out,
+                       size_t out_cap, const void* tab, size_t tab_cap, const void* tw, hipStream_t s, int w = 0);
 // fan-in y pass of the adjoint: output o sums terms first[o] .. first[o+1]-1;
 // term k is the forward y-FFT of input field src[k] times m_y^py[k] m_z^pz[k]
 // (powers 0..2; first[0] = 0, first[nout] = nterm, every output has a term)

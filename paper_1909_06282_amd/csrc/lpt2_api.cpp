@@ -677,6 +677,20 @@ lpt2_status mg_source_k(Ctx& c, const Tables* t, const void* noise) {
   return LPT2_OK;
 }
 
+// adjoint x pass (mode 0: five inputs, the noise gradient; mode 1: two, S_bar), one realisation
+lpt2_status xadj(Ctx& c, const char* name, int mode, const void* in, void* out, const Tables* t) {
+  lpt2_plan_t p = c.p;
+  hipStream_t s = c.s;
+  Grid& g = c.g;
+  if (c.nr != 1) return fail(p, LPT2_EINVAL, "adjoint x pass takes one realisation");
+  const bool f32 = p->prec == PREC_F32;
+  const int row = mode == 0 ? (f32 ? TAB_PAIR32 : TAB_PAIR64) : (f32 ? TAB_PSI2_32 : TAB_PSI2);
+  const void* tab = t->radial + (size_t)row * g.n2cnt;
+  const size_t cap = sizeof(double) * (size_t)(TAB_ROWS - row) * g.n2cnt;
+  RUN(name, c.fields(mode == 0 ? 6 : 3),
+      launch_xadj(p->prec, g.n, mode, in, c.cap(in), c.sstride(), out, c.cap(out), tab, cap, g.tw, s, g.tiles[2]));
+  return LPT2_OK;
+}
 // fan-in y pass over the c.nr realisations of each of op.nin slots at `in`
 lpt2_status yfan(Ctx& c, const char* name, const void* in, void* out, const YFan& op) {
   lpt2_plan_t p = c.p;
@@ -731,11 +745,7 @@ lpt2_status backward_one(Ctx& c, const Tables* t, const void* noise, const void*
   const int nq[2] = {2, 1};
   const int tq[3][3] = {{1, 1, 0}, {2, 0, 1}, {0, 0, 0}};  // Q0: y, z; Q1: x
   CHK(yfan(c, "y_fan_gpsi2", c.slot(1), c.slot(4), yfan_op(3, 2, nq, tq)));
-  XOp o1 = op_blank(2, 1, 1);
-  op_tables(o1, g, t);
-  op_set(o1, 0, MUL_PI, -1, -1, TAB_PSI2, 1.0);
-  op_set(o1, 1, MUL_PI, 0, -1, TAB_PSI2, 1.0);
-  CHK(xp(c, "x_adj_psi2", c.slot(4), c.slot(10), o1));
+  CHK(xadj(c, "x_adj_psi2", 1, c.slot(4), c.slot(10), t));
   CHK(inv_y(c, "y_inv_sbar", c.slot(10), 1));
   CHK(z_c2r_ws(c, "z_c2r_sbar", c.slot(10), 1));
   // phi recomputed from the noise: U_p (slots 1..3), then phi stored as
@@ -766,14 +776,7 @@ lpt2_status backward_one(Ctx& c, const Tables* t, const void* noise, const void*
                         {1, 1, 0}, {2, 0, 1},             // Vbar0: psi1 y, z
                         {0, 0, 0}};                       // Vbar1: psi1 x
   CHK(yfan(c, "y_fan_adj", c.slot(1), c.slot(10), yfan_op(9, 5, nu, tu)));
-  XOp o3 = op_blank(5, 1, 1);
-  op_tables(o3, g, t);
-  op_set(o3, 0, MUL_REAL, -1, -1, TAB_PHI, -1.0);
-  op_set(o3, 1, MUL_REAL, 0, -1, TAB_PHI, -1.0);
-  op_set(o3, 2, MUL_REAL, 0, 0, TAB_PHI, -1.0);
-  op_set(o3, 3, MUL_MI, -1, -1, TAB_PSI1, 1.0);
-  op_set(o3, 4, MUL_MI, 0, -1, TAB_PSI1, 1.0);
-  CHK(xp(c, "x_adj_noise", c.slot(10), c.slot(0), o3));
+  CHK(xadj(c, "x_adj_noise", 0, c.slot(10), c.slot(0), t));
   CHK(inv_y(c, "y_inv_gnoise", c.slot(0), 1));
   CHK(z_c2r(c, "z_c2r_gnoise", c.slot(0), c.one(gw, 1), c.field()));
   return LPT2_OK;
