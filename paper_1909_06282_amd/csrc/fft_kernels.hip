@@ -432,7 +432,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
     const long off = tile_off(tile, a);
     const Cx<T>* b = in + src * fsi + off;
 #pragma unroll
-    for (int sl = 0; sl < C::E; ++sl) pf[sl] = a ? b[slot_elem<C::L, C::E, C::R0I>(t, sl) * M] : zero<T>();
+    for (int sl = 0; sl < C::E; ++sl) pf[sl] = b[slot_elem<C::L, C::E, C::R0I>(t, sl) * M];  // column 0 if missing
   };
   long tile = block_index<C>();
   if (tile < NTILES) load(tile, op.src[0]);
@@ -447,10 +447,11 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
         for (int sl = 0; sl < C::E; ++sl) v[sl] = pf[sl];
         int on = o + 1;
         while (on < op.nout && op.src[on] == op.src[o]) ++on;
-        if (on < op.nout)
-          load(tile, op.src[on]);
-        else if (tile + gridDim.x < NTILES)
-          load(tile + gridDim.x, op.src[0]);
+        // always one load (after the last tile: the current column again), so
+        // the compiler keeps it in flight instead of waiting at a merge
+        const bool same = on < op.nout;
+        const long nt = same || tile + gridDim.x >= NTILES ? tile : tile + gridDim.x;
+        load(nt, op.src[same ? on : 0]);
       }
       const int pw = op.pw[o];
 #pragma unroll
