@@ -252,6 +252,126 @@ __global__ __launch_bounds__(256) void k_zsource(const Cx<T>* __restrict__ phi, 
   r2c_finish<T, N>(s, t, lb, stw, sk + lsafe * C::L, act);
 }
 
+// Products of the full modified-gravity source, per z line.  The input
+// fields (inverse-transformed along x and y, every k factor applied) are
+// transformed along z here and combined in registers into real accumulator
+// lines (field k of `acc` at acc + k * afs reals):
+//   KIND 0 (the diagonal pairs, weight 1) and KIND 1 (the off-diagonal
+//   pairs, weight 2): per pair, NT fields a (R1), b (R2) [, c (R4)]:
+//     acc0 += w a b, acc1 += w a^2 [, acc2 += 2 w a c]; KIND 0 also sums
+//     the trace of a and adds its square to acc1, and writes the
+//     accumulators (the first pass), KIND 1 adds to them;
+//   KIND 2 (f(R) only): fields p_x, q_x, p_y, q_y, p_z, q_z, chi:
+//     acc2 += sum_j p_j q_j, acc3 = chi^2.
+// FP32 loads the next field's line while the current one transforms.
+template <typename T, int N, int KIND, int NT>
+__global__ __launch_bounds__(256) void k_zmg(const Cx<T>* __restrict__ in, long fstride, T* __restrict__ acc,
+                                             long afs, long nlines, const Cx<T>* __restrict__ tw) {
+  using C = LineCfg<N>;
+  constexpr int NF = KIND == 2 ? 7 : 3 * NT;
+  constexpr T W = KIND == 1 ? T(2) : T(1);
+  __shared__ Cx<T> lds[C::G * C::SPAN];
+  __shared__ Cx<T> stw[N];
+  stage_twiddles<T, N>(stw, tw);
+  const int t = threadIdx.x % C::TPL, g = threadIdx.x / C::TPL;
+  const long line = (long)blockIdx.x * C::G + g;
+  const bool act = line < nlines;
+  const long lsafe = act ? line : 0;
+  Cx<T>* lb = lds + g * C::SPAN;
+  constexpr bool PF = sizeof(T) == 4;
+  Cx<T> raw[C::E], v[C::E], a[C::E], r0[C::E], r1[C::E], r2[C::E], tr[C::E];
+  const Cx<T>* src = in + lsafe * C::L;  // line 0 stands in for an inactive line
+  auto load_field = [&](int f) {
+#pragma unroll
+    for (int q = 0; q < C::E; ++q) raw[q] = src[f * fstride + t + q * C::TPL];
+  };
+  // accumulator k's real line as pairs, in the inverse transform's output slots
+  auto acc_line = [&](int k) { return reinterpret_cast<Cx<T>*>(acc + k * afs + lsafe * N); };
+#pragma unroll
+  for (int i = 0; i < C::E; ++i) r0[i] = r1[i] = r2[i] = tr[i] = zero<T>();
+  load_field(0);
+#pragma unroll 1
+  for (int f = 0; f < NF; ++f) {
+    c2r_prepare_regs<T, N>(raw, 0, v, t, lb, stw);
+    if (PF && f < NF - 1) load_field(f + 1);
+    fft<T, C::L, +1, 1, SY_WAVE, true>(v, t, stw, 2, lb);
+    if constexpr (KIND == 2) {
+      if (f == 6) {
+#pragma unroll
+        for (int i = 0; i < C::E; ++i) tr[i] = mk(v[i].x * v[i].x, v[i].y * v[i].y);  // chi^2
+      } else if (f % 2 == 0) {
+#pragma unroll
+        for (int i = 0; i < C::E; ++i) a[i] = v[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < C::E; ++i) r2[i] = mk(r2[i].x + a[i].x * v[i].x, r2[i].y + a[i].y * v[i].y);
+      }
+    } else {
+      const int tb = f % NT;
+      if (tb == 0) {
+#pragma unroll
+        for (int i = 0; i < C::E; ++i) {
+          a[i] = v[i];
+          if (KIND == 0) tr[i] = tr[i] + v[i];
+        }
+      } else if (tb == 1) {
+#pragma unroll
+        for (int i = 0; i < C::E; ++i) {
+          r0[i] = mk(r0[i].x + W * a[i].x * v[i].x, r0[i].y + W * a[i].y * v[i].y);
+          r1[i] = mk(r1[i].x + W * a[i].x * a[i].x, r1[i].y + W * a[i].y * a[i].y);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < C::E; ++i)
+          r2[i] = mk(r2[i].x + T(2) * W * a[i].x * v[i].x, r2[i].y + T(2) * W * a[i].y * v[i].y);
+      }
+    }
+    if (!PF && f < NF - 1) load_field(f + 1);
+  }
+  if (!act) return;
+  if constexpr (KIND == 0) {
+    Cx<T>* d0 = acc_line(0);
+    Cx<T>* d1 = acc_line(1);
+#pragma unroll
+    for (int sl = 0; sl < C::E; ++sl) {
+      const int e = slot_elem<C::L, C::E, C::RLI>(t, sl);
+      d0[e] = r0[sl];
+      d1[e] = mk(r1[sl].x + tr[sl].x * tr[sl].x, r1[sl].y + tr[sl].y * tr[sl].y);
+    }
+    if (NT == 3) {
+      Cx<T>* d2 = acc_line(2);
+#pragma unroll
+      for (int sl = 0; sl < C::E; ++sl) d2[slot_elem<C::L, C::E, C::RLI>(t, sl)] = r2[sl];
+    }
+  } else if constexpr (KIND == 1) {
+    Cx<T>* d0 = acc_line(0);
+    Cx<T>* d1 = acc_line(1);
+#pragma unroll
+    for (int sl = 0; sl < C::E; ++sl) {
+      const int e = slot_elem<C::L, C::E, C::RLI>(t, sl);
+      d0[e] = d0[e] + r0[sl];
+      d1[e] = d1[e] + r1[sl];
+    }
+    if (NT == 3) {
+      Cx<T>* d2 = acc_line(2);
+#pragma unroll
+      for (int sl = 0; sl < C::E; ++sl) {
+        const int e = slot_elem<C::L, C::E, C::RLI>(t, sl);
+        d2[e] = d2[e] + r2[sl];
+      }
+    }
+  } else {
+    Cx<T>* d2 = acc_line(2);
+    Cx<T>* d3 = acc_line(3);
+#pragma unroll
+    for (int sl = 0; sl < C::E; ++sl) {
+      const int e = slot_elem<C::L, C::E, C::RLI>(t, sl);
+      d2[e] = d2[e] + r2[sl];
+      d3[e] = tr[sl];
+    }
+  }
+}
+
 // Adjoint of the source: with S_bar given per real value,
 //   phi_bar_ii = S_bar (tr phi - phi_ii), phi_bar_ij = -2 S_bar phi_ij (i < j),
 // each forward-transformed along z.  Logical field f of the six (xx, yy, zz,
@@ -997,6 +1117,38 @@ hipError_t launch_zsource(int prec, int n, const void* phi, size_t phi_cap, long
   if ((5 * (size_t)fstride + (size_t)nlines * lc) * cb > phi_cap || (size_t)nlines * lc * cb > sk_cap)
     return hipErrorInvalidValue;
 #define CALL(NN) return prec == PREC_F32 ? zsource_t<float, NN>(phi, fstride, zp, sk, nlines, tw, s) : zsource_t<double, NN>(phi, fstride, zp, sk, nlines, tw, s)
+  LPT2_SWITCH_N(n, CALL)
+#undef CALL
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int N, int KIND, int NT>
+static hipError_t zmg_t(const void* in, long fstride, void* acc, long afs, long nlines, const void* tw, hipStream_t s) {
+  using C = LineCfg<N>;
+  const long blocks = (nlines + C::G - 1) / C::G;
+  hipLaunchKernelGGL((k_zmg<T, N, KIND, NT>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in, fstride,
+                     (T*)acc, afs, nlines, (const Cx<T>*)tw);
+  return hipGetLastError();
+}
+template <typename T, int N>
+static hipError_t zmg_k(int kind, int nt, const void* in, long fstride, void* acc, long afs, long nlines,
+                        const void* tw, hipStream_t s) {
+  if (kind == 0) return nt == 3 ? zmg_t<T, N, 0, 3>(in, fstride, acc, afs, nlines, tw, s) : zmg_t<T, N, 0, 2>(in, fstride, acc, afs, nlines, tw, s);
+  if (kind == 1) return nt == 3 ? zmg_t<T, N, 1, 3>(in, fstride, acc, afs, nlines, tw, s) : zmg_t<T, N, 1, 2>(in, fstride, acc, afs, nlines, tw, s);
+  return zmg_t<T, N, 2, 3>(in, fstride, acc, afs, nlines, tw, s);
+}
+hipError_t launch_zmg(int prec, int n, int kind, int nt, const void* in, size_t in_cap, long fstride, void* acc,
+                      size_t acc_cap, long acc_fstride, long nlines, const void* tw, hipStream_t s) {
+  if (nlines <= 0) return hipSuccess;
+  if (!pow2n(n) || !in || !acc || !tw || fstride < 0 || acc_fstride < 0 || kind < 0 || kind > 2 ||
+      (nt != 2 && nt != 3) || (kind == 2 && nt != 3))
+    return hipErrorInvalidValue;
+  const int nf = kind == 2 ? 7 : 3 * nt, nacc = kind == 2 ? 4 : nt;
+  const size_t es = esize(prec), lc = (size_t)n / 2;
+  if (((size_t)(nf - 1) * fstride + (size_t)nlines * lc) * 2 * es > in_cap ||
+      ((size_t)(nacc - 1) * acc_fstride + (size_t)nlines * n) * es > acc_cap)
+    return hipErrorInvalidValue;
+#define CALL(NN) return prec == PREC_F32 ? zmg_k<float, NN>(kind, nt, in, fstride, acc, acc_fstride, nlines, tw, s) : zmg_k<double, NN>(kind, nt, in, fstride, acc, acc_fstride, nlines, tw, s)
   LPT2_SWITCH_N(n, CALL)
 #undef CALL
   return hipErrorInvalidValue;

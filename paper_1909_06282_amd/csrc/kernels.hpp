@@ -115,6 +115,12 @@ hipError_t launch_xpass(int prec, int n, const void* in, size_t in_cap, long in_
 // (field f of the six multiplied by m_z^zp.r[f] first)
 hipError_t launch_zsource(int prec, int n, const void* phi, size_t phi_cap, long fstride, const ZPow& zp, void* sk,
                           size_t sk_cap, long nlines, const void* tw, hipStream_t s);
+// z pass of the full MG source: kind 0 / 1 (diagonal / off-diagonal pairs,
+// nt = 2 or 3 fields per pair), kind 2 (gradients and chi, f(R)); `in` holds
+// the fields (half-spectrum lines, every k factor applied), `acc` the real
+// accumulator fields acc_fstride reals apart (see k_zmg)
+hipError_t launch_zmg(int prec, int n, int kind, int nt, const void* in, size_t in_cap, long fstride, void* acc,
+                      size_t acc_cap, long acc_fstride, long nlines, const void* tw, hipStream_t s);
 // z pass of the adjoint: 6 phi lines + real S_bar line -> 6 phi_bar half-spectrum lines
 // (logical field f = xx,yy,zz,xy,xz,yz read and written at field zp.fmap[f],
 // multiplied by m_z^zp.r[f] before its inverse transform)

@@ -615,65 +615,63 @@ lpt2_status source_k(Ctx& c, const Tables* t, const void* noise, int dst, double
   return LPT2_OK;
 }
 
-// S_MG(k) = S1+S2+S3+S4 into slot 10 (uses slots 0..10)
+// S_MG(k) = S1+S2+S3+S4 into slot 10 (uses slots 0..10 and 12..15; slot 11
+// is left alone).  The pairs (i,j) go in two groups, the diagonal ones and
+// the others: one x pass gives each pair's fields R1, R2 (and R4) with the
+// full k factors, one y pass inverts them, and one z pass (k_zmg) inverts
+// them along z and accumulates the products in registers into real fields in
+// slots 12..15: R1 (G S1 part), R2 + (tr phi)^2 (the C2 parts), R5 and chi^2.
 lpt2_status mg_source_k(Ctx& c, const Tables* t, const void* noise) {
   lpt2_plan_t p = c.p;
   hipStream_t s = c.s;
   Grid& g = c.g;
-  const long cnt = g.n3;
   const bool fr = g.c.gravity == GRAV_FR;
-  if (c.cap(c.slot(10)) < 2 * c.field()) return fail(p, LPT2_EINVAL, "workspace too small");
+  const int nt = fr ? 3 : 2;  // fields per pair
+  if (c.cap(c.slot(12)) < 4 * c.field()) return fail(p, LPT2_EINVAL, "workspace too small");
   CHK(fwd_zy(c, "z_r2c_noise", "y_fwd_noise", c.one(noise, 1), c.field(), c.slot(0)));
-  // accumulators (real fields stored in spectral slots): R1 5, R2 6, tr->R3 7, R5 8, chi^2 9
-  for (int i = 5; i <= 9; ++i) RUN("fill", 0.0, launch_fill(p->prec, c.slot(i), cnt, 0.0, s));
-  for (int q = 0; q < 6; ++q) {
-    const int i = PI_[q], j = PJ_[q];
-    XOp op = op_blank(1, fr ? 3 : 2, 1);
+  const long nlines = (long)g.n * g.n;
+  const long afs = 2 * c.sstride();  // reals from one accumulator field to the next
+  for (int grp = 0; grp < 2; ++grp) {
+    XOp op = op_blank(1, 3 * nt, 1);
     op_tables(op, g, t);
-    op_set(op, 0, MUL_REAL, i, j, TAB_R1, -1.0);
-    op_set(op, 1, MUL_REAL, i, j, TAB_R2, -1.0);
-    if (fr) op_set(op, 2, MUL_REAL, i, j, TAB_R4, -1.0);
+    for (int k = 0; k < 3; ++k) {
+      const int q = 3 * grp + k, i = PI_[q], j = PJ_[q];
+      op_set(op, nt * k, MUL_REAL, i, j, TAB_R1, -1.0);
+      op_set(op, nt * k + 1, MUL_REAL, i, j, TAB_R2, -1.0);
+      if (fr) op_set(op, nt * k + 2, MUL_REAL, i, j, TAB_R4, -1.0);
+    }
     CHK(xp(c, "x_mg_phi", c.slot(0), c.slot(1), op));
     CHK(inv_y(c, "y_inv_mg", c.slot(1), op.nout));
-    CHK(z_c2r_ws(c, "z_c2r_mg", c.slot(1), op.nout));  // in place
-    const double w = (i == j) ? 1.0 : 2.0;
-    RUN("mg_pair", 0.0,
-        launch_mg_pair(p->prec, cnt, w, c.slot(1), c.slot(2), fr ? c.slot(3) : nullptr, c.slot(5), c.slot(6),
-                       fr ? c.slot(8) : nullptr, i == j ? c.slot(7) : nullptr, s));
+    RUN("z_mg_pairs", c.fields(op.nout + (grp == 0 ? nt : 2.0 * nt)),
+        launch_zmg(p->prec, g.n, grp, nt, c.slot(1), c.cap(c.slot(1)), c.sstride(), c.slot(12), c.cap(c.slot(12)),
+                   afs, nlines, g.tw, s));
   }
-  RUN("square", 0.0, launch_square(p->prec, cnt, c.slot(7), s));
   if (fr) {
-    for (int j = 0; j < 3; ++j) {
-      XOp op = op_blank(1, 2, 1);
-      op_tables(op, g, t);
-      op_set(op, 0, MUL_MI, j, -1, TAB_R5, 1.0);
-      op_set(op, 1, MUL_PI, j, -1, TAB_R6, 1.0);
-      CHK(xp(c, "x_mg_grad", c.slot(0), c.slot(1), op));
-      CHK(inv_y(c, "y_inv_mg", c.slot(1), 2));
-      CHK(z_c2r_ws(c, "z_c2r_mg", c.slot(1), 2));
-      RUN("mg_dot", 0.0, launch_mg_dot(p->prec, cnt, c.slot(1), c.slot(2), c.slot(8), s));
-    }
-    XOp op = op_blank(1, 1, 1);
+    XOp op = op_blank(1, 7, 1);
     op_tables(op, g, t);
-    op_set(op, 0, MUL_REAL, -1, -1, TAB_R3, 1.0);
-    CHK(xp(c, "x_mg_chi", c.slot(0), c.slot(9), op));
-    CHK(inv_y(c, "y_inv_mg", c.slot(9), 1));
-    CHK(z_c2r_ws(c, "z_c2r_mg", c.slot(9), 1));
-    RUN("square", 0.0, launch_square(p->prec, cnt, c.slot(9), s));
+    for (int j = 0; j < 3; ++j) {
+      op_set(op, 2 * j, MUL_MI, j, -1, TAB_R5, 1.0);
+      op_set(op, 2 * j + 1, MUL_PI, j, -1, TAB_R6, 1.0);
+    }
+    op_set(op, 6, MUL_REAL, -1, -1, TAB_R3, 1.0);
+    CHK(xp(c, "x_mg_grad", c.slot(0), c.slot(1), op));
+    CHK(inv_y(c, "y_inv_mg", c.slot(1), 7));
+    RUN("z_mg_grad", c.fields(7.0 + 3.0),
+        launch_zmg(p->prec, g.n, 2, 3, c.slot(1), c.cap(c.slot(1)), c.sstride(), c.slot(12), c.cap(c.slot(12)), afs,
+                   nlines, g.tw, s));
   }
-  const int nr = fr ? 5 : 3;
-  CHK(fwd_zy(c, "z_r2c_mg", "y_fwd_mg", c.one(c.slot(5), nr), c.cap(c.slot(5)), c.slot(5)));
+  const int nr = fr ? 4 : 2;
+  CHK(fwd_zy(c, "z_r2c_mg", "y_fwd_mg", c.one(c.slot(12), nr), c.cap(c.slot(12)), c.slot(12)));
   const double G = four_pi_g_rho(g.c, t->a);
   XOp op = op_blank(nr, 1, 0);
   op_tables(op, g, t);
-  op_set(op, 0, MUL_REAL, -1, -1, -1, G);       // F R1
-  op_set(op, 1, MUL_REAL, -1, -1, TAB_C2, 1.0);  // F R2
-  op_set(op, 2, MUL_REAL, -1, -1, TAB_C2, 1.0);  // F (tr phi)^2
+  op_set(op, 0, MUL_REAL, -1, -1, -1, G);        // F R1
+  op_set(op, 1, MUL_REAL, -1, -1, TAB_C2, 1.0);  // F [R2 + (tr phi)^2]
   if (fr) {
-    op_set(op, 3, MUL_REAL, -1, -1, TAB_C5, 1.0);  // F R5
-    op_set(op, 4, MUL_REAL, -1, -1, TAB_C4, 1.0);  // F chi^2
+    op_set(op, 2, MUL_REAL, -1, -1, TAB_C5, 1.0);  // F R5
+    op_set(op, 3, MUL_REAL, -1, -1, TAB_C4, 1.0);  // F chi^2
   }
-  CHK(xp(c, "x_fwd_mg", c.slot(5), c.slot(10), op));
+  CHK(xp(c, "x_fwd_mg", c.slot(12), c.slot(10), op));
   return LPT2_OK;
 }
 
