@@ -11,10 +11,12 @@ imports nothing from it; the only common input is the white noise drawn by
 
 Everything runs in float64 on the CPU (numpy for the growth ODE and the
 background, torch CPU tensors for grid fields so that autograd can
-differentiate the field pipeline).  FFTs are library calls (torch.fft, which
-wraps pocketfft); the brute-force DFT tests in ``tests/`` pin their use.
+differentiate the field pipeline).  The discrete Fourier transforms are the
+oracle's own (``fft``: mixed-radix Cooley-Tukey in tensor operations, no FFT
+library), pinned in ``tests/`` to the brute-force DFT.
 
 Modules
+    fft        -- the oracle's own 3D DFT (complex and real half spectrum)
     model      -- the parameter set (cosmology, gravity model, growth grid)
     cosmology  -- background, Hu-Sawicki m^2/M1/M2, mu(k,a), BBKS P(k), sigma8
     growth     -- the D1(k,a) and D2(k,a) ODEs (RK4 in ln a) and k tables
@@ -30,7 +32,7 @@ the docstrings of the functions that take them.  Parity-unpinned functions
 say so in their docstrings.
 """
 from .model import Model, preset
-from . import cosmology, growth, fields, spectrum, mgsource, cic, adjoint
+from . import fft, cosmology, growth, fields, spectrum, mgsource, cic, adjoint
 
-__all__ = ["Model", "preset", "cosmology", "growth", "fields", "spectrum",
+__all__ = ["Model", "preset", "fft", "cosmology", "growth", "fields", "spectrum",
            "mgsource", "cic", "adjoint"]

@@ -1,7 +1,7 @@
 """Gradients of the 2LPT pipeline w.r.t. the white noise (autograd on the oracle).
 
 Test infrastructure only (FP64 CPU oracle).  torch autograd differentiates
-the oracle's own FP64 chain (rfftn/irfftn, pointwise multipliers, the
+the oracle's own FP64 chain (its own real DFTs, pointwise multipliers, the
 quadratic source and the CIC paint); no hand-written adjoint lives here, so
 this is an independent check of the GPU's hand-written backward pass.
 """

@@ -83,7 +83,11 @@ def big_pi(k, a, m: Model):
 
 
 def bbks_transfer(k, m: Model):
-    """BBKS (Bardeen, Bond, Kaiser & Szalay 1986) transfer function, q = k/Gamma."""
+    """BBKS (Bardeen, Bond, Kaiser & Szalay 1986) transfer function, q = k/Gamma.
+
+    Parity unpinned: no tabulated values of the fit are available here; only
+    its limits (T -> 1 as k -> 0) and its use inside the sigma8 integral are
+    checked."""
     k = np.asarray(k, dtype=np.float64)
     q = k / (m.omega_m * m.h)
     x = 2.34 * q
@@ -101,6 +105,8 @@ def tophat_window(x):
 
 def sigma8_amplitude(m: Model, intervals: int = 1 << 16) -> float:
     """Amplitude A such that P(k) = A k^n_s T^2(k) has sigma(8 Mpc/h) = sigma8.
+
+    Pinned by an adaptive quadrature of int d^3k/(2 pi)^3 P W^2 over k.
 
     sigma^2 = (1/2 pi^2) Int k^3 P(k) W^2(8k) dln k, composite Simpson on
     ln k in [ln 1e-5, ln 1e3] with ``intervals`` (even) sub-intervals.

@@ -6,9 +6,10 @@ can differentiate the chain).
 Conventions
   * real fields are [n][n][n], C order (x slowest, z fastest); cell size
     L/n; particle (ix, iy, iz) sits at q = (ix, iy, iz) L/n;
-  * F is the unnormalised forward DFT, F^-1 carries 1/n^3 (torch's default);
-  * k = 2 pi m / L with m the signed FFT index; spectra keep the half
-    m_z in [0, n/2] that rfftn returns;
+  * F is the unnormalised forward DFT, F^-1 carries 1/n^3 (both from the
+    oracle's own transform in ``fft``);
+  * k = 2 pi m / L with m the signed DFT index; spectra keep the half
+    m_z in [0, n/2];
   * mask: the DC mode and every mode on a Nyquist plane (|m_i| = n/2 for any
     axis) are zero in delta(k), S(k) and every multiplier, so that the odd
     derivative multipliers i k_i are unambiguous and every spectrum is
@@ -38,7 +39,7 @@ import numpy as np
 import torch
 
 from . import cosmology as cz
-from . import growth
+from . import fft, growth
 from .model import Model
 
 PAIRS = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
@@ -52,7 +53,8 @@ def as_f64(x) -> torch.Tensor:
 
 def modes(n: int):
     """Signed integer mode numbers (mx, my, mz) broadcastable to [n, n, n//2+1]."""
-    full = np.fft.fftfreq(n, d=1.0 / n).round().astype(np.int64)
+    j = np.arange(n, dtype=np.int64)
+    full = np.where(j <= (n - 1) // 2, j, j - n)        # 0, 1, .., -1 (DFT order)
     half = np.arange(n // 2 + 1, dtype=np.int64)
     return full[:, None, None], full[None, :, None], half[None, None, :]
 
@@ -87,11 +89,11 @@ def shaping(m: Model, amplitude: float | None = None) -> np.ndarray:
 def delta_k(w, m: Model, amplitude: float | None = None) -> torch.Tensor:
     """delta(k) = F[w] sqrt(P n^3/V) mask (complex128, half spectrum)."""
     w = as_f64(w)
-    return torch.fft.rfftn(w) * torch.from_numpy(shaping(m, amplitude))
+    return fft.rfftn(w) * torch.from_numpy(shaping(m, amplitude))
 
 
 def _irfft(x: torch.Tensor, n: int) -> torch.Tensor:
-    return torch.fft.irfftn(x, s=(n, n, n))
+    return fft.irfftn(x, s=(n, n, n))
 
 
 def _inv_k2(m: Model):
@@ -142,7 +144,7 @@ def source(dk: torch.Tensor, m: Model) -> torch.Tensor:
 
 def source_k(s: torch.Tensor, m: Model) -> torch.Tensor:
     """S(k) = F[S] with DC and Nyquist planes zeroed."""
-    return torch.fft.rfftn(s) * torch.from_numpy(mask(m.n))
+    return fft.rfftn(s) * torch.from_numpy(mask(m.n))
 
 
 def psi2(sk: torch.Tensor, m: Model, d2_modes: np.ndarray) -> torch.Tensor:

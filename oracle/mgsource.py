@@ -20,8 +20,9 @@ Readings taken here:
   * phi^(1), delta^(1) inside S1..S4 are evolved by D1(k,a) (text after eq.
     s4); S_GR = -(G/2) D1_GR(a)^2 F[(tr phi)^2 - phi_ij phi_ji] from the
     unevolved potential, D1_GR normalised to 1 at a = 1.
-  * "divide the source term by the LCDM one" for complex values is taken as
-    Re(S_MG conj(S_GR)) / |S_GR|^2 per mode; modes with S_GR = 0 are left out.
+  * the ratio of the source to its LCDM counterpart (Sec. 3, the procedure
+    paragraph) is taken, for complex values, as Re(S_MG conj(S_GR)) / |S_GR|^2
+    per mode; modes with S_GR = 0 are left out.
   * triangle choice: weighted least squares of the bin means against the
     analytic ratio R_T(k) = D1(k1) D1(k2) B(k,k1,k2) / (D1_GR^2 (1 - c^2)),
     counts as weights, bins with mean k <= 0.4 h/Mpc.  The squeezed triangle
@@ -35,7 +36,7 @@ import numpy as np
 import torch
 
 from . import cosmology as cz
-from . import fields, growth, spectrum
+from . import fft, fields, growth, spectrum
 from .model import Model
 
 CANDIDATES = (
@@ -58,11 +59,11 @@ def d1_gr(a: float, m: Model) -> float:
 
 
 def _irfft(x, n):
-    return torch.fft.irfftn(x, s=(n, n, n))
+    return fft.irfftn(x, s=(n, n, n))
 
 
 def _rfft(x):
-    return torch.fft.rfftn(x)
+    return fft.rfftn(x)
 
 
 def full_source(w, m: Model, a: float, tab=None):
@@ -212,7 +213,7 @@ def direct_triangle_sum(dk: np.ndarray, m: Model, a: float, tab=None):
         tab = growth.tables(m.with_(factorisation="eds"), a)
     kn, d1, _ = tab
     f = 2.0 * math.pi / m.box
-    idx = np.fft.fftfreq(n, d=1.0 / n).round().astype(np.int64)
+    idx = fields.modes(n)[0].reshape(-1)
     g = float(cz.four_pi_g_rho(a, m))
     pos = [(i, j, l) for i in range(n) for j in range(n) for l in range(n)
            if dk[i, j, l] != 0 and (i, j, l) != (0, 0, 0)]

@@ -21,7 +21,9 @@ from __future__ import annotations
 import math
 
 import numpy as np
+import torch
 
+from . import fft
 from .fields import modes
 from .model import Model
 
@@ -87,7 +89,7 @@ def matter_power(delta, m: Model, nbins: int, deconvolve: bool = False):
     """Shell-averaged power of a real density contrast on the grid,
     q = V |F[delta]/n^3|^2, optionally divided by the CIC window squared."""
     d = delta.detach().numpy() if hasattr(delta, "detach") else np.asarray(delta)
-    dk = np.fft.rfftn(np.asarray(d, dtype=np.float64))
+    dk = fft.rfftn(torch.from_numpy(np.asarray(d, dtype=np.float64))).numpy()
     return _power_of(dk, m, nbins, deconvolve)
 
 
@@ -107,13 +109,14 @@ def interlaced_density_k(disp, m: Model) -> np.ndarray:
     two transforms are averaged.  The alias images whose index sum is odd
     enter the two with opposite signs and cancel."""
     from . import cic
-    import torch
     d = torch.as_tensor(disp, dtype=torch.float64)
     d1 = cic.paint(d, m).numpy()
     d2 = cic.paint(d + m.box / (2 * m.n), m).numpy()
     mx, my, mz = modes(m.n)
     phase = np.exp(1j * np.pi * (mx + my + mz) / m.n)
-    return 0.5 * (np.fft.rfftn(d1) + np.fft.rfftn(d2) * phase)
+    f1 = fft.rfftn(torch.from_numpy(d1)).numpy()
+    f2 = fft.rfftn(torch.from_numpy(d2)).numpy()
+    return 0.5 * (f1 + f2 * phase)
 
 
 def matter_power_interlaced(disp, m: Model, nbins: int, deconvolve: bool = False):

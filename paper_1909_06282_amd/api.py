@@ -224,6 +224,9 @@ class Plan:
         if g_noise is None:
             g_noise = [torch.empty_like(w) for w in noise]
         g_noise = self._lists(g_noise)
+        R = len(self.sizes)
+        if not (len(noise) == len(g_psi1) == len(g_psi2) == len(g_noise) == R):
+            raise ValueError(f"plan holds {R} realisations: noise, g_psi1, g_psi2 and g_noise need one entry each")
         for w, a1, a2, gw, n in zip(noise, g_psi1, g_psi2, g_noise, self.sizes):
             self._check_field(w, (n, n, n), "noise")
             self._check_field(a1, (3, n, n, n), "g_psi1")

@@ -141,3 +141,18 @@ def test_strerror():
     _, L = _lib()
     assert L.lpt2_strerror(0) == b"ok"
     assert L.lpt2_strerror(-2) == b"unsupported"
+
+
+def test_backward_refuses_lists_shorter_than_the_plan_before_any_device_work():
+    # the binding checks one entry per realisation before it builds the
+    # pointer arrays the library reads one per realisation
+    import torch
+    from paper_1909_06282_amd.api import Plan
+    p = Plan.__new__(Plan)
+    p.sizes, p.dtype, p.handle, p._lib = [8, 8], torch.float64, None, None
+    w = torch.zeros((8, 8, 8), dtype=torch.float64)
+    g = torch.zeros((3, 8, 8, 8), dtype=torch.float64)
+    for args in (([w], [g, g], [g, g]), ([w, w], [g], [g, g]), ([w, w], [g, g], [g]),
+                 ([w, w], [g, g], [g, g], [w])):
+        with pytest.raises(ValueError, match="realisations"):
+            p.backward(1.0, *args)
