@@ -297,9 +297,13 @@ lpt2_status lpt2_backward(lpt2_plan_t plan, double a, const void* const* noise,
 
 /* Cloud-in-cell density of the displaced particles of realisation 0:
  * delta[g] = sum_p prod_axes max(0, 1 - |x_p - g L/n|/(L/n)) - 1, periodic,
- * x_p = q_p + psi1_p + psi2_p.  delta is a device [n][n][n] output.  The
- * float atomics make the summation order, and so the last bits, vary from
- * run to run. */
+ * x_p = q_p + psi1_p + psi2_p (eq. position).  The density contrast of the
+ * displaced particles follows from mass conservation (eq. deltajacobian:
+ * each particle carries the mass of its Lagrangian cell); painting the
+ * particles on the mesh is the discrete form used here, which conserves the
+ * total mass exactly.  delta is a device [n][n][n] output.  Non-finite
+ * positions are not painted.  The float atomics make the summation order,
+ * and so the last bits, vary from run to run. */
 lpt2_status lpt2_paint_cic(lpt2_plan_t plan, const void* psi1, const void* psi2,
                            void* delta, void* stream);
 

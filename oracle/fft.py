@@ -27,7 +27,7 @@ from functools import lru_cache
 
 import torch
 
-DIRECT = 16
+DIRECT = 32
 
 
 @lru_cache(maxsize=None)
@@ -75,12 +75,36 @@ def _dft_last(x: torch.Tensor, sign: int) -> torch.Tensor:
     return y.transpose(-1, -2).reshape(*lead, n)        # index k1 + n1 k2
 
 
+def _dft_mid(x: torch.Tensor, sign: int) -> torch.Tensor:
+    """Unnormalised DFT along the middle axis of a contiguous [A][n][B]
+    complex tensor: the same index map as ``_dft_last``, laid out so that
+    the B values of one index move together (no strided gathers)."""
+    a, n, b = x.shape
+    n1 = _split(n)
+    if n <= DIRECT or n1 == 1:
+        return torch.matmul(_dft_matrix(n, sign), x)
+    n2 = n // n1
+    y = _dft_mid(x.reshape(a, n1, n2 * b), sign)        # [k1][j2] over j1 = x(n2 j1 + j2)
+    y = y.reshape(a, n1, n2, b) * _twiddle(n1, n2, sign).T.reshape(1, n1, n2, 1)
+    y = y.transpose(1, 2).reshape(a, n2, n1 * b)        # [j2][k1]
+    y = _dft_mid(y, sign)                               # [k2][k1]: index k1 + n1 k2
+    return y.reshape(a, n, b)
+
+
 def dft(x: torch.Tensor, dim: int, inverse: bool = False) -> torch.Tensor:
     """DFT of a complex tensor along ``dim`` (F, or F^-1 with its 1/n)."""
     sign = 1 if inverse else -1
-    y = _dft_last(x.movedim(dim, -1), sign).movedim(-1, dim)
+    dim = dim % x.dim()
+    n = x.shape[dim]
+    if dim == x.dim() - 1:
+        y = _dft_last(x, sign)
+    else:
+        shape = x.shape
+        a = math.prod(shape[:dim])
+        b = math.prod(shape[dim + 1:])
+        y = _dft_mid(x.contiguous().reshape(a, n, b), sign).reshape(shape)
     if inverse:
-        y = y / x.shape[dim]
+        y = y / n
     return y
 
 

@@ -494,57 +494,4 @@ hipError_t launch_cic_back(int prec, int n, double box, const void* psi1, const 
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// real-space accumulators of the full MG source
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ void k_mg_pair(long count, T w, const T* __restrict__ pa, const T* __restrict__ pm,
-                          const T* __restrict__ c, T* __restrict__ r1, T* __restrict__ r2, T* __restrict__ r5,
-                          T* __restrict__ tr) {
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x) {
-    const T a = pa[i];
-    r1[i] += w * a * pm[i];
-    r2[i] += w * a * a;
-    if (c) r5[i] += T(2) * w * a * c[i];
-    if (tr) tr[i] += a;
-  }
-}
-template <typename T>
-__global__ void k_mg_dot(long count, const T* __restrict__ p, const T* __restrict__ q, T* __restrict__ r5) {
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x)
-    r5[i] += p[i] * q[i];
-}
-template <typename T>
-__global__ void k_square(long count, T* __restrict__ x) {
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x)
-    x[i] = x[i] * x[i];
-}
-
-hipError_t launch_mg_pair(int prec, long count, double w, const void* pa, const void* pm, const void* c, void* r1,
-                          void* r2, void* r5, void* tr, hipStream_t s) {
-  if (prec == PREC_F32)
-    hipLaunchKernelGGL(k_mg_pair<float>, dim3(grid_for(count)), dim3(256), 0, s, count, (float)w, (const float*)pa,
-                       (const float*)pm, (const float*)c, (float*)r1, (float*)r2, (float*)r5, (float*)tr);
-  else
-    hipLaunchKernelGGL(k_mg_pair<double>, dim3(grid_for(count)), dim3(256), 0, s, count, w, (const double*)pa,
-                       (const double*)pm, (const double*)c, (double*)r1, (double*)r2, (double*)r5, (double*)tr);
-  return hipGetLastError();
-}
-hipError_t launch_mg_dot(int prec, long count, const void* p, const void* q, void* r5, hipStream_t s) {
-  if (prec == PREC_F32)
-    hipLaunchKernelGGL(k_mg_dot<float>, dim3(grid_for(count)), dim3(256), 0, s, count, (const float*)p,
-                       (const float*)q, (float*)r5);
-  else
-    hipLaunchKernelGGL(k_mg_dot<double>, dim3(grid_for(count)), dim3(256), 0, s, count, (const double*)p,
-                       (const double*)q, (double*)r5);
-  return hipGetLastError();
-}
-hipError_t launch_square(int prec, long count, void* x, hipStream_t s) {
-  if (prec == PREC_F32)
-    hipLaunchKernelGGL(k_square<float>, dim3(grid_for(count)), dim3(256), 0, s, count, (float*)x);
-  else
-    hipLaunchKernelGGL(k_square<double>, dim3(grid_for(count)), dim3(256), 0, s, count, (double*)x);
-  return hipGetLastError();
-}
-
 }  // namespace lpt2

@@ -181,16 +181,7 @@ hipError_t launch_positions(int prec, int n, double box, const void* psi1, const
 hipError_t launch_cic_back(int prec, int n, double box, const void* psi1, const void* psi2, const void* gdelta,
                            void* gpsi, hipStream_t s);
 
-// real-space helpers of the full modified-gravity source
-// (each pointer given to these must hold at least `count` values; the
-// caller checks that, the buffers being whole fields)
+// x[0..count) = value (x must hold count values)
 hipError_t launch_fill(int prec, void* x, long count, double value, hipStream_t s);
-// r1 += w pa pm; r2 += w pa^2; r5 += 2 w pa c (if c); tr += pa (if tr)
-hipError_t launch_mg_pair(int prec, long count, double w, const void* pa, const void* pm, const void* c, void* r1,
-                          void* r2, void* r5, void* tr, hipStream_t s);
-// r5 += p q
-hipError_t launch_mg_dot(int prec, long count, const void* p, const void* q, void* r5, hipStream_t s);
-// x = x * x
-hipError_t launch_square(int prec, long count, void* x, hipStream_t s);
 
 }  // namespace lpt2

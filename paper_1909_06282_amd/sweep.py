@@ -10,11 +10,12 @@ the comparison with the LCDM fit of D2):
     wavenumbers, the count-weighted misfit of each over k <= kcut, and the
     chosen candidate;
   * on the growth-table nodes: D1(k,a), D2(k,a) of the T1 factorisation, and
-    D2 of the LCDM fit (eq. lcdm-fit) and of GR, for D2_T1 / D2_fit.
+    D2 of the LCDM fit (eq. lcdm-fit) and of GR.
 
 Every number comes from the library's entry points (lpt2_source_spectrum,
 lpt2_triangle_ratio, lpt2_choose_factorisation, lpt2_growth_table);
-this module only loops and collects.
+this module only loops and collects.  The caller supplies the white noise
+(a device tensor); the command line draws unit Gaussian noise from a seed.
 
     python -m paper_1909_06282_amd.sweep --n 128 --box 256 \\
         --fr0 1e-4 1e-5 1e-6 --z 0 0.5 1 --out sweep.json
@@ -56,17 +57,15 @@ def sweep_point(noise: torch.Tensor, n: int, box: float, fr0: float, z: float, n
         "shells": {key: spec[key][sel].tolist() for key in ("k_mean", "count", "mean", "std")},
         "triangle_ratio": curves, "costs": costs, "chosen": chosen,
         "growth": {"k": kn.tolist(), "d1": d1.tolist(), "d2_t1": d2.tolist(), "d2_lcdm_fit": fit.tolist(),
-                   "d1_gr": gr[1].tolist(), "d2_gr": gr[2].tolist(),
-                   "d2_t1_over_fit": (d2 / fit).tolist()},
+                   "d1_gr": gr[1].tolist(), "d2_gr": gr[2].tolist()},
     }
 
 
-def sweep(n: int, box: float, fr0_list, z_list, seed: int = 1, nbins: int | None = None, kcut: float = 0.4,
+def sweep(noise: torch.Tensor, box: float, fr0_list, z_list, nbins: int | None = None, kcut: float = 0.4,
           precision: str = "fp64", **cosmo) -> list:
-    """sweep_point over every (|f_R0|, z), all on the white noise of ``seed``."""
-    from seeded_inputs import white_noise
-    dt = np.float32 if precision == "fp32" else np.float64
-    noise = torch.from_numpy(white_noise(n, seed, dt)).cuda()
+    """sweep_point over every (|f_R0|, z), all on the same white noise
+    (a contiguous [n][n][n] device tensor of the plan's precision)."""
+    n = int(noise.shape[0])
     nb = nbins or n // 2
     return [sweep_point(noise, n, box, f, z, nb, kcut, precision, **cosmo) for f in fr0_list for z in z_list]
 
@@ -83,14 +82,17 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--out", default=None, help="write the records as JSON")
     args = ap.parse_args()
-    recs = sweep(args.n, args.box, args.fr0, args.z, args.seed, args.nbins, args.kcut, args.precision)
+    dt = np.float32 if args.precision == "fp32" else np.float64
+    w = np.random.default_rng(args.seed).standard_normal((args.n, args.n, args.n)).astype(dt)
+    noise = torch.from_numpy(w).cuda()
+    recs = sweep(noise, args.box, args.fr0, args.z, args.nbins, args.kcut, args.precision)
     for r in recs:
         best = sorted(r["costs"].items(), key=lambda kv: kv[1])[:3]
         g = r["growth"]
         i = int(np.argmin(np.abs(np.log(np.asarray(g["k"]) / 0.1))))
         print(f"|f_R0|={r['fr0']:g} z={r['z']:g}: chosen {r['chosen']:12s} "
-              f"best {', '.join(f'{k} {v:.4g}' for k, v in best)}; D2_T1/D2_fit at k={g['k'][i]:.3f}: "
-              f"{g['d2_t1_over_fit'][i]:.4f}", flush=True)
+              f"best {', '.join(f'{k} {v:.4g}' for k, v in best)}; at k={g['k'][i]:.3f}: D2_T1 "
+              f"{g['d2_t1'][i]:.6g}, D2 of the LCDM fit {g['d2_lcdm_fit'][i]:.6g}", flush=True)
     if args.out:
         with open(args.out, "w") as fh:
             json.dump(recs, fh)

@@ -3,18 +3,26 @@
   * C2: 256^3, L = 512, |f_R0| = 1e-5, z = 0: FP64 <= 1e-12 and FP32 <= 1e-5
     against the full FP64 oracle; the 128-bin source spectrum; the 128-bin
     S_MG/S_GR spectrum and the factorisation choice;
-  * C3: 512^3, L = 1024, FP32 against the full FP64 oracle (one seed per
-    (|f_R0|, z) corner is too slow for the oracle; seed 1 at F6 z = 0 and F4
-    z = 1 are checked);
+  * C3: 512^3, L = 1024, FP32 against the full FP64 oracle at every
+    (|f_R0|, z) corner the benchmark cycles through, one of seeds 1-4 each;
+    FP64 against the oracle at one corner (<= 1e-12); a second output time
+    of lpt2_displace_epochs against the oracle;
   * C4: the batched mix (64 x 128^3 + 32 x 64^3, seeds 100-195) as one
     tuned, graph-captured FP32 plan: every realisation against the batched
     FP64 GPU path, the first and last of each size against the oracle;
   * mixed radix: 384^3 FP64 and FP32 against the oracle; the paper's 768^3
-    grid (L = 750) FP32 against the FP64 GPU path;
+    grid (L = 750) FP32 against the FP64 GPU path (and, when
+    LPT2_ORACLE_768=1 is set, FP64 against the oracle: several minutes of
+    CPU and ~100 GB of host memory);
   * C5: the adjoint at 128^3: FP32 gradient against the FP64 oracle's
     autograd gradient, and the FP64 GPU gradient against central finite
     differences (eps = 1e-3) on 64 cells.
+
+The oracle's a-independent pieces of one noise field (delta(k) and S(k)) are
+computed once and reused by the checks of that field at other |f_R0| and a.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -40,17 +48,48 @@ def _plan(**kw):
     return Plan(cfg), cfg
 
 
+_SOURCE = {}   # (n, box, cosmology, seed) -> oracle (delta(k), S(k)); one field kept at a time
+
+
+def _oracle_displace(m, w, seed, a):
+    """The oracle's psi1, psi2 (fields.displace step by step), with delta(k)
+    and S(k), which depend on neither the gravity model nor a, shared between
+    the checks of one noise field."""
+    key = (m.n, m.box, m.omega_m, m.h, m.n_s, m.sigma8, seed)
+    if key not in _SOURCE:
+        _SOURCE.clear()
+        print(f"  oracle delta(k), S(k) n={m.n} seed={seed}", flush=True)
+        dk = fields.delta_k(w, m)
+        sk = fields.source_k(fields.source(dk, m), m)
+        _SOURCE[key] = (dk, sk)
+    dk, sk = _SOURCE[key]
+    print(f"  oracle psi1, psi2 a={a:.4g}", flush=True)
+    d1m, d2m = fields.growth_on_modes(m, a, growth.tables(m, a))
+    return fields.psi1(dk, m, d1m), fields.psi2(sk, m, d2m)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _drop_oracle_fields():
+    yield
+    _SOURCE.clear()
+
+
+def _errors(g1, g2, r1, r2):
+    return normwise(g1, r1), normwise(g2, r2), normwise(g1 + g2, r1 + r2)
+
+
 def _parity(prec, a, seed, tol, **kw):
     plan, cfg = _plan(precision=prec, **kw)
     m = oracle_model(cfg)
     w = white_noise(cfg.n, seed)
+    print(f"  gpu {prec} n={cfg.n} seed={seed} a={a:.4g}", flush=True)
     p1, p2 = plan.displace(a, to_dev(w, cfg.dtype))
     torch.cuda.synchronize()
     g1, g2 = p1.cpu().double(), p2.cpu().double()
     del p1, p2
     plan.close()
-    r1, r2 = fields.displace(w, m, a, growth.tables(m, a))
-    e1, e2, et = normwise(g1, r1), normwise(g2, r2), normwise(g1 + g2, r1 + r2)
+    r1, r2 = _oracle_displace(m, w, seed, a)
+    e1, e2, et = _errors(g1, g2, r1, r2)
     print(f"  {prec} n={cfg.n} a={a}: psi1 {e1:.3e} psi2 {e2:.3e} total {et:.3e}", flush=True)
     assert e1 < tol and e2 < tol and et < tol
 
@@ -105,10 +144,40 @@ def test_c2_source_ratio_and_factorisation_choice():
         assert abs(costs[k] - v) <= 1e-8 * max(1.0, abs(v)), k
 
 
-@pytest.mark.parametrize("fr0,z", [(1e-6, 0.0), (1e-4, 1.0)])
-def test_c3_fp32_displacements(fr0, z):
-    print(f"C3 fp32 fr0={fr0} z={z}", flush=True)
-    _parity("fp32", 1.0 / (1.0 + z), 1, 1e-5, fr0_abs=fr0, **C3)
+# every (|f_R0|, z) corner the benchmark cycles through, seeds 1-4 (seed 3
+# last: the FP64 and multi-epoch checks below reuse its oracle source)
+C3_CORNERS = [(1e-6, 0.0, 1), (1e-6, 1.0, 2), (1e-4, 1.0, 4), (1e-4, 0.0, 3)]
+
+
+@pytest.mark.parametrize("fr0,z,seed", C3_CORNERS)
+def test_c3_fp32_displacements(fr0, z, seed):
+    print(f"C3 fp32 fr0={fr0} z={z} seed={seed}", flush=True)
+    _parity("fp32", 1.0 / (1.0 + z), seed, 1e-5, fr0_abs=fr0, **C3)
+
+
+def test_c3_fp64_displacements():
+    # the FP64 path bench.py reports beside the FP32 headline
+    print("C3 fp64 fr0=1e-4 z=0 seed=3", flush=True)
+    _parity("fp64", 1.0, 3, 1e-12, fr0_abs=1e-4, **C3)
+
+
+def test_c3_epochs_fp32_second_output_time():
+    # lpt2_displace_epochs at a = 1 and 0.5 (z = 0 and 1) from one source:
+    # both epochs against the oracle (the second reuses F[w] and F[S])
+    print("C3 epochs fp32 fr0=1e-4 seed=3 a=(1, 0.5)", flush=True)
+    plan, cfg = _plan(precision="fp32", fr0_abs=1e-4, **C3)
+    m = oracle_model(cfg)
+    w = white_noise(cfg.n, 3)
+    outs = plan.displace_epochs([1.0, 0.5], to_dev(w, torch.float32))
+    torch.cuda.synchronize()
+    got = [(p1.cpu().double(), p2.cpu().double()) for p1, p2 in outs]
+    del outs
+    plan.close()
+    for (g1, g2), a in zip(got, (1.0, 0.5)):
+        r1, r2 = _oracle_displace(m, w, 3, a)
+        e1, e2, et = _errors(g1, g2, r1, r2)
+        print(f"  epoch a={a}: psi1 {e1:.3e} psi2 {e2:.3e} total {et:.3e}", flush=True)
+        assert e1 < 1e-5 and e2 < 1e-5 and et < 1e-5
 
 
 C4 = [dict(n=128, box=256.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1"),
@@ -173,7 +242,7 @@ def test_mixed_radix_384_displacements(prec, tol):
     plan, cfg = _plan(precision=prec, n=384, box=768.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1")
     m = oracle_model(cfg)
     w = white_noise(cfg.n, 2)
-    r1, r2 = fields.displace(w, m, 1.0, growth.tables(m, 1.0))
+    r1, r2 = _oracle_displace(m, w, 2, 1.0)
     wide = max(plan.tile_options(0)[1])
     for tiles in ([0, 0, 0], [0, wide, 0]):
         plan.set_tiles(0, tiles)
@@ -206,6 +275,13 @@ def test_backward_384_wide_fan_in_tile_agrees():
     print(f"  tiles {plan.get_tiles(0)}: relative L2 {e:.3e}", flush=True)
     assert e < 1e-5
     plan.close()
+
+
+@pytest.mark.skipif(os.environ.get("LPT2_ORACLE_768") != "1",
+                    reason="the 768^3 FP64 oracle takes minutes and ~100 GB of host memory; set LPT2_ORACLE_768=1")
+def test_mixed_radix_768_fp64_vs_oracle():
+    print("mixed radix 768^3 fp64 vs oracle", flush=True)
+    _parity("fp64", 1.0, 1, 1e-12, n=768, box=750.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1")
 
 
 def test_mixed_radix_768_fp32_vs_fp64():
@@ -261,29 +337,68 @@ def test_c5_adjoint_fp64_vs_oracle_autograd():
 
 
 def test_c5_adjoint_fp32_vs_fp64_gpu():
-    # The FP32 gradient differs from the FP64 one where an FP32 particle
-    # position falls on the other side of a CIC cell face (the CIC weight
-    # slope jumps there).  With position errors ~1e-6 cells about
-    # 3 n^3 1e-6 ~ a few particles flip; each moves the gradient by an O(1)
-    # share of one particle's contribution, i.e. a relative L2 change of order
-    # sqrt(flips / n^3) ~ 1e-3.  Tolerance: relative L2 <= 2e-3, loss <= 1e-5.
+    # The loss gradient is g = B(d): d = dL/dx from the CIC transpose (per
+    # particle), B the transpose of the displacement chain (lpt2_backward,
+    # linear).  So g32 - g64 = (B32 - B64)(d32) + B64(d32 - d64): FP32
+    # rounding of a linear chain, plus the change of d.  d is piecewise
+    # constant in the particle position along each axis (the CIC weight
+    # slope jumps at cell faces), so d32 - d64 is rounding except at the
+    # particles that sit, within the FP32-vs-FP64 position difference, on a
+    # cell face: there it jumps by up to two one-sided values.  Asserted:
+    #   * |g32 - g64 - B64(d32 - d64)| <= 1e-5 |g64|;
+    #   * every particle whose d moved by more than 1e-4 max|d| is within
+    #     2 max|u32 - u64| of a face (u: position in cell units);
+    #   * away from those particles, |d32 - d64| <= 1e-5 |d64|;
+    #   * on them, |d32 - d64| <= 2 sqrt(3 count) max|d64| (the count bound).
     print("C5 adjoint fp32 vs fp64", flush=True)
-    w = white_noise(128, 1)
+    n, box = 128, 256.0
+    w = white_noise(n, 1)
     out = {}
     for prec in ("fp64", "fp32"):
-        plan, cfg, loss, target = _c5_loss_pieces(prec)
-        wt = to_dev(w, cfg.dtype).requires_grad_(True)
-        L = loss(wt)
-        L.backward()
-        out[prec] = (float(L), wt.grad.double().cpu())
-        plan.close()
-    l64, g64 = out["fp64"]
-    l32, g32 = out["fp32"]
-    l2 = float((g32 - g64).norm() / g64.norm())
-    print(f"  loss rel {abs(l32 / l64 - 1):.3e} gradient relative L2 {l2:.3e} normwise {normwise(g32, g64):.3e}",
-          flush=True)
-    assert abs(l32 / l64 - 1) < 1e-5
-    assert l2 < 2e-3
+        plan, cfg = _plan(precision=prec, n=n, box=box, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1")
+        with torch.no_grad():
+            t1, t2 = plan.displace(1.0, to_dev(white_noise(n, 7), cfg.dtype))
+            target = plan.paint_cic(t1, t2).clone()
+            wd = to_dev(w, cfg.dtype)
+            p1, p2 = plan.displace(1.0, wd)
+            delta = plan.paint_cic(p1, p2)
+            loss = float(((delta.double() - target.double()) ** 2).sum())
+            d = plan.paint_cic_backward(p1, p2, (2.0 * (delta - target)).contiguous())
+            g = plan.backward(1.0, wd, d, d)
+            torch.cuda.synchronize()
+        out[prec] = dict(plan=plan, wd=wd, loss=loss, d=d.double(), g=g.double(), disp=(p1.double() + p2.double()))
+    o64, o32 = out["fp64"], out["fp32"]
+    g64, g32 = o64["g"], o32["g"]
+    dd = (o32["d"] - o64["d"]).contiguous()
+    g_lin = o64["plan"].backward(1.0, o64["wd"], dd, dd).double()
+    torch.cuda.synchronize()
+    e_total = float((g32 - g64).norm() / g64.norm())
+    e_resid = float((g32 - g64 - g_lin).norm() / g64.norm())
+    # positions in cell units and their distance to the nearest face
+    cell = box / n
+    u64 = o64["disp"].cpu() / cell
+    u32 = o32["disp"].cpu() / cell
+    eps = float((u32 - u64).abs().max())
+    frac = u64 - torch.floor(u64)
+    face = torch.minimum(frac, 1.0 - frac)
+    near = (face < 2.0 * eps).any(dim=0)                      # [n][n][n] particles near a face
+    dmax = float(o64["d"].abs().max())
+    jump = ((dd.abs() > 1e-4 * dmax).any(dim=0)).cpu()
+    count = int(near.sum())
+    far = (~near).to(dd.device)
+    e_far = float((dd * far).norm() / o64["d"].norm())
+    d_near = float((dd * near.to(dd.device)).norm())
+    print(f"  loss rel {abs(o32['loss'] / o64['loss'] - 1):.3e}; gradient relative L2 {e_total:.3e}, "
+          f"after the d-change term {e_resid:.3e}", flush=True)
+    print(f"  max position difference {eps:.2e} cells; particles within 2x of a face {count}; "
+          f"particles whose d jumped {int(jump.sum())}; |dd| off them {e_far:.2e} rel", flush=True)
+    assert abs(o32["loss"] / o64["loss"] - 1) < 1e-5
+    assert e_resid < 1e-5
+    assert not bool((jump & ~near).any())
+    assert e_far < 1e-5
+    assert d_near <= 2.0 * (3 * count) ** 0.5 * dmax
+    for o in out.values():
+        o["plan"].close()
 
 
 def test_c5_adjoint_fp64_vs_finite_differences():
@@ -307,7 +422,11 @@ def test_c5_adjoint_fp64_vs_finite_differences():
           flush=True)
     for i in order[:4]:
         c = cells[i]
-        print(f"  cell {c}: grad {g[c].item():.6e} fd(1e-3) {fd(c, 1e-3):.6e} fd(3e-4) {fd(c, 3e-4):.6e} "
-              f"fd(1e-4) {fd(c, 1e-4):.6e}", flush=True)
+        f3, f34, f4 = fd(c, 1e-3), fd(c, 3e-4), fd(c, 1e-4)
+        gc = g[c].item()
+        print(f"  cell {c}: grad {gc:.6e} fd(1e-3) {f3:.6e} fd(3e-4) {f34:.6e} fd(1e-4) {f4:.6e}", flush=True)
+        # the mismatch comes from CIC kinks inside the FD step: it shrinks with the step
+        if abs(f3 - gc) > 1e-3 * max(1.0, abs(gc)):
+            assert abs(f4 - gc) < abs(f3 - gc), c
     assert np.median(mis) < 1e-3
     assert mis.max() < 5e-2

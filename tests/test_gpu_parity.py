@@ -54,7 +54,7 @@ def test_fft3d_forward_matches_dft(n, prec):
     plan, cfg = _plan(precision=prec, n=n, box=2.0 * n)
     x = white_noise(n, 5)
     got = plan.fft3d(-1, to_dev(x, cfg.dtype)).cpu().to(torch.complex128)
-    ref = torch.fft.rfftn(torch.from_numpy(x))[:, :, : n // 2]
+    ref = oracle.fft.rfftn(torch.from_numpy(x))[:, :, : n // 2]
     err = float((got - ref).abs().max() / ref.abs().max())
     assert err < (1e-14 if prec == "fp64" else 1e-6), err
 
@@ -65,9 +65,9 @@ def test_fft3d_inverse_matches_dft(n, prec):
     print(f"fft3d inverse n={n} {prec}", flush=True)
     plan, cfg = _plan(precision=prec, n=n, box=2.0 * n)
     x = white_noise(n, 6)
-    half = torch.fft.rfftn(torch.from_numpy(x))
+    half = oracle.fft.rfftn(torch.from_numpy(x))
     half[:, :, n // 2] = 0
-    ref = torch.fft.irfftn(half, s=(n, n, n)) * n ** 3
+    ref = oracle.fft.irfftn(half, s=(n, n, n)) * n ** 3
     inp = torch.view_as_real(half[:, :, : n // 2].contiguous()).to(cfg.dtype).cuda().contiguous()
     got = plan.fft3d(+1, inp).cpu()
     assert normwise(got, ref) < (1e-14 if prec == "fp64" else 1e-6)
@@ -129,6 +129,29 @@ def test_displace_fr_t1_fp32(n):
                     factorisation="t1", nk_growth=64)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", F64_TOL), ("fp32", F32_TOL)])
+def test_displace_epochs_match_oracle(prec, tol):
+    # lpt2_displace_epochs: the full chain at the first a, the first-order x
+    # pass and the psi2 passes from the kept F[w], F[S] at the others; every
+    # output time against the oracle (the factorisation of the unevolved
+    # potential, Sec. 2.4)
+    print(f"epochs vs oracle {prec} n=32", flush=True)
+    plan, cfg = _plan(precision=prec, n=32, box=64.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1",
+                      nk_growth=64)
+    m = oracle_model(cfg)
+    w = white_noise(32, 5)
+    a_list = [1.0, 2.0 / 3.0, 0.5, 0.25]
+    outs = plan.displace_epochs(a_list, to_dev(w, cfg.dtype))
+    torch.cuda.synchronize()
+    for (p1, p2), a in zip(outs, a_list):
+        r1, r2 = fields.displace(w, m, a, _tables(m, a))
+        e1, e2 = normwise(p1, r1), normwise(p2, r2)
+        tot = normwise(p1.double() + p2.double(), r1 + r2)
+        print(f"  a={a:.4f}: psi1 {e1:.3e} psi2 {e2:.3e} total {tot:.3e}", flush=True)
+        assert e1 < tol and e2 < tol and tot < tol
+    plan.close()
+
+
 def test_displace_batched_plan_matches_single():
     print("displace two-grid plan", flush=True)
     from paper_1909_06282_amd import Plan
@@ -178,7 +201,7 @@ def test_displace_delta_matches_oracle(prec, tol):
     p1, p2 = plan.displace_delta(0.8, to_dev(dx, cfg.dtype))
     torch.cuda.synchronize()
     m = oracle_model(cfg)
-    dk = torch.fft.rfftn(torch.from_numpy(dx))
+    dk = oracle.fft.rfftn(torch.from_numpy(dx))
     r1, r2 = fields.displace_from_delta_k(dk, m, 0.8, _tables(m, 0.8))
     e1, e2 = normwise(p1, r1), normwise(p2, r2)
     print(f"  psi1 {e1:.3e} psi2 {e2:.3e}", flush=True)
