@@ -230,15 +230,14 @@ def epochs_timing(reps: int):
             "value": len(a_list) * float(N) ** 3 / (t_ep / 1e3), "unit": "grid-cells/s"}
 
 
-def grid768_timing(reps: int):
-    """The paper's own grid size: one 768^3 realisation in 750 Mpc/h (three
-    times a power of two: a radix-12 first stage), |f_R0| = 1e-5, z = 0, FP32."""
+def grid_timing(n: int, box: float, reps: int, note: str):
+    """One realisation of the paper's own grid sizes: n^3 in `box` Mpc/h,
+    |f_R0| = 1e-5, z = 0, FP32, with the per-kernel breakdown."""
     import numpy as np
     import torch
     from paper_1909_06282_amd import LPT2Config, Plan
     from seeded_inputs import white_noise
-    n = 768
-    plan = Plan(LPT2Config(n=n, box=750.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", precision="fp32"))
+    plan = Plan(LPT2Config(n=n, box=box, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", precision="fp32"))
     w = torch.from_numpy(white_noise(n, 1, np.float32)).cuda()
     p1 = torch.empty((3, n, n, n), dtype=torch.float32, device="cuda")
     p2 = torch.empty_like(p1)
@@ -249,9 +248,22 @@ def grid768_timing(reps: int):
     prof = {name: {"avg_ms": round(t / max(l, 1), 4), "GBps": round(by / (t / l / 1e3) / 1e9, 1) if t > 0 else None}
             for name, l, t, by in plan.profile()}
     plan.profile_enable(False)
-    return {"workload": "768^3 (L=750 Mpc/h) |f_R0|=1e-5 z=0 FP32 seed 1", "ms_per_step": round(ms, 3),
+    plan.close()
+    return {"workload": f"{n}^3 (L={box:g} Mpc/h) |f_R0|=1e-5 z=0 FP32 seed 1 ({note})", "ms_per_step": round(ms, 3),
             "value": float(n) ** 3 / (ms / 1e3), "unit": "grid-cells/s",
             "algorithmic_GBps": round(53 * 4 * float(n) ** 3 / (ms / 1e3) / 1e9, 1), "kernels": prof}
+
+
+def grid768_timing(reps: int):
+    """The paper's N-body grid: 768^3 in 750 Mpc/h (three times a power of
+    two: a radix-12 first stage)."""
+    return grid_timing(768, 750.0, reps, "radix-12 first stage")
+
+
+def grid700_timing(reps: int):
+    """The paper's 700 Mpc/h box at one particle per Mpc/h: 700^3 (x/y
+    radices 5, 7, 4, 5; z 5, 7, 2, 5)."""
+    return grid_timing(700, 700.0, reps, "radices 5 and 7")
 
 
 def matter_power_timing(reps: int):
@@ -301,12 +313,17 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the adjoint and factorisation-choice timings")
     ap.add_argument("--only-768", action="store_true",
                     help="time only the 768^3 grid (for profiling it) and print its record")
+    ap.add_argument("--only-700", action="store_true",
+                    help="time only the 700^3 grid (for profiling it) and print its record")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.only_768:
         print(json.dumps({"grid_768": grid768_timing(max(1, args.steps))}), flush=True)
+        return
+    if args.only_700:
+        print(json.dumps({"grid_700": grid700_timing(max(1, args.steps))}), flush=True)
         return
 
     import numpy as np
@@ -456,6 +473,8 @@ def main():
         out["epochs"] = epochs_timing(4)
         torch.cuda.empty_cache()
         out["grid_768"] = grid768_timing(5)
+        torch.cuda.empty_cache()
+        out["grid_700"] = grid700_timing(5)
         torch.cuda.empty_cache()
     out["numpy"] = np.__version__
     if not args.no_cpu:

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblpt2.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["fft_kernels.hip", "aux_kernels.hip", "lpt2_api.cpp"]
+SOURCES = ["fft_kernels.hip", "aux_kernels.hip", "lpt2_api.cpp"] + sorted(
+    f for f in os.listdir(CSRC) if f.startswith("fft_sizes_") and f.endswith(".hip"))
 ARCH = "gfx950"
 
 FLAGS = [
@@ -49,7 +50,8 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    workers = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS") or (os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]

@@ -139,11 +139,14 @@ hipError_t launch_radial(const RadialSetup& r, const double* d1n, const double* 
 // in a fixed order, and a second kernel sums the block partials in block
 // order with Neumaier compensation: the result is bitwise reproducible.
 // ---------------------------------------------------------------------------
+// the largest divisor of m that is at most 64 (a chunk of a line in one wavefront)
+constexpr int bin_chunk(int m, int c = 64) { return c <= 1 ? 1 : (m % c == 0 ? c : bin_chunk(m, c - 1)); }
+
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_bin1(const Cx<T>* __restrict__ A, const Cx<T>* __restrict__ B, int quantity,
                                               double qscale, int nbins, double kf, double* __restrict__ partial) {
   constexpr int M = N / 2;
-  constexpr int CH = M <= 64 ? M : (M % 64 == 0 ? 64 : 48);  // chunk of a line: divides M
+  constexpr int CH = bin_chunk(M);  // chunk of a line: divides M
   constexpr int CPL = M / CH;  // chunks per line
   static_assert(M % CH == 0, "a line must split into whole chunks");
   __shared__ double hist[4][BIN_MAXBINS][4];
@@ -278,6 +281,8 @@ hipError_t launch_bin(int prec, int n, const void* A, size_t a_cap, const void* 
     case 128: CALL(128); case 256: CALL(256); case 512: CALL(512);
     case 24: CALL(24); case 48: CALL(48); case 96: CALL(96); case 192: CALL(192);
     case 384: CALL(384); case 768: CALL(768);
+    case 40: CALL(40); case 56: CALL(56); case 200: CALL(200); case 400: CALL(400);
+    case 600: CALL(600); case 700: CALL(700);
     default: return hipErrorInvalidValue;
   }
 #undef CALL
@@ -302,7 +307,7 @@ __global__ __launch_bounds__(256) void k_cic(int n, double inv_cell, double shif
   constexpr int R3 = CIC_R * CIC_R * CIC_R;
   __shared__ T acc[R3];
   const long n3 = (long)n * n * n;
-  const int tpa = n / CIC_T;  // tiles per axis
+  const int tpa = (n + CIC_T - 1) / CIC_T;  // tiles per axis (the last one partial when CIC_T does not divide n)
   const int bt = blockIdx.x;
   const int tx = bt / (tpa * tpa), ty = (bt / tpa) % tpa, tz = bt % tpa;
   const long o0[3] = {(long)tx * CIC_T - CIC_H, (long)ty * CIC_T - CIC_H, (long)tz * CIC_T - CIC_H};
@@ -311,6 +316,7 @@ __global__ __launch_bounds__(256) void k_cic(int n, double inv_cell, double shif
   auto wrap = [n](long g) { long r = g % n; return r < 0 ? r + n : r; };
   for (int q = threadIdx.x; q < CIC_T * CIC_T * CIC_T; q += blockDim.x) {
     const int id[3] = {tx * CIC_T + q / (CIC_T * CIC_T), ty * CIC_T + (q / CIC_T) % CIC_T, tz * CIC_T + q % CIC_T};
+    if (id[0] >= n || id[1] >= n || id[2] >= n) continue;  // beyond a partial tile
     const long p = ((long)id[0] * n + id[1]) * n + id[2];
     long i0[3];
     double f[3];
@@ -405,8 +411,9 @@ hipError_t launch_cic(int prec, int n, double box, const void* psi1, const void*
   hipError_t e = launch_fill(prec, delta, n3, -1.0, s);
   if (e != hipSuccess) return e;
   const double ic = n / box;
-  if (n % CIC_T != 0) return hipErrorInvalidValue;
-  const unsigned blocks = (unsigned)((long)(n / CIC_T) * (n / CIC_T) * (n / CIC_T));  // one per tile
+  if (n < 2) return hipErrorInvalidValue;
+  const long tpa = (n + CIC_T - 1) / CIC_T;
+  const unsigned blocks = (unsigned)(tpa * tpa * tpa);  // one per tile
   if (prec == PREC_F32)
     hipLaunchKernelGGL(k_cic<float>, dim3(blocks), dim3(256), 0, s, n, ic, shift, (const float*)psi1, (const float*)psi2,
                        (float*)delta);

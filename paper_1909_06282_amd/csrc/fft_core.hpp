@@ -1,7 +1,8 @@
 // Register/LDS Stockham FFT engine shared by the axis-pass kernels.
 //
-// One transform of length L (a power of two, 4..512, or three times one,
-// 12..768) is carried by L/E threads, each holding E complex values in
+// One transform of length L (a power of two, 4..512, three times one,
+// 12..768, or a length of the table of lengths with a factor 5 or 7) is
+// carried by L/E threads, each holding E complex values in
 // registers.  A stage of radix R (R in {2, 4, 8, 12}, R divides E) runs E/R
 // butterflies per thread; between stages
 // the values go through LDS once (write in the stage's output order, read in
@@ -49,12 +50,50 @@ constexpr int plan_radix_fwd(int L, int s) {
 constexpr int plan_radix(int L, int s, bool inv) {
   return s >= plan_stages(L) ? 0 : (inv ? plan_radix_fwd(L, plan_stages(L) - 1 - s) : plan_radix_fwd(L, s));
 }
-constexpr int plan_first(int L, bool inv) { return plan_radix(L, 0, inv); }
-constexpr int plan_last(int L, bool inv) { return plan_radix(L, plan_stages(L) - 1, inv); }
 // product of the radices of stages 0..s-1
 constexpr int plan_span(int L, int s, bool inv) { return s <= 0 ? 1 : plan_span(L, s - 1, inv) * plan_radix(L, s - 1, inv); }
-// elements per thread: 8 (12 for lengths 3 * 2^k), except the single radix-4 length
-constexpr int elems_per_thread(int L) { return L == 4 ? 4 : (is_pow2(L) ? 8 : 12); }
+
+// Lengths with a factor 5 or 7 (the grids 40, 56, 200, 400, 600 and 700 and
+// their half lengths along z).  E values per thread, T = L/E threads; the
+// stages (radices 2, 3, 4, 5, 7, 8) need not divide E: stage s has L/R_s
+// butterflies, thread t takes butterflies t, t + T, ... (the last round
+// partly), and every stage reads its inputs from and writes its outputs to
+// LDS.  On entry and exit thread t holds elements t + s T (s < E) in
+// registers ("natural" slots); the first stage reads straight from those
+// registers when its radix divides E, and the last stage writes straight
+// into them when its radix divides E.  Forward and inverse use the same
+// stage order.
+struct GenPlan {
+  int L, E, ns, r[4];
+};
+constexpr GenPlan kGenPlans[] = {
+    {20, 5, 2, {5, 4, 0, 0}},   {28, 7, 2, {7, 4, 0, 0}},   {40, 8, 2, {8, 5, 0, 0}},
+    {56, 8, 2, {8, 7, 0, 0}},   {100, 10, 3, {5, 4, 5, 0}}, {200, 10, 3, {5, 8, 5, 0}},
+    {300, 10, 4, {5, 4, 3, 5}}, {350, 10, 4, {5, 7, 2, 5}}, {400, 10, 4, {5, 4, 4, 5}},
+    {600, 10, 4, {5, 8, 3, 5}}, {700, 10, 4, {5, 7, 4, 5}},
+};
+constexpr int kNGenPlans = (int)(sizeof(kGenPlans) / sizeof(kGenPlans[0]));
+constexpr int gen_find(int L, int i = 0) {
+  return i >= kNGenPlans ? -1 : (kGenPlans[i].L == L ? i : gen_find(L, i + 1));
+}
+constexpr bool is_gen(int L) { return gen_find(L) >= 0; }
+constexpr int gen_E(int L) { return kGenPlans[gen_find(L)].E; }
+constexpr int gen_stages(int L) { return kGenPlans[gen_find(L)].ns; }
+constexpr int gen_radix(int L, int s) { return kGenPlans[gen_find(L)].r[s]; }
+constexpr int gen_span(int L, int s) { return s <= 0 ? 1 : gen_span(L, s - 1) * gen_radix(L, s - 1); }
+constexpr bool gen_ok(int L) {
+  bool ok = gen_span(L, gen_stages(L)) == L && L % gen_E(L) == 0;
+  for (int s = 0; s < gen_stages(L); ++s) ok = ok && L % gen_radix(L, s) == 0;
+  return ok;
+}
+
+// Radix pattern of the registers on entry (first) and exit (last): for the
+// lengths with a factor 5 or 7 the natural slots, i.e. the pattern of radix E.
+constexpr int plan_first(int L, bool inv) { return is_gen(L) ? gen_E(L) : plan_radix(L, 0, inv); }
+constexpr int plan_last(int L, bool inv) { return is_gen(L) ? gen_E(L) : plan_radix(L, plan_stages(L) - 1, inv); }
+// elements per thread: 8 (12 for lengths 3 * 2^k), except the single radix-4
+// length; the table above for lengths with a factor 5 or 7
+constexpr int elems_per_thread(int L) { return is_gen(L) ? gen_E(L) : (L == 4 ? 4 : (is_pow2(L) ? 8 : 12)); }
 // the plan multiplies out to L and every radix divides E
 constexpr bool plan_ok(int L) {
   bool ok = plan_span(L, plan_stages(L), false) == L;
@@ -152,9 +191,66 @@ __device__ __forceinline__ void dft12(Cx<T>* x) {
   }
 }
 
+// X_k = sum_m x_m w^(km), w = exp(D 2 pi i / P), P = 5 or 7 (odd prime): the
+// inputs pair up as s_m = x_m + x_{P-m}, d_m = x_m - x_{P-m} (m = 1..(P-1)/2),
+// and for k = 1..(P-1)/2
+//   X_k, X_{P-k} = x_0 + sum_m s_m cos(2 pi km/P) +/- D i sum_m d_m sin(2 pi km/P).
+// cos and sin of 2 pi j / P for P = 5, 7 and 0 <= j < P
+__host__ __device__ constexpr double odd_cos(int P, int j) {
+  return P == 5 ? (j == 0 ? 1.0 : (j == 1 || j == 4) ? 0.30901699437494742410229341718281905886436444230012
+                                                      : -0.80901699437494742410229341718281905886436444230012)
+                : (j == 0 ? 1.0 : (j == 1 || j == 6) ? 0.62348980185873353052500488400423981063227473089640
+                                : (j == 2 || j == 5) ? -0.22252093395631440428890256449679475946635556876452
+                                                     : -0.90096886790241912623610231950744505116591916213188);
+}
+__host__ __device__ constexpr double odd_sin(int P, int j) {
+  return P == 5 ? (j == 0 ? 0.0 : j == 1 ? 0.95105651629515357211643933337938214340569863412575
+                                : j == 2 ? 0.58778525229247312916870595463907276859765243764314
+                                : j == 3 ? -0.58778525229247312916870595463907276859765243764314
+                                         : -0.95105651629515357211643933337938214340569863412575)
+                : (j == 0 ? 0.0 : j == 1 ? 0.78183148246802980870844452667405775023233451870869
+                                : j == 2 ? 0.97492791218182360701813168299393121723278580062000
+                                : j == 3 ? 0.43388373911755812047576833284835875460999072778746
+                                : j == 4 ? -0.43388373911755812047576833284835875460999072778746
+                                : j == 5 ? -0.97492791218182360701813168299393121723278580062000
+                                         : -0.78183148246802980870844452667405775023233451870869);
+}
+
+template <int P, int D, typename T>
+__device__ __forceinline__ void dft_odd(Cx<T>* x) {
+  constexpr int H = (P - 1) / 2;
+  Cx<T> sm[H], dm[H];
+#pragma unroll
+  for (int m = 1; m <= H; ++m) {
+    sm[m - 1] = x[m] + x[P - m];
+    dm[m - 1] = x[m] - x[P - m];
+  }
+  const Cx<T> x0 = x[0];
+  Cx<T> tot = x0;
+#pragma unroll
+  for (int m = 0; m < H; ++m) tot = tot + sm[m];
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    Cx<T> a = x0, b = zero<T>();
+#pragma unroll
+    for (int m = 1; m <= H; ++m) {
+      const int j = (k * m) % P;
+      const T c = T(odd_cos(P, j)), sn = T(odd_sin(P, j));
+      a = mk(a.x + c * sm[m - 1].x, a.y + c * sm[m - 1].y);
+      b = mk(b.x + sn * dm[m - 1].x, b.y + sn * dm[m - 1].y);
+    }
+    const Cx<T> ib = mul_si<D>(b);  // D i b
+    x[k] = a + ib;
+    x[P - k] = a - ib;
+  }
+  x[0] = tot;
+}
+
 template <int R, int D, typename T>
 __device__ __forceinline__ void butterfly(Cx<T>* x) {
-  if constexpr (R == 12) {
+  if constexpr (R == 7 || R == 5) {
+    dft_odd<R, D>(x);
+  } else if constexpr (R == 12) {
     dft12<D>(x);
   } else if constexpr (R == 8) {
     dft8<D>(x);
@@ -163,7 +259,7 @@ __device__ __forceinline__ void butterfly(Cx<T>* x) {
   } else if constexpr (R == 3) {
     dft3<D>(x[0], x[1], x[2]);
   } else {
-    static_assert(R == 2, "radix 2, 3, 4, 8 or 12");
+    static_assert(R == 2, "radix 2, 3, 4, 5, 7, 8 or 12");
     dft2<D>(x[0], x[1]);
   }
 }
@@ -269,6 +365,126 @@ __device__ __forceinline__ void fft_from(Cx<T>* v, int t, const Cx<T>* __restric
   }
 }
 
+// ---- lengths with a factor 5 or 7 ----------------------------------------------
+// One radix-R butterfly b of a stage of span NS (inputs twiddled as in `stage`).
+template <typename T, int L, int R, int NS, int D>
+__device__ __forceinline__ void gen_butterfly(Cx<T>* x, int b, const Cx<T>* __restrict__ tw, int tws) {
+  if constexpr (NS > 1) {
+    const int k = (int)((unsigned)b % (unsigned)NS);
+    const int step = k * (L / (NS * R)) * tws;
+#pragma unroll
+    for (int j = 1; j < R; ++j) {
+      Cx<T> w = tw[step * j];
+      if (D > 0) w.y = -w.y;
+      x[j] = x[j] * w;
+    }
+  }
+  butterfly<R, D>(x);
+}
+
+// The LDS buffer of an exchange, after the synchronisation its writes need
+// (SY_PING: the other buffer, no barrier).
+template <typename T, int SY>
+__device__ __forceinline__ Cx<T>* gen_buffer(Cx<T>* lb, int pingstride, int& ph) {
+  if constexpr (SY == SY_PING) {
+    Cx<T>* b = lb + (ph & 1) * pingstride;
+    ++ph;
+    return b;
+  } else {
+    lds_sync<SY>();
+    return lb;
+  }
+}
+
+// Stage S: its inputs are in `in` (U butterflies x R values); the outputs go
+// to the next stage's inputs through LDS, or (last stage) to the natural
+// slots v.
+template <typename T, int L, int D, int ES, int SY, bool PAD, int S>
+__device__ __forceinline__ void gen_from(Cx<T>* in, Cx<T>* v, int t, const Cx<T>* __restrict__ tw, int tws,
+                                         Cx<T>* lb, int pingstride, int& ph) {
+  constexpr int E = gen_E(L), TP = L / E;
+  constexpr int R = gen_radix(L, S), NS = gen_span(L, S), NB = L / R;
+  constexpr int U = (NB + TP - 1) / TP;
+  constexpr bool FULL = NB % TP == 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int b = t + u * TP;
+    if (FULL || b < NB) gen_butterfly<T, L, R, NS, D>(in + u * R, b, tw, tws);
+  }
+  constexpr bool LAST = S == gen_stages(L) - 1;
+  if constexpr (LAST && E % R == 0) {
+    // outputs b + q L/R, b = t + u TP: natural slot u + q U
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[u + q * U] = in[u * R + q];
+  } else {
+    Cx<T>* buf = gen_buffer<T, SY>(lb, pingstride, ph);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = t + u * TP;
+      if (FULL || b < NB) {
+        const int k = (int)((unsigned)b % (unsigned)NS);
+        const int base = (b - k) * R + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) buf[lds_index<PAD>(base + q * NS) * ES] = in[u * R + q];
+      }
+    }
+    lds_sync<SY>();
+    if constexpr (LAST) {
+#pragma unroll
+      for (int sl = 0; sl < E; ++sl) v[sl] = buf[lds_index<PAD>(t + sl * TP) * ES];
+    } else {
+      constexpr int R2 = gen_radix(L, S + 1), NB2 = L / R2, U2 = (NB2 + TP - 1) / TP;
+      Cx<T> nx[U2 * R2];
+#pragma unroll
+      for (int u = 0; u < U2; ++u) {
+        const int b = t + u * TP;
+        if (NB2 % TP == 0 || b < NB2) {
+#pragma unroll
+          for (int j = 0; j < R2; ++j) nx[u * R2 + j] = buf[lds_index<PAD>(b + j * NB2) * ES];
+        } else {
+#pragma unroll
+          for (int j = 0; j < R2; ++j) nx[u * R2 + j] = zero<T>();
+        }
+      }
+      gen_from<T, L, D, ES, SY, PAD, S + 1>(nx, v, t, tw, tws, lb, pingstride, ph);
+    }
+  }
+}
+
+template <typename T, int L, int D, int ES, int SY, bool PAD>
+__device__ __forceinline__ void gen_fft(Cx<T>* v, int t, const Cx<T>* __restrict__ tw, int tws, Cx<T>* lb,
+                                        int pingstride, int& ph) {
+  constexpr int E = gen_E(L), TP = L / E;
+  constexpr int R = gen_radix(L, 0), NB = L / R, U = (NB + TP - 1) / TP;
+  Cx<T> x[U * R];
+  if constexpr (E % R == 0) {
+    // inputs b + j L/R of butterfly b = t + u TP: natural slot u + j U
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int j = 0; j < R; ++j) x[u * R + j] = v[u + j * U];
+  } else {
+    Cx<T>* buf = gen_buffer<T, SY>(lb, pingstride, ph);
+#pragma unroll
+    for (int sl = 0; sl < E; ++sl) buf[lds_index<PAD>(t + sl * TP) * ES] = v[sl];
+    lds_sync<SY>();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = t + u * TP;
+      if (NB % TP == 0 || b < NB) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) x[u * R + j] = buf[lds_index<PAD>(b + j * NB) * ES];
+      } else {
+#pragma unroll
+        for (int j = 0; j < R; ++j) x[u * R + j] = zero<T>();
+      }
+    }
+  }
+  gen_from<T, L, D, ES, SY, PAD, 0>(x, v, t, tw, tws, lb, pingstride, ph);
+}
+
 // In: slots in the first-stage pattern of the direction's plan.
 // Out: slots in the last-stage pattern.  D = -1 forward, +1 inverse.
 // For SY_PING, lb + pingstride is the second buffer and `phase` persists
@@ -276,12 +492,17 @@ __device__ __forceinline__ void fft_from(Cx<T>* v, int t, const Cx<T>* __restric
 template <typename T, int L, int D, int ES, int SY = SY_BLOCK, bool PAD = false, int E = elems_per_thread(L)>
 __device__ __forceinline__ void fft(Cx<T>* v, int t, const Cx<T>* __restrict__ tw, int tws, Cx<T>* lb,
                                     int pingstride = 0, int* phase = nullptr) {
-  constexpr bool INV = D > 0;
-  static_assert(plan_ok(L) && L % E == 0, "every radix must divide E and the plan must multiply out to L");
   int dummy = 0;
   int& ph = phase ? *phase : dummy;
-  stage<T, L, E, plan_radix(L, 0, INV), 1, D>(v, t, tw, tws);
-  fft_from<T, L, E, D, ES, SY, PAD, 1>(v, t, tw, tws, lb, pingstride, ph);
+  if constexpr (is_gen(L)) {
+    static_assert(gen_ok(L) && E == gen_E(L), "the stages must multiply out to L");
+    gen_fft<T, L, D, ES, SY, PAD>(v, t, tw, tws, lb, pingstride, ph);
+  } else {
+    constexpr bool INV = D > 0;
+    static_assert(plan_ok(L) && L % E == 0, "every radix must divide E and the plan must multiply out to L");
+    stage<T, L, E, plan_radix(L, 0, INV), 1, D>(v, t, tw, tws);
+    fft_from<T, L, E, D, ES, SY, PAD, 1>(v, t, tw, tws, lb, pingstride, ph);
+  }
 }
 
 }  // namespace lpt2

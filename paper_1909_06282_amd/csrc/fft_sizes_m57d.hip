@@ -1,0 +1,7 @@
+// Kernel instantiations for grid sizes: 700 (one translation unit per
+// group, so the build compiles the groups in parallel).
+#include "fft_passes.hpp"
+
+namespace lpt2 {
+LPT2_INSTANTIATE_SIZE(700)
+}  // namespace lpt2

@@ -117,10 +117,13 @@ struct Busy {
   }
 };
 
-// powers of two 8..512, or three times a power of two 24..768
-bool pow2_in_range(int n) {
+// powers of two 8..512, three times a power of two 24..768, and the sizes
+// with a factor 5 or 7: 40, 56, 200, 400, 600, 700 (the paper's boxes of
+// 200-700 Mpc/h at one particle per Mpc/h, Sec. 3)
+bool supported_n(int n) {
   const bool p2 = n > 0 && (n & (n - 1)) == 0, m = n % 3 == 0 && n > 0 && ((n / 3) & (n / 3 - 1)) == 0;
-  return (p2 && n >= 8 && n <= 512) || (m && n >= 24 && n <= 768);
+  const bool q = n == 40 || n == 56 || n == 200 || n == 400 || n == 600 || n == 700;
+  return (p2 && n >= 8 && n <= 512) || (m && n >= 24 && n <= 768) || q;
 }
 
 // sigma8 normalisation: A = sigma8^2 / [(1/2 pi^2) Int k^3 k^ns T^2 W^2(8k) dln k],
@@ -143,8 +146,8 @@ double sigma8_amplitude(const Cosmo& c, double sigma8) {
 }
 
 lpt2_status validate(const lpt2_config& c, std::string& why) {
-  if (!pow2_in_range(c.n)) {
-    why = "n must be a power of two in 8..512 or three times one in 24..768";
+  if (!supported_n(c.n)) {
+    why = "n must be a power of two in 8..512, three times one in 24..768, or one of 40, 56, 200, 400, 600, 700";
     return LPT2_EUNSUPPORTED;
   }
   if (c.precision != LPT2_FP64 && c.precision != LPT2_FP32) {

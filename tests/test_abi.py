@@ -60,7 +60,8 @@ def _plan_status(abi, L, **kw):
 
 
 @pytest.mark.parametrize("kw,status", [
-    (dict(n=40), -2), (dict(n=36), -2), (dict(n=12), -2), (dict(n=1536), -2), (dict(n=4), -2),
+    (dict(n=44), -2), (dict(n=36), -2), (dict(n=12), -2), (dict(n=1536), -2), (dict(n=4), -2),
+    (dict(n=350), -2), (dict(n=800), -2), (dict(n=20), -2),
     (dict(n=1024), -2), (dict(precision=7), -2),
     (dict(box=0.0), -1), (dict(box=-3.0), -1), (dict(gravity=1, fr0_abs=0.0), -1),
     (dict(gravity=1, hs_n=2), -2), (dict(gravity=9), -1), (dict(factorisation=8), -1),

@@ -256,6 +256,74 @@ def test_mixed_radix_384_displacements(prec, tol):
     plan.close()
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_radix5_200_displacements(prec, tol):
+    # the paper's smallest source-ratio box: 200 Mpc/h at one particle per
+    # Mpc/h, |f_R0| = 1e-4, z = 0 (x/y radices 5, 8, 5; z 5, 4, 5)
+    print(f"radix 5: 200^3 {prec}", flush=True)
+    _parity(prec, 1.0, 1, tol, n=200, box=200.0, gravity="fr_hs", fr0_abs=1e-4, factorisation="t1")
+
+
+def test_radix5_400_fp32_displacements():
+    # 400 Mpc/h at 1 Mpc/h (x/y radices 5, 4, 4, 5; z 5, 8, 5)
+    print("radix 5: 400^3 fp32", flush=True)
+    _parity("fp32", 1.0, 1, 1e-5, n=400, box=400.0, gravity="fr_hs", fr0_abs=1e-4, factorisation="t1")
+
+
+@pytest.mark.parametrize("n", [600, 700])
+def test_radix57_fft3d_and_fp32_vs_fp64(n):
+    # 600 (x/y 5, 8, 3, 5; z 5, 4, 3, 5) and 700 (x/y 5, 7, 4, 5; z 5, 7, 2, 5),
+    # the paper's 600 and 700 Mpc/h boxes at 1 Mpc/h: the forward 3D transform
+    # against the oracle's DFT (FP64), then the FP32 displacements against the
+    # FP64 GPU path
+    print(f"radix 5/7: {n}^3 fft3d fp64 vs oracle", flush=True)
+    kw = dict(n=n, box=float(n), gravity="fr_hs", fr0_abs=1e-4, factorisation="t1")
+    w = white_noise(n, 1)
+    plan, cfg = _plan(precision="fp64", **kw)
+    got = plan.fft3d(-1, to_dev(w, torch.float64)).cpu()
+    ref = oracle.fft.rfftn(torch.from_numpy(w))[:, :, : n // 2]
+    err = float((got - ref).abs().max() / ref.abs().max())
+    del got, ref
+    print(f"  fft3d forward: {err:.3e}", flush=True)
+    assert err < 1e-13
+    q1, q2 = plan.displace(1.0, to_dev(w, torch.float64))
+    torch.cuda.synchronize()
+    plan.close()
+    print(f"  fp32 vs fp64 displacements", flush=True)
+    plan, cfg = _plan(precision="fp32", **kw)
+    p1, p2 = plan.displace(1.0, to_dev(w, torch.float32))
+    torch.cuda.synchronize()
+    e1 = float((p1.double() - q1).abs().max() / q1.abs().max())
+    e2 = float((p2.double() - q2).abs().max() / q2.abs().max())
+    et = float(((p1.double() + p2.double()) - (q1 + q2)).abs().max() / (q1 + q2).abs().max())
+    print(f"  psi1 {e1:.3e} psi2 {e2:.3e} total {et:.3e}", flush=True)
+    assert e1 < 1e-5 and e2 < 1e-5 and et < 1e-5
+    plan.close()
+
+
+def test_cic_paint_700_partial_tiles_against_oracle():
+    # 700 is not a multiple of the 8-cell painting tile: the last tile of
+    # every axis is partial.  FP64 paint of the 700^3 FP64 displacements
+    # against the oracle's cloud-in-cell (mass conservation included)
+    print("cic paint 700^3 fp64 vs oracle", flush=True)
+    n = 700
+    plan, cfg = _plan(precision="fp64", n=n, box=float(n), gravity="fr_hs", fr0_abs=1e-5, factorisation="t1")
+    p1, p2 = plan.displace(1.0, to_dev(white_noise(n, 2), torch.float64))
+    d = plan.paint_cic(p1, p2)
+    torch.cuda.synchronize()
+    got = d.cpu()
+    total = float(got.sum())
+    disp = (p1 + p2).cpu()
+    del p1, p2, d
+    plan.close()
+    print("  oracle paint", flush=True)
+    ref = cic.paint(disp, oracle_model(cfg))
+    err = float((got - ref).abs().max())
+    print(f"  max |gpu - oracle| {err:.3e}; sum of delta {total:.3e}", flush=True)
+    assert err < 1e-10
+    assert abs(total) < 1e-6          # every particle's unit mass lands on the mesh
+
+
 def test_backward_384_wide_fan_in_tile_agrees():
     # the adjoint's fan-in y pass with one LDS exchange buffer (widest tile)
     # against the same gradient with the default tiles (pinned to the oracle

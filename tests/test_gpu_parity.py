@@ -48,7 +48,7 @@ def _tables(model, a):
 
 # ---------------------------------------------------------------- FFT
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 24, 48, 96])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 24, 48, 96, 40, 56, 200])
 def test_fft3d_forward_matches_dft(n, prec):
     print(f"fft3d forward n={n} {prec}", flush=True)
     plan, cfg = _plan(precision=prec, n=n, box=2.0 * n)
@@ -60,7 +60,7 @@ def test_fft3d_forward_matches_dft(n, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 24, 48, 96])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 24, 48, 96, 40, 56, 200])
 def test_fft3d_inverse_matches_dft(n, prec):
     print(f"fft3d inverse n={n} {prec}", flush=True)
     plan, cfg = _plan(precision=prec, n=n, box=2.0 * n)
@@ -122,7 +122,17 @@ def test_displace_fr_t1_fp64(n, a):
                     factorisation="t1", nk_growth=64)
 
 
-@pytest.mark.parametrize("n", [8, 32, 128, 96])
+@pytest.mark.parametrize("n", [40, 56])
+@pytest.mark.parametrize("a", [1.0, 0.5])
+def test_displace_radix57_fp64(n, a):
+    # grids with a factor 5 (40: x/y radices 8, 5; z 5, 4) and 7 (56: 8, 7;
+    # z 7, 4), 1 Mpc/h cells as in the paper's source-ratio boxes
+    print(f"displace f(R) T1 fp64 n={n} a={a}", flush=True)
+    _check_displace("fp64", a, F64_TOL, n=n, box=float(n), gravity="fr_hs", fr0_abs=1e-4,
+                    factorisation="t1", nk_growth=64)
+
+
+@pytest.mark.parametrize("n", [8, 32, 128, 96, 40, 56])
 def test_displace_fr_t1_fp32(n):
     print(f"displace f(R) T1 fp32 n={n}", flush=True)
     _check_displace("fp32", 1.0, F32_TOL, n=n, box=2.0 * n, gravity="fr_hs", fr0_abs=1e-5,
