@@ -146,6 +146,33 @@ lpt2_status lpt2_realisation_info(lpt2_plan_t plan, int r, int* n, int* precisio
 lpt2_status lpt2_displace(lpt2_plan_t plan, double a, const void* const* noise,
                           void* const* psi1, void* const* psi2, void* stream);
 
+/* For callers that cannot allocate device memory while they run (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * lpt2_displace of a one-realisation plan (noise, psi1, psi2 are single
+ * device pointers), computed in a static device scratch of the library
+ * instead of the plan's workspace, and allocating nothing: no hipMalloc,
+ * hipFree, event creation or allocating library call on any path.
+ *   - The scratch holds LPT2_NOALLOC_SLOT_BYTES for the 16 half-spectrum
+ *     slots of the chain (16 n^3 reals: FP32 up to n = 96, FP64 up to
+ *     n = 64) and LPT2_NOALLOC_TABLE_BYTES for growth and radial tables.
+ *     A larger grid returns LPT2_EUNSUPPORTED; a plan of several
+ *     realisations returns LPT2_EUNSUPPORTED.
+ *   - Growth tables: the plan's cached tables at a if it has them (from an
+ *     earlier lpt2_displace or lpt2_growth_table at that a), else they are
+ *     rebuilt in the scratch on every call (the growth ODE runs each time).
+ *   - An AUTO plan whose choice at a is not made returns LPT2_ESTATE.
+ *   - Each GPU holds one copy of the scratch from the library's first plan
+ *     on it until the process ends; every call on that GPU shares it and
+ *     overwrites it (nothing in it needs to start at zero).  Calls that
+ *     overlap on one GPU (other streams, other plans, other threads) race on
+ *     the scratch: the caller must order them.
+ *   - Results equal lpt2_displace's (the same kernels and tables); per-launch
+ *     profiling is not recorded. */
+#define LPT2_NOALLOC_SLOT_BYTES ((unsigned long)64 << 20)
+#define LPT2_NOALLOC_TABLE_BYTES ((unsigned long)2 << 20)
+lpt2_status lpt2_displace_noalloc(lpt2_plan_t plan, double a, const void* noise, void* psi1,
+                                  void* psi2, void* stream);
+
 /* Several output times from one source (Sec. 2.4: the factorised D2 makes
  * S(k) independent of a).  psi1 and psi2 at each of a[0..n_a) for every
  * realisation: the full chain runs once at a[0]; for a[1..] only the

@@ -151,6 +151,18 @@ class Plan:
                                            _stream(stream)), self.handle)
         return (psi1[0], psi2[0]) if single else (psi1, psi2)
 
+    def displace_noalloc(self, a: float, noise: torch.Tensor, psi1: torch.Tensor, psi2: torch.Tensor, stream=None):
+        """lpt2_displace_noalloc: lpt2_displace of a one-realisation plan in the
+        library's static scratch (the caller passes the outputs)."""
+        n = self.sizes[0]
+        self._check_field(noise, (n, n, n), "noise")
+        self._check_field(psi1, (3, n, n, n), "psi1")
+        self._check_field(psi2, (3, n, n, n), "psi2")
+        _abi.check(self._lib.lpt2_displace_noalloc(self.handle, float(a), C.c_void_p(noise.data_ptr()),
+                                                   C.c_void_p(psi1.data_ptr()), C.c_void_p(psi2.data_ptr()),
+                                                   _stream(stream)), self.handle)
+        return psi1, psi2
+
     def displace_epochs(self, a_list, noise, psi1=None, psi2=None, stream=None):
         """lpt2_displace_epochs: [(psi1, psi2) per a] (lists per realisation for multi-realisation plans)."""
         single = isinstance(noise, torch.Tensor)

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -16,6 +17,23 @@
 #include "kernels.hpp"
 
 using namespace lpt2;
+
+// Device memory of lpt2_displace_noalloc: the 16 workspace slots of one
+// realisation, then room for the growth and radial tables when the plan has
+// none cached at the requested a.  Every GPU that runs the library holds one
+// copy until the process ends.  Host code never passes the name `scratch`
+// to a kernel or a copy (on the host it is only a stand-in for the symbol):
+// it uses the device address from hipGetSymbolAddress, kept per device in
+// g_scratch_ptr.
+constexpr size_t kScratchSlotBytes = LPT2_NOALLOC_SLOT_BYTES;
+constexpr size_t kScratchTableBytes = LPT2_NOALLOC_TABLE_BYTES;
+static __device__ __align__(256) char scratch[kScratchSlotBytes + kScratchTableBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
 
 namespace {
 
@@ -84,6 +102,7 @@ struct lpt2_plan_s {
   hipEvent_t fork = nullptr;        // several grids: their streams wait on this
   bool graph_mode = false;
   bool capturing = false;            // no per-launch events inside a capture
+  bool quiet = false;                // no per-launch events (the allocation-free entry point)
   hipStream_t cap_stream = nullptr;  // stream the graphs are captured on
   std::vector<GraphEntry> graphs;
 };
@@ -103,6 +122,25 @@ lpt2_status fail(lpt2_plan_t p, lpt2_status st, const std::string& msg) {
 
 lpt2_status hip_fail(lpt2_plan_t p, hipError_t e, const char* what) {
   return fail(p, LPT2_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Device address of `scratch` on the current device: resolved once per device
+// (with that device current) and kept; later calls only look it up.
+lpt2_status scratch_address(lpt2_plan_t p, char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(p, e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(p, LPT2_EDEVICE, "device index beyond the scratch address table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(p, e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(p, LPT2_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = (char*)g_scratch_ptr[dev];
+  return LPT2_OK;
 }
 
 struct Busy {
@@ -213,7 +251,7 @@ template <class F>
 lpt2_status run(lpt2_plan_t p, hipStream_t s, const char* name, double bytes, F&& launch) {
   hipEvent_t a = nullptr, b = nullptr;
   int idx = -1;
-  const bool prof = p->prof && !p->capturing;
+  const bool prof = p->prof && !p->capturing && !p->quiet;
   if (prof) {
     idx = prof_slot(p, name, bytes);
     a = take_event(p);
@@ -233,6 +271,12 @@ lpt2_status run(lpt2_plan_t p, hipStream_t s, const char* name, double bytes, F&
   do {                                                                      \
     lpt2_status st_ = run(p, s, name, (double)(bytes), [&]() { return (expr); }); \
     if (st_ != LPT2_OK) return st_;                                         \
+  } while (0)
+
+#define CHK(x)                      \
+  do {                              \
+    lpt2_status st_ = (x);          \
+    if (st_ != LPT2_OK) return st_; \
   } while (0)
 
 // Destroys the captured graphs (the caller has synchronised the device).
@@ -265,15 +309,15 @@ int auto_lookup(const Grid& g, double a) {
 }
 
 // ---- growth tables -------------------------------------------------------------
-lpt2_status build_tables(lpt2_plan_t p, Grid& g, double a, bool gr, bool unit, hipStream_t s, Tables& out) {
+// Launches the growth-ODE and radial-table kernels of (a, gr, unit) into the
+// memory t already points at: d1n, d2n (nk doubles each) and, unless gr,
+// radial (TAB_ROWS x n2cnt doubles).  Allocates nothing.
+lpt2_status build_tables_into(lpt2_plan_t p, Grid& g, double a, bool gr, bool unit, hipStream_t s, Tables& t) {
   const lpt2_config& cf = g.cfg;
-  Tables t;
   t.a = a;
   t.unit = unit;
+  t.cand = kAutoNone;
   const int nk = cf.nk_growth;
-  hipError_t e = hipMalloc((void**)&t.d1n, sizeof(double) * nk * 2);
-  if (e != hipSuccess) return fail(p, LPT2_ENOMEM, "growth table allocation failed");
-  t.d2n = t.d1n + nk;
   GrowthSetup gs;
   gs.c = g.c;
   if (gr) gs.c.gravity = GRAV_GR;
@@ -309,17 +353,8 @@ lpt2_status build_tables(lpt2_plan_t p, Grid& g, double a, bool gr, bool unit, h
     case LPT2_D2_WINTHER: gs.mode = 1; gs.winther = 1; break;
     default: gs.mode = 1; break;  // T1
   }
-  lpt2_status st = run(p, s, "growth_ode", 0.0, [&]() { return launch_growth(gs, t.d1n, t.d2n, s); });
-  if (st != LPT2_OK) {
-    (void)hipFree(t.d1n);
-    return st;
-  }
+  CHK(run(p, s, "growth_ode", 0.0, [&]() { return launch_growth(gs, t.d1n, t.d2n, s); }));
   if (!gr) {
-    e = hipMalloc((void**)&t.radial, sizeof(double) * TAB_ROWS * g.n2cnt);
-    if (e != hipSuccess) {
-      (void)hipFree(t.d1n);
-      return fail(p, LPT2_ENOMEM, "radial table allocation failed");
-    }
     RadialSetup rs;
     rs.c = g.c;
     rs.n = g.n;
@@ -330,12 +365,29 @@ lpt2_status build_tables(lpt2_plan_t p, Grid& g, double a, bool gr, bool unit, h
     rs.lkmin = g.lkmin;
     rs.lkmax = g.lkmax;
     rs.unit = unit ? 1 : 0;
-    st = run(p, s, "radial_tables", 0.0, [&]() { return launch_radial(rs, t.d1n, t.d2n, t.radial, g.n2cnt, s); });
-    if (st != LPT2_OK) {
+    CHK(run(p, s, "radial_tables", 0.0, [&]() { return launch_radial(rs, t.d1n, t.d2n, t.radial, g.n2cnt, s); }));
+  }
+  return LPT2_OK;
+}
+
+lpt2_status build_tables(lpt2_plan_t p, Grid& g, double a, bool gr, bool unit, hipStream_t s, Tables& out) {
+  Tables t;
+  const int nk = g.cfg.nk_growth;
+  hipError_t e = hipMalloc((void**)&t.d1n, sizeof(double) * nk * 2);
+  if (e != hipSuccess) return fail(p, LPT2_ENOMEM, "growth table allocation failed");
+  t.d2n = t.d1n + nk;
+  if (!gr) {
+    e = hipMalloc((void**)&t.radial, sizeof(double) * TAB_ROWS * g.n2cnt);
+    if (e != hipSuccess) {
       (void)hipFree(t.d1n);
-      (void)hipFree(t.radial);
-      return st;
+      return fail(p, LPT2_ENOMEM, "radial table allocation failed");
     }
+  }
+  lpt2_status st = build_tables_into(p, g, a, gr, unit, s, t);
+  if (st != LPT2_OK) {
+    (void)hipFree(t.d1n);
+    if (t.radial) (void)hipFree(t.radial);
+    return st;
   }
   out = t;
   return LPT2_OK;
@@ -344,6 +396,15 @@ lpt2_status build_tables(lpt2_plan_t p, Grid& g, double a, bool gr, bool unit, h
 void free_tables(Tables& t) {
   (void)hipFree(t.d1n);
   if (t.radial) (void)hipFree(t.radial);
+}
+
+// the cached tables of (a, unit) that are current (for AUTO: built for the
+// candidate chosen at a), or nullptr; no side effects
+const Tables* find_tables(const Grid& g, double a, bool unit) {
+  const int cand = g.cfg.factorisation == LPT2_D2_AUTO ? auto_lookup(g, a) : kAutoNone;
+  for (const Tables& t : g.tables)
+    if (t.a == a && t.unit == unit && t.cand == cand) return &t;
+  return nullptr;
 }
 
 lpt2_status get_tables(lpt2_plan_t p, Grid& g, double a, bool gr, hipStream_t s, Tables** out, bool unit = false) {
@@ -419,12 +480,14 @@ struct Ctx {
   char* base;        // slot 0
   int nr = 1;        // realisations per slot
   char* end = nullptr;  // end of the workspace region this context may use (nullptr: the workspace end)
+  char* lo = nullptr;   // start of that region (nullptr: the workspace start)
   long sstride() const { return (long)nr * g.nnm; }  // complex from one slot to the next
   char* slot(int i) const { return base + (size_t)i * sstride() * cs; }
   size_t cap(const void* ptr) const {  // bytes from a workspace pointer to the region end
     const char* q = (const char*)ptr;
+    const char* b = lo ? lo : p->ws;
     const char* e = end ? end : p->ws + p->ws_bytes;
-    return (q >= p->ws && q < e) ? (size_t)(e - q) : 0;
+    return (q >= b && q < e) ? (size_t)(e - q) : 0;
   }
   size_t field() const { return (size_t)g.n3 * p->es; }  // bytes of one real field
   double fields(double k) const { return k * (double)field() * nr; }  // bytes of k fields of the batch
@@ -547,11 +610,6 @@ YOp yop(int nin, int nout, const int* src, const int* pw) {
   }
   return op;
 }
-#define CHK(x)                      \
-  do {                              \
-    lpt2_status st_ = (x);          \
-    if (st_ != LPT2_OK) return st_; \
-  } while (0)
 
 // psi1, psi2 of the c.nr realisations of a batch (see lpt2_displace).  The
 // k-space factors are split by axis: the radial part (and k_x) is applied in
@@ -1308,6 +1366,13 @@ lpt2_status lpt2_plan(const lpt2_config* cfgs, int n_cfgs, const int* counts, lp
     return fail(nullptr, LPT2_ENOMEM, "binner allocation failed");
   }
   p->bin_out = p->bin_partial + (size_t)BIN_BLOCKS * BIN_MAXBINS * 4;
+  char* scr = nullptr;  // the allocation-free entry point's memory on this device
+  lpt2_status sst = scratch_address(p, &scr);
+  if (sst != LPT2_OK) {
+    const std::string msg = p->err;
+    lpt2_destroy(p);
+    return fail(nullptr, sst, msg);
+  }
   *out = p;
   return LPT2_OK;
 }
@@ -1368,6 +1433,51 @@ lpt2_status lpt2_displace(lpt2_plan_t p, double a, const void* const* noise, voi
   hipError_t e = hipGraphLaunch(ge->exec, s);
   if (e != hipSuccess) return hip_fail(p, e, "graph launch");
   return LPT2_OK;
+}
+
+lpt2_status lpt2_displace_noalloc(lpt2_plan_t p, double a, const void* noise, void* psi1, void* psi2,
+                                  void* stream) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  CHK(check_a(p, a));
+  if (!noise || !psi1 || !psi2) return fail(p, LPT2_EINVAL, "null pointer");
+  if (p->rgrid.size() != 1) return fail(p, LPT2_EUNSUPPORTED, "lpt2_displace_noalloc takes plans of one realisation");
+  Grid& g = p->grids[0];
+  const size_t slots = (size_t)WS_FIELDS * g.n3 * p->es;
+  if (slots > kScratchSlotBytes)
+    return fail(p, LPT2_EUNSUPPORTED, "grid of " + std::to_string(g.n) + "^3 needs " + std::to_string(slots) +
+                                          " bytes of scratch; the static scratch holds " +
+                                          std::to_string(kScratchSlotBytes) + " (FP32 n <= 96, FP64 n <= 64)");
+  const size_t tabs = sizeof(double) * (2 * (size_t)g.cfg.nk_growth + (size_t)TAB_ROWS * g.n2cnt) + 256;
+  if (tabs > kScratchTableBytes) return fail(p, LPT2_EUNSUPPORTED, "growth tables do not fit the static scratch");
+  if (g.cfg.factorisation == LPT2_D2_AUTO && auto_lookup(g, a) == kAutoNone)
+    return fail(p, LPT2_ESTATE, "AUTO factorisation not chosen at this a (run lpt2_displace or "
+                                "lpt2_choose_factorisation first)");
+  char* base = nullptr;
+  CHK(scratch_address(p, &base));
+  hipStream_t s = (hipStream_t)stream;
+  struct Quiet {  // no per-launch profiling events (creating one may allocate)
+    lpt2_plan_t p;
+    explicit Quiet(lpt2_plan_t q) : p(q) { p->quiet = true; }
+    ~Quiet() { p->quiet = false; }
+  } quiet(p);
+  // the plan's tables at a if it has them, else built into the scratch (not kept)
+  Tables local;
+  const Tables* t = find_tables(g, a, false);
+  if (!t) {
+    char* tb = base + kScratchSlotBytes;
+    local.d1n = (double*)tb;
+    local.d2n = local.d1n + g.cfg.nk_growth;
+    local.radial = (double*)(tb + ((sizeof(double) * 2 * (size_t)g.cfg.nk_growth + 255) & ~(size_t)255));
+    CHK(build_tables_into(p, g, a, false, false, s, local));
+    t = &local;
+  }
+  Ctx c{p, g, s, 2 * p->es, base, 1, base + kScratchSlotBytes, base};
+  const void* in[1] = {noise};
+  void* o1[1] = {psi1};
+  void* o2[1] = {psi2};
+  return displace_batch(c, t, in, o1, o2);
 }
 
 lpt2_status lpt2_displace_epochs(lpt2_plan_t p, int n_a, const double* a, const void* const* noise,
