@@ -312,6 +312,15 @@ lpt2_status lpt2_choose_factorisation(lpt2_plan_t plan, double a, const void* no
  * lpt2_factorisation_candidate), or -1 if not chosen yet (or not AUTO). */
 lpt2_status lpt2_auto_choice(lpt2_plan_t plan, int grid, double a, int* candidate);
 
+/* Counts the non-finite values (NaN, +-inf) of a device array of `count`
+ * reals in the plan's precision (a noise field before lpt2_displace, say:
+ * the displacement entry points do not scan their inputs, and one
+ * non-finite noise value spreads through every transform to all outputs).
+ * Synchronises `stream`.  *nonfinite receives the count; the call returns
+ * LPT2_EINVAL when it is not zero and LPT2_OK otherwise. */
+lpt2_status lpt2_check_finite(lpt2_plan_t plan, const void* field, long long count, long long* nonfinite,
+                              void* stream);
+
 /* Vector-Jacobian product of lpt2_displace: given g_psi1[r], g_psi2[r]
  * (device, [3][n][n][n]) returns g_noise[r] = d/dw sum(g_psi1 psi1 + g_psi2 psi2)
  * (device, [n][n][n]).  phi_,ij are recomputed from noise[r], not stored.

@@ -187,13 +187,22 @@ def triangle_ratio(k, m: Model, a: float, ratio: float, theta_deg: float,
     return dd * b / (d1_gr(a, m) ** 2 * (1.0 - c * c))
 
 
-def choose_triangle(kmean, cnt, mean, m: Model, a: float, kcut: float = 0.4, tab=None):
-    """Name of the candidate with the smallest count-weighted squared misfit."""
+def choose_triangle(kmean, cnt, mean, m: Model, a: float, kcut: float = 0.4, tab=None, metric: str = "l2"):
+    """Name of the candidate with the smallest misfit over the populated
+    shells with 0 < k <= kcut, and every candidate's misfit.
+
+    metric "l2" (the reading taken for the choice): count-weighted squared
+    misfit sum_b N_b (mean_b - R_T(k_b))^2; "maxrel" (a second reading, for
+    comparison): max_b |mean_b / R_T(k_b) - 1|.
+    """
     sel = (cnt > 0) & (kmean <= kcut) & (kmean > 0)
     best, best_cost, costs = None, math.inf, {}
     for name, r, th, win in CANDIDATES:
         rt = triangle_ratio(kmean[sel], m, a, r, th, win, tab)
-        cost = float(np.sum(cnt[sel] * (mean[sel] - rt) ** 2))
+        if metric == "maxrel":
+            cost = float(np.max(np.abs(mean[sel] / rt - 1.0)))
+        else:
+            cost = float(np.sum(cnt[sel] * (mean[sel] - rt) ** 2))
         costs[name] = cost
         if cost < best_cost:
             best, best_cost = name, cost

@@ -47,7 +47,7 @@ EXPORTS = [
     "lpt2_strerror", "lpt2_last_error", "lpt2_set_graph", "lpt2_get_tiles", "lpt2_set_tiles",
     "lpt2_tile_options", "lpt2_autotune", "lpt2_factorisation_candidates", "lpt2_factorisation_candidate",
     "lpt2_choose_factorisation", "lpt2_auto_choice", "lpt2_displace_delta", "lpt2_positions",
-    "lpt2_displace_epochs", "lpt2_matter_power", "lpt2_displace_noalloc",
+    "lpt2_displace_epochs", "lpt2_matter_power", "lpt2_displace_noalloc", "lpt2_check_finite",
 ]
 
 _lib = None
@@ -99,6 +99,7 @@ def load() -> C.CDLL:
     L.lpt2_displace_epochs.argtypes = [plan_t, C.c_int, dp, vpp, vpp, vpp, vp]
     L.lpt2_matter_power.argtypes = [plan_t, vp, vp, C.c_int, C.c_int, dp, dp, dp, dp, vp]
     L.lpt2_displace_noalloc.argtypes = [plan_t, C.c_double, vp, vp, vp, vp]
+    L.lpt2_check_finite.argtypes = [plan_t, vp, C.c_longlong, C.POINTER(C.c_longlong), vp]
     L.lpt2_strerror.argtypes = [C.c_int]
     L.lpt2_strerror.restype = C.c_char_p
     L.lpt2_last_error.argtypes = [plan_t]
@@ -109,7 +110,7 @@ def load() -> C.CDLL:
                  "lpt2_profile_get", "lpt2_set_graph", "lpt2_get_tiles", "lpt2_set_tiles", "lpt2_tile_options",
                  "lpt2_autotune", "lpt2_factorisation_candidate", "lpt2_choose_factorisation", "lpt2_auto_choice",
                  "lpt2_displace_delta", "lpt2_positions", "lpt2_displace_epochs",
-                 "lpt2_matter_power", "lpt2_displace_noalloc"):
+                 "lpt2_matter_power", "lpt2_displace_noalloc", "lpt2_check_finite"):
         getattr(L, name).restype = C.c_int
     L.lpt2_realisations.restype = C.c_int
     L.lpt2_profile_count.restype = C.c_int

@@ -327,6 +327,19 @@ class Plan:
                                             _stream(stream)), self.handle)
         return out
 
+    def check_finite(self, x: torch.Tensor, stream=None) -> int:
+        """lpt2_check_finite: the number of non-finite values of a device
+        tensor in the plan's precision (0 if every value is finite)."""
+        if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != self.dtype or not x.is_contiguous():
+            raise ValueError(f"expected a contiguous device tensor of {self.dtype}")
+        cnt = C.c_longlong()
+        st = self._lib.lpt2_check_finite(self.handle, C.c_void_p(x.data_ptr()), x.numel(), C.byref(cnt),
+                                         _stream(stream))
+        if st == _abi.EINVAL and cnt.value > 0:
+            return int(cnt.value)
+        _abi.check(st, self.handle)
+        return int(cnt.value)
+
     def growth_table(self, a: float):
         nk = self.cfgs[0].nk_growth
         k, d1, d2 = np.zeros(nk), np.zeros(nk), np.zeros(nk)

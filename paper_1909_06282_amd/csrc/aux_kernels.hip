@@ -293,29 +293,34 @@ hipError_t launch_bin(int prec, int n, const void* A, size_t a_cap, const void* 
 // Particle p = (ix,iy,iz) moves to u = (ix,iy,iz) + (psi1 + psi2)/cell in
 // cell units; per axis the two nearest nodes get 1 - f and f, f = u - floor(u).
 // ---------------------------------------------------------------------------
-// Scatter: a workgroup takes a Lagrangian tile of CIC_T^3 particles and
-// accumulates their clouds in LDS over the tile's cells plus a halo of
-// CIC_H cells on every side; only the touched cells are then added to the
-// grid, one coalesced global atomic per cell in place of eight per particle
-// (device-scope atomics from every CU on neighbouring cells are what the
-// direct scatter waits on).  A corner outside the halo goes to the grid
-// directly, so any displacement is painted.
-constexpr int CIC_T = 8, CIC_H = 4, CIC_R = CIC_T + 2 * CIC_H;
+// Scatter: a workgroup takes a Lagrangian tile of CIC_TX x CIC_TY x CIC_TZ
+// particles (z fastest: a wavefront's 32 consecutive z particles read 128-byte
+// rows of each displacement component) and accumulates their clouds in LDS
+// over the tile's cells plus a halo of CIC_H cells on every side; only the
+// touched cells are then added to the grid, one coalesced global atomic per
+// cell (about (16 x 16 x 40) / (8 x 8 x 32) = 5 per particle) in place of
+// eight per particle (device-scope atomics from every CU on neighbouring
+// cells are what the direct scatter waits on).  A corner outside the halo
+// goes to the grid directly, so any displacement is painted.  Tiles at the
+// high end of an axis are partial when the tile does not divide n.
+constexpr int CIC_TX = 8, CIC_TY = 8, CIC_TZ = 32, CIC_H = 4;
+constexpr int CIC_RX = CIC_TX + 2 * CIC_H, CIC_RY = CIC_TY + 2 * CIC_H, CIC_RZ = CIC_TZ + 2 * CIC_H;
 template <typename T>
 __global__ __launch_bounds__(256) void k_cic(int n, double inv_cell, double shift, const T* __restrict__ p1,
                                              const T* __restrict__ p2, T* __restrict__ rho) {
-  constexpr int R3 = CIC_R * CIC_R * CIC_R;
+  constexpr int R3 = CIC_RX * CIC_RY * CIC_RZ;
   __shared__ T acc[R3];
   const long n3 = (long)n * n * n;
-  const int tpa = (n + CIC_T - 1) / CIC_T;  // tiles per axis (the last one partial when CIC_T does not divide n)
+  const int tpx = (n + CIC_TX - 1) / CIC_TX, tpy = (n + CIC_TY - 1) / CIC_TY, tpz = (n + CIC_TZ - 1) / CIC_TZ;
   const int bt = blockIdx.x;
-  const int tx = bt / (tpa * tpa), ty = (bt / tpa) % tpa, tz = bt % tpa;
-  const long o0[3] = {(long)tx * CIC_T - CIC_H, (long)ty * CIC_T - CIC_H, (long)tz * CIC_T - CIC_H};
+  const int tx = bt / (tpy * tpz), ty = (bt / tpz) % tpy, tz = bt % tpz;
+  (void)tpx;
+  const long o0[3] = {(long)tx * CIC_TX - CIC_H, (long)ty * CIC_TY - CIC_H, (long)tz * CIC_TZ - CIC_H};
   for (int i = threadIdx.x; i < R3; i += blockDim.x) acc[i] = T(0);
   __syncthreads();
   auto wrap = [n](long g) { long r = g % n; return r < 0 ? r + n : r; };
-  for (int q = threadIdx.x; q < CIC_T * CIC_T * CIC_T; q += blockDim.x) {
-    const int id[3] = {tx * CIC_T + q / (CIC_T * CIC_T), ty * CIC_T + (q / CIC_T) % CIC_T, tz * CIC_T + q % CIC_T};
+  for (int q = threadIdx.x; q < CIC_TX * CIC_TY * CIC_TZ; q += blockDim.x) {
+    const int id[3] = {tx * CIC_TX + q / (CIC_TY * CIC_TZ), ty * CIC_TY + (q / CIC_TZ) % CIC_TY, tz * CIC_TZ + q % CIC_TZ};
     if (id[0] >= n || id[1] >= n || id[2] >= n) continue;  // beyond a partial tile
     const long p = ((long)id[0] * n + id[1]) * n + id[2];
     long i0[3];
@@ -334,8 +339,8 @@ __global__ __launch_bounds__(256) void k_cic(int n, double inv_cell, double shif
       const double w = (ox ? f[0] : 1.0 - f[0]) * (oy ? f[1] : 1.0 - f[1]) * (oz ? f[2] : 1.0 - f[2]);
       const long gx = i0[0] + ox, gy = i0[1] + oy, gz = i0[2] + oz;
       const long rx = gx - o0[0], ry = gy - o0[1], rz = gz - o0[2];
-      if (rx >= 0 && rx < CIC_R && ry >= 0 && ry < CIC_R && rz >= 0 && rz < CIC_R)
-        atomicAdd(&acc[(rx * CIC_R + ry) * CIC_R + rz], (T)w);
+      if (rx >= 0 && rx < CIC_RX && ry >= 0 && ry < CIC_RY && rz >= 0 && rz < CIC_RZ)
+        atomicAdd(&acc[(rx * CIC_RY + ry) * CIC_RZ + rz], (T)w);
       else
         atomicAdd(&rho[(wrap(gx) * n + wrap(gy)) * n + wrap(gz)], (T)w);
     }
@@ -344,7 +349,7 @@ __global__ __launch_bounds__(256) void k_cic(int n, double inv_cell, double shif
   for (int i = threadIdx.x; i < R3; i += blockDim.x) {
     const T v = acc[i];
     if (v != T(0)) {
-      const long gx = o0[0] + i / (CIC_R * CIC_R), gy = o0[1] + (i / CIC_R) % CIC_R, gz = o0[2] + i % CIC_R;
+      const long gx = o0[0] + i / (CIC_RY * CIC_RZ), gy = o0[1] + (i / CIC_RZ) % CIC_RY, gz = o0[2] + i % CIC_RZ;
       atomicAdd(&rho[(wrap(gx) * n + wrap(gy)) * n + wrap(gz)], v);
     }
   }
@@ -386,6 +391,17 @@ __global__ void k_cic_back(int n, double inv_cell, const T* __restrict__ p1, con
   for (int c = 0; c < 3; ++c) gp[c * n3 + p] = (T)(g[c] * inv_cell);
 }
 
+// number of non-finite values (NaN, +-inf) of x[0..count), added to *out
+template <typename T>
+__global__ __launch_bounds__(256) void k_count_nonfinite(const T* __restrict__ x, long count,
+                                                         unsigned long long* __restrict__ out) {
+  unsigned long long c = 0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x)
+    c += __builtin_isfinite(x[i]) ? 0ull : 1ull;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
 template <typename T>
 __global__ void k_fill(T* __restrict__ x, long count, T value) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x) x[i] = value;
@@ -405,6 +421,17 @@ hipError_t launch_fill(int prec, void* x, long count, double value, hipStream_t 
   return hipGetLastError();
 }
 
+hipError_t launch_count_nonfinite(int prec, const void* x, long count, unsigned long long* out, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (!x || !out) return hipErrorInvalidValue;
+  const unsigned blocks = grid_for(count) < 4096 ? grid_for(count) : 4096;
+  if (prec == PREC_F32)
+    hipLaunchKernelGGL(k_count_nonfinite<float>, dim3(blocks), dim3(256), 0, s, (const float*)x, count, out);
+  else
+    hipLaunchKernelGGL(k_count_nonfinite<double>, dim3(blocks), dim3(256), 0, s, (const double*)x, count, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_cic(int prec, int n, double box, const void* psi1, const void* psi2, void* delta, hipStream_t s,
                       double shift) {
   const long n3 = (long)n * n * n;
@@ -412,8 +439,8 @@ hipError_t launch_cic(int prec, int n, double box, const void* psi1, const void*
   if (e != hipSuccess) return e;
   const double ic = n / box;
   if (n < 2) return hipErrorInvalidValue;
-  const long tpa = (n + CIC_T - 1) / CIC_T;
-  const unsigned blocks = (unsigned)(tpa * tpa * tpa);  // one per tile
+  const long tpx = (n + CIC_TX - 1) / CIC_TX, tpy = (n + CIC_TY - 1) / CIC_TY, tpz = (n + CIC_TZ - 1) / CIC_TZ;
+  const unsigned blocks = (unsigned)(tpx * tpy * tpz);  // one per tile
   if (prec == PREC_F32)
     hipLaunchKernelGGL(k_cic<float>, dim3(blocks), dim3(256), 0, s, n, ic, shift, (const float*)psi1, (const float*)psi2,
                        (float*)delta);

@@ -92,6 +92,7 @@ struct lpt2_plan_s {
   size_t ws_bytes = 0;
   double* bin_partial = nullptr;
   double* bin_out = nullptr;
+  unsigned long long* counter = nullptr;  // lpt2_check_finite (inside the binner allocation)
   std::string err;
   std::atomic<int> busy{0};
   bool prof = false;
@@ -118,6 +119,23 @@ lpt2_status fail(lpt2_plan_t p, lpt2_status st, const std::string& msg) {
   else
     g_err = msg;
   return st;
+}
+
+// Device allocations of the library.  For tests of the out-of-memory paths,
+// LPT2_FAIL_ALLOC=k makes the k-th allocation counted from the start of the
+// latest lpt2_plan call on this thread (1-based) fail as if the device were
+// out of memory.
+thread_local long g_alloc_count = 0;
+hipError_t dev_malloc(void** ptr, size_t bytes) {
+  ++g_alloc_count;
+  if (const char* f = std::getenv("LPT2_FAIL_ALLOC")) {
+    const long k = std::atol(f);
+    if (k > 0 && g_alloc_count == k) {
+      *ptr = nullptr;
+      return hipErrorOutOfMemory;
+    }
+  }
+  return hipMalloc(ptr, bytes);
 }
 
 lpt2_status hip_fail(lpt2_plan_t p, hipError_t e, const char* what) {
@@ -373,11 +391,11 @@ lpt2_status build_tables_into(lpt2_plan_t p, Grid& g, double a, bool gr, bool un
 lpt2_status build_tables(lpt2_plan_t p, Grid& g, double a, bool gr, bool unit, hipStream_t s, Tables& out) {
   Tables t;
   const int nk = g.cfg.nk_growth;
-  hipError_t e = hipMalloc((void**)&t.d1n, sizeof(double) * nk * 2);
+  hipError_t e = dev_malloc((void**)&t.d1n, sizeof(double) * nk * 2);
   if (e != hipSuccess) return fail(p, LPT2_ENOMEM, "growth table allocation failed");
   t.d2n = t.d1n + nk;
   if (!gr) {
-    e = hipMalloc((void**)&t.radial, sizeof(double) * TAB_ROWS * g.n2cnt);
+    e = dev_malloc((void**)&t.radial, sizeof(double) * TAB_ROWS * g.n2cnt);
     if (e != hipSuccess) {
       (void)hipFree(t.d1n);
       return fail(p, LPT2_ENOMEM, "radial table allocation failed");
@@ -1249,7 +1267,11 @@ void lpt2_config_default(lpt2_config* c) {
 }
 
 const char* lpt2_strerror(lpt2_status s) {
-  switch (s) {
+  // read as an int: callers through C or ctypes may pass any int, and a value
+  // outside the enumerators must not be loaded as an lpt2_status
+  int v = 0;
+  std::memcpy(&v, &s, sizeof(v));
+  switch (v) {
     case LPT2_OK: return "ok";
     case LPT2_EINVAL: return "invalid argument";
     case LPT2_EUNSUPPORTED: return "unsupported";
@@ -1263,6 +1285,7 @@ const char* lpt2_strerror(lpt2_status s) {
 const char* lpt2_last_error(lpt2_plan_t p) { return p ? p->err.c_str() : g_err.c_str(); }
 
 lpt2_status lpt2_plan(const lpt2_config* cfgs, int n_cfgs, const int* counts, lpt2_plan_t* out) {
+  g_alloc_count = 0;
   if (!out) return fail(nullptr, LPT2_EINVAL, "out is NULL");
   *out = nullptr;
   if (!cfgs || n_cfgs < 1) return fail(nullptr, LPT2_EINVAL, "need at least one configuration");
@@ -1308,7 +1331,7 @@ lpt2_status lpt2_plan(const lpt2_config* cfgs, int n_cfgs, const int* counts, lp
       tw32[2 * m + 1] = (float)sinl(ang);
     }
     const size_t twb = (size_t)2 * g.n * p->es;
-    hipError_t e = hipMalloc(&g.tw, twb);
+    hipError_t e = dev_malloc(&g.tw, twb);
     if (e != hipSuccess) {
       p->grids.push_back(g);
       lpt2_destroy(p);
@@ -1342,7 +1365,7 @@ lpt2_status lpt2_plan(const lpt2_config* cfgs, int n_cfgs, const int* counts, lp
     region_total += per * b;
   }
   p->ws_bytes = std::max(maxf * WS_FIELDS, region_total);
-  hipError_t e = hipMalloc((void**)&p->ws, p->ws_bytes);
+  hipError_t e = dev_malloc((void**)&p->ws, p->ws_bytes);
   if (e != hipSuccess) {
     p->ws = nullptr;
     lpt2_destroy(p);
@@ -1359,13 +1382,15 @@ lpt2_status lpt2_plan(const lpt2_config* cfgs, int n_cfgs, const int* counts, lp
       return fail(nullptr, LPT2_EDEVICE, std::string("stream setup: ") + hipGetErrorString(e));
     }
   }
-  e = hipMalloc((void**)&p->bin_partial, sizeof(double) * (BIN_BLOCKS * (size_t)BIN_MAXBINS * 4 + 4 * BIN_MAXBINS));
+  e = dev_malloc((void**)&p->bin_partial,
+                 sizeof(double) * (BIN_BLOCKS * (size_t)BIN_MAXBINS * 4 + 4 * BIN_MAXBINS) + 256);
   if (e != hipSuccess) {
     p->bin_partial = nullptr;
     lpt2_destroy(p);
     return fail(nullptr, LPT2_ENOMEM, "binner allocation failed");
   }
   p->bin_out = p->bin_partial + (size_t)BIN_BLOCKS * BIN_MAXBINS * 4;
+  p->counter = reinterpret_cast<unsigned long long*>(p->bin_out + 4 * BIN_MAXBINS);
   char* scr = nullptr;  // the allocation-free entry point's memory on this device
   lpt2_status sst = scratch_address(p, &scr);
   if (sst != LPT2_OK) {
@@ -1715,6 +1740,27 @@ lpt2_status lpt2_positions(lpt2_plan_t p, int r, const void* psi1, const void* p
   hipStream_t s = (hipStream_t)stream;
   RUN("positions", 9.0 * (double)g.n3 * p->es,
       launch_positions(p->prec, g.n, g.cfg.box, psi1, psi2, pos, s));
+  return LPT2_OK;
+}
+
+lpt2_status lpt2_check_finite(lpt2_plan_t p, const void* field, long long count, long long* nonfinite,
+                              void* stream) {
+  if (!p) return fail(nullptr, LPT2_EINVAL, "plan is NULL");
+  Busy b(p);
+  if (!b.ok) return fail(p, LPT2_ESTATE, "plan is in use by another call");
+  if (!field || !nonfinite || count < 0) return fail(p, LPT2_EINVAL, "null pointer or negative count");
+  *nonfinite = 0;
+  if (count == 0) return LPT2_OK;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemsetAsync(p->counter, 0, sizeof(unsigned long long), s);
+  if (e != hipSuccess) return hip_fail(p, e, "counter reset");
+  RUN("check_finite", (double)count * p->es, launch_count_nonfinite(p->prec, field, count, p->counter, s));
+  unsigned long long h = 0;
+  e = hipMemcpyAsync(&h, p->counter, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(p, e, "counter readback");
+  *nonfinite = (long long)h;
+  if (h) return fail(p, LPT2_EINVAL, std::to_string(h) + " non-finite values");
   return LPT2_OK;
 }
 

@@ -85,33 +85,103 @@ struct GrowthTri {
   int with_d2;
 };
 
-// y = [D1(k), D1'(k), D1(k1), D1'(k1), D1(k2), D1'(k2), D2, D2']
-__host__ __device__ inline void growth_rhs(const Cosmo& c, const GrowthTri& g, double x, const double* y, double* dy) {
-  const double a = exp(x);
-  const double om = omega_m_a(c, a);
-  const double fr = 2.0 - 1.5 * om, gg = 1.5 * om;
-  const double m2 = (c.gravity == GRAV_FR) ? hs_m2(c, a) : 0.0;
-  const double mk = mu_of(c, g.k, a, m2);
-  dy[0] = y[1];
-  dy[1] = -fr * y[1] + gg * mk * y[0];
-  if (g.with_d2) {
-    dy[2] = y[3];
-    dy[3] = -fr * y[3] + gg * mu_of(c, g.k1, a, m2) * y[2];
-    dy[4] = y[5];
-    dy[5] = -fr * y[5] + gg * mu_of(c, g.k2, a, m2) * y[4];
-    const double src = g.winther ? y[0] * y[0] : y[2] * y[4];
-    const double b = brace(c, g.k, g.k1, g.k2, g.cs, a);
-    dy[6] = y[7];
-    dy[7] = -fr * y[7] + gg * mk * y[6] - gg * src * b / g.bgr;
-  } else {
-    dy[2] = dy[3] = dy[4] = dy[5] = dy[6] = dy[7] = 0.0;
+// The right-hand side of the growth ODEs with everything that does not
+// depend on a or on the state worked out once per node: powers of a from one
+// exponential, one division for Omega_m(a) and one per distinct wavenumber
+// for 1/Pi (the printed forms of mu, the brace and the M_k are algebraically
+// the same expressions; see brace(), mu_of(), hs_m2(), hs_M2()).
+struct GrowthRhs {
+  int gravity;                   // GRAV_*
+  double om, ol, mu0;
+  double m2c, M2c, Gc;           // m^2 = m2c X^3, M2 = M2c X^5 (X = om a^-3 + 4 ol), 4 pi G rho = Gc a^-3
+  double q, q1, q2;              // k^2, k1^2, k2^2
+  double c2, r12, r21, ibgr;     // cos^2, (k1.k2)/k1^2, (k1.k2)/k2^2, 1/(1 - cos^2)
+  bool sym;                      // k1 == k2: D1(k1) = D1(k2) (one pair of states serves both)
+  int winther, with_d2;
+
+  __host__ __device__ void init(const Cosmo& c, const GrowthTri& g) {
+    gravity = c.gravity;
+    om = c.om;
+    ol = c.ol;
+    mu0 = c.mu0;
+    const double x0 = c.om + 4.0 * c.ol, x02 = x0 * x0;
+    m2c = (c.gravity == GRAV_FR) ? 0.5 * (kH0 * kH0 / c.fr0) / x02 : 0.0;
+    M2c = (c.gravity == GRAV_FR) ? 2.25 * (kH0 * kH0 / (c.fr0 * c.fr0)) / (x02 * x02) : 0.0;
+    Gc = 1.5 * kH0 * kH0 * c.om;
+    q = g.k * g.k;
+    q1 = g.k1 * g.k1;
+    q2 = g.k2 * g.k2;
+    c2 = g.cs * g.cs;
+    r12 = g.k1 > 0.0 ? g.cs * g.k2 / g.k1 : 0.0;
+    r21 = g.k2 > 0.0 ? g.cs * g.k1 / g.k2 : 0.0;
+    ibgr = 1.0 / g.bgr;
+    sym = g.k1 == g.k2;
+    winther = g.winther;
+    with_d2 = g.with_d2;
   }
-}
+
+  // y = [D1(k), D1'(k), D1(k1), D1'(k1), D1(k2), D1'(k2), D2, D2'] (D1(k2)
+  // unused and left alone when sym)
+  __host__ __device__ void eval(double x, const double* y, double* dy) const {
+    const double ia = exp(-x), ia2 = ia * ia, ia3 = ia2 * ia;
+    const double m = om * ia3;
+    const double oma = m / (m + ol);
+    const double fr = 2.0 - 1.5 * oma, gg = 1.5 * oma;
+    double mk = 1.0, m1 = 1.0, mm2 = 1.0, b = 1.0;  // b: the brace over (1 - cos^2)
+    if (gravity == GRAV_MUC) {
+      mk = m1 = mm2 = mu0;
+      b = mu0;
+    } else if (gravity == GRAV_FR) {
+      const double X = m + 4.0 * ol, X2 = X * X;
+      const double ms = m2c * X2 * X;
+      const double qa = q * ia2, pk = qa + ms, ipk = 1.0 / pk;
+      mk = 1.0 + (1.0 / 3.0) * qa * ipk;
+      double ip1 = 0.0, ip2 = 0.0;
+      if (with_d2) {
+        const double qa1 = q1 * ia2, p1 = qa1 + ms;
+        ip1 = 1.0 / p1;
+        m1 = 1.0 + (1.0 / 3.0) * qa1 * ip1;
+        if (sym) {
+          ip2 = ip1;
+          mm2 = m1;
+        } else {
+          const double qa2 = q2 * ia2, p2 = qa2 + ms;
+          ip2 = 1.0 / p2;
+          mm2 = 1.0 + (1.0 / 3.0) * qa2 * ip2;
+        }
+        const double G = Gc * ia3, M2 = M2c * X2 * X2 * X;
+        double br = mk - c2 * (m1 + mm2 - mk);
+        br += ms * ipk * (2.0 * c2 * (m1 + mm2 - 2.0) + r12 * (m1 - 1.0) + r21 * (mm2 - 1.0));
+        br -= (2.0 / 27.0) * G * qa * M2 * ipk * ip1 * ip2;
+        b = br * ibgr;
+      }
+    }
+    dy[0] = y[1];
+    dy[1] = -fr * y[1] + gg * mk * y[0];
+    if (with_d2) {
+      dy[2] = y[3];
+      dy[3] = -fr * y[3] + gg * m1 * y[2];
+      if (sym) {
+        dy[4] = dy[5] = 0.0;
+      } else {
+        dy[4] = y[5];
+        dy[5] = -fr * y[5] + gg * mm2 * y[4];
+      }
+      const double src = winther ? y[0] * y[0] : y[2] * (sym ? y[2] : y[4]);
+      dy[6] = y[7];
+      dy[7] = -fr * y[7] + gg * mk * y[6] - gg * src * b;
+    } else {
+      dy[2] = dy[3] = dy[4] = dy[5] = dy[6] = dy[7] = 0.0;
+    }
+  }
+};
 
 // Classical RK4 from ln(a_init) to ln(a) in `steps` equal steps; EdS growing
 // mode start (power-law mode for the constant-mu model).  Returns raw D1, D2.
 __host__ __device__ inline void growth_solve(const Cosmo& c, const GrowthTri& g, double a_init, double a,
                                              int steps, double& d1, double& d2) {
+  GrowthRhs f;
+  f.init(c, g);
   double y[8], k1[8], k2[8], k3[8], k4[8], t[8];
   double dd1, sd1, dd2, sd2;
   if (c.gravity == GRAV_MUC) {
@@ -132,13 +202,13 @@ __host__ __device__ inline void growth_solve(const Cosmo& c, const GrowthTri& g,
   const double h = (x1 - x0) / steps;
   for (int s = 0; s < steps; ++s) {
     const double x = x0 + s * h;
-    growth_rhs(c, g, x, y, k1);
+    f.eval(x, y, k1);
     for (int i = 0; i < 8; ++i) t[i] = y[i] + 0.5 * h * k1[i];
-    growth_rhs(c, g, x + 0.5 * h, t, k2);
+    f.eval(x + 0.5 * h, t, k2);
     for (int i = 0; i < 8; ++i) t[i] = y[i] + 0.5 * h * k2[i];
-    growth_rhs(c, g, x + 0.5 * h, t, k3);
+    f.eval(x + 0.5 * h, t, k3);
     for (int i = 0; i < 8; ++i) t[i] = y[i] + h * k3[i];
-    growth_rhs(c, g, x + h, t, k4);
+    f.eval(x + h, t, k4);
     for (int i = 0; i < 8; ++i) y[i] = y[i] + (h / 6.0) * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
   }
   d1 = y[0];

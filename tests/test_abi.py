@@ -119,6 +119,8 @@ def test_null_plan_on_every_plan_entry_point():
     assert L.lpt2_autotune(None, 1.0, None, None, None, None, None) == E
     assert L.lpt2_profile_enable(None, 1) == E
     assert L.lpt2_profile_reset(None) == E
+    cnt = C.c_longlong()
+    assert L.lpt2_check_finite(None, None, 8, C.byref(cnt), None) == E
     assert L.lpt2_workspace_bytes(None) == 0
     assert L.lpt2_last_error(None)  # the plan-less error text is kept
 

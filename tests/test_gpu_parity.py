@@ -454,6 +454,60 @@ def test_cic_paint_and_transpose_match_oracle(n, stretch):
     assert normwise(g, gref) < 1e-12
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_check_finite_counts_nonfinite_noise(prec):
+    # the displacement entry points do not scan their inputs; lpt2_check_finite
+    # finds the non-finite values of a noise field before it is used
+    print(f"check_finite {prec}", flush=True)
+    from paper_1909_06282_amd import _abi
+    plan, cfg = _plan(precision=prec, n=32, box=64.0)
+    w = to_dev(white_noise(32, 1), cfg.dtype)
+    assert plan.check_finite(w) == 0
+    flat = w.view(-1)
+    flat[5] = float("nan")
+    flat[32 ** 3 - 1] = float("inf")
+    flat[1000] = -float("inf")
+    assert plan.check_finite(w) == 3
+    import ctypes as C
+    L = _abi.load()
+    cnt = C.c_longlong()
+    st = L.lpt2_check_finite(plan.handle, C.c_void_p(w.data_ptr()), w.numel(), C.byref(cnt), None)
+    assert st == _abi.EINVAL and cnt.value == 3
+    assert b"non-finite" in L.lpt2_last_error(plan.handle)
+    plan.close()
+
+
+def test_allocation_failures_return_enomem_and_leave_no_state(monkeypatch):
+    # LPT2_FAIL_ALLOC=k fails the k-th device allocation after lpt2_plan
+    # starts: the plan's own allocations (twiddles, workspace, binner), then
+    # the growth tables of the first displacement; each gives LPT2_ENOMEM,
+    # releases what was allocated, and a plan made afterwards works
+    print("allocation failure injection", flush=True)
+    from paper_1909_06282_amd import LPT2Error, _abi
+    kw = dict(precision="fp64", n=16, box=32.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=32)
+    w = to_dev(white_noise(16, 2), torch.float64)
+    for k in (1, 2, 3):
+        monkeypatch.setenv("LPT2_FAIL_ALLOC", str(k))
+        with pytest.raises(LPT2Error) as ei:
+            _plan(**kw)
+        assert ei.value.status == _abi.ENOMEM, (k, str(ei.value))
+    for k in (4, 5):                     # growth table, then radial table of the first call at a
+        monkeypatch.setenv("LPT2_FAIL_ALLOC", str(k))
+        plan, cfg = _plan(**kw)
+        with pytest.raises(LPT2Error) as ei:
+            plan.displace(1.0, w)
+        assert ei.value.status == _abi.ENOMEM, (k, str(ei.value))
+        plan.close()
+    monkeypatch.delenv("LPT2_FAIL_ALLOC")
+    plan, cfg = _plan(**kw)
+    p1, p2 = plan.displace(1.0, w)
+    torch.cuda.synchronize()
+    m = oracle_model(cfg)
+    r1, r2 = fields.displace(white_noise(16, 2), m, 1.0, _tables(m, 1.0))
+    assert normwise(p1, r1) < F64_TOL and normwise(p2, r2) < F64_TOL
+    plan.close()
+
+
 def test_invalid_arguments_raise():
     from paper_1909_06282_amd import LPT2Error
     plan, cfg = _plan(n=8, box=16.0)

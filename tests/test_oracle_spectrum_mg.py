@@ -138,6 +138,24 @@ def test_fr_source_ratio_close_to_t1():
     assert best == "T1"
 
 
+def test_second_misfit_metric_picks_a_curve_that_matches_exactly():
+    # the max-relative-deviation reading of the choice: bin means set to one
+    # candidate's analytic ratio (with a few empty and out-of-range shells)
+    # give that candidate a zero misfit and select it; the count-weighted
+    # reading agrees
+    m = oracle.Model(n=64, box=256.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk=64, ode_steps=128)
+    a = 0.8
+    tab = growth.tables(m.with_(factorisation="eds"), a)
+    km = np.linspace(0.02, 0.6, 30)
+    cnt = np.full(30, 500.0)
+    cnt[[3, 17]] = 0.0
+    for name, r, th, win in mgsource.CANDIDATES:
+        mean = mgsource.triangle_ratio(km, m, a, r, th, win, tab=tab)
+        for metric in ("maxrel", "l2"):
+            best, costs = mgsource.choose_triangle(km, cnt, mean, m, a, 0.4, tab, metric=metric)
+            assert best == name and costs[name] < 1e-12, (name, metric)
+
+
 def test_matter_power_parseval_on_band_limited_field():
     # sum over shells of count * mean / V equals the variance of a field whose
     # modes all lie inside the shells (a few plane waves below k_Nyq)
