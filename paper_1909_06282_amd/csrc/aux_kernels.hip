@@ -9,43 +9,91 @@
 namespace lpt2 {
 
 // ---------------------------------------------------------------------------
-// growth ODE: one thread per k node (eq. d1, eq. full-d2), one more for the
-// k = 0 normalisation run to a = 1; then normalised D1, D2 tables.
+// growth ODE (eq. d1, eq. full-d2): one wave per block, lanes 0..62 each run
+// one k node's chain and lane 63 the k = 0 normalisation run to a = 1 (every
+// block repeats it, so no block waits on another); then normalised D1, D2
+// tables.  The factors that depend on a alone (GrowthAFac) are the same for
+// every node: the wave works them out for GROWTH_CHUNK steps at a time into
+// LDS (the three times of each RK4 step, for the nodes' time grid and for the
+// normalisation's), and each chain keeps only its own arithmetic, with 1/Pi
+// from the hardware reciprocal and two Newton steps.  A single wave per block
+// leaves the whole register file to the chain's 48-double state.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_growth(GrowthSetup g, double* __restrict__ d1n, double* __restrict__ d2n) {
-  __shared__ double s1[1024], s2[1024];
-  const int i = threadIdx.x;
-  if (i < g.nk) {
+constexpr int GROWTH_CHUNK = 128;
+constexpr int GROWTH_NODES = 63;  // nodes per block; the last lane normalises
+
+// 1/p: v_rcp_f64 refined by two Newton steps (each squares the relative
+// error; the result is within an ulp or two of the rounded quotient)
+__device__ __forceinline__ double fast_rcp(double p) {
+  double r = __builtin_amdgcn_rcp(p);
+  double e = fma(-p, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-p, r, 1.0);
+  return fma(r, e, r);
+}
+
+__global__ __launch_bounds__(64) void k_growth(GrowthSetup g, double* __restrict__ d1n, double* __restrict__ d2n) {
+  __shared__ GrowthAFac tab[2][3 * GROWTH_CHUNK];  // [0]: to g.a, [1]: the normalisation run to a = 1
+  const int lane = threadIdx.x;
+  const bool norm = lane == GROWTH_NODES;
+  const int i = blockIdx.x * GROWTH_NODES + lane;
+  const bool node = !norm && i < g.nk;
+  GrowthTri tri;
+  if (node) {
     const double k = exp(g.lkmin + (g.lkmax - g.lkmin) * (double)i / (double)(g.nk - 1));
-    GrowthTri tri;
     tri.k = k;
     triangle(k, g.ratio, g.cs, tri.k1, tri.k2);
     tri.cs = g.cs;
     tri.bgr = 1.0 - g.cs * g.cs;
     tri.winther = g.winther;
     tri.with_d2 = (g.mode == 1);
-    double d1, d2;
-    growth_solve(g.c, tri, g.a_init, g.a, g.steps, d1, d2);
-    s1[i] = d1;
-    s2[i] = d2;
-  } else if (i == g.nk) {
-    GrowthTri tri;
+  } else {
     tri.k = tri.k1 = tri.k2 = 0.0;
     tri.cs = 0.0;
     tri.bgr = 1.0;
     tri.winther = 0;
     tri.with_d2 = 0;
-    double d1, d2;
-    growth_solve(g.c, tri, g.a_init, 1.0, g.steps, d1, d2);
-    s1[i] = d1;
   }
-  __syncthreads();
-  if (i < g.nk) {
-    const double norm = s1[g.nk];
-    const double d1v = s1[i] / norm;
+  GrowthRhs f;
+  f.init(g.c, tri);
+  double y[8], k1[8], k2[8], k3[8], k4[8], t[8];
+  growth_start(g.c, g.a_init, y);
+  const double x0 = log(g.a_init);
+  const double h0 = (log(g.a) - x0) / g.steps, h1 = (0.0 - x0) / g.steps;
+  const double h = norm ? h1 : h0;
+  const GrowthAFac* my = tab[norm ? 1 : 0];
+  for (int s0 = 0; s0 < g.steps; s0 += GROWTH_CHUNK) {
+    const int ns = g.steps - s0 < GROWTH_CHUNK ? g.steps - s0 : GROWTH_CHUNK;
+    __syncthreads();  // the previous chunk's factors are no longer read
+    for (int e = lane; e < 2 * 3 * ns; e += blockDim.x) {
+      const int grid = e / (3 * ns), r = e % (3 * ns), st = r / 3, kind = r % 3;
+      const double hh = grid ? h1 : h0;
+      double x = x0 + (s0 + st) * hh;
+      if (kind == 1) x = x + 0.5 * hh;
+      if (kind == 2) x = x + hh;
+      tab[grid][r] = f.afac(x);
+    }
+    __syncthreads();
+    if (node || norm) {
+      for (int st = 0; st < ns; ++st) {
+        const GrowthAFac a0 = my[3 * st], am = my[3 * st + 1], a1 = my[3 * st + 2];
+        f.eval_at(a0, y, k1, fast_rcp);
+        for (int q = 0; q < 8; ++q) t[q] = y[q] + 0.5 * h * k1[q];
+        f.eval_at(am, t, k2, fast_rcp);
+        for (int q = 0; q < 8; ++q) t[q] = y[q] + 0.5 * h * k2[q];
+        f.eval_at(am, t, k3, fast_rcp);
+        for (int q = 0; q < 8; ++q) t[q] = y[q] + h * k3[q];
+        f.eval_at(a1, t, k4, fast_rcp);
+        for (int q = 0; q < 8; ++q) y[q] = y[q] + (h / 6.0) * (k1[q] + 2.0 * k2[q] + 2.0 * k3[q] + k4[q]);
+      }
+    }
+  }
+  const double nrm = __shfl(y[0], GROWTH_NODES);
+  if (node) {
+    const double d1v = y[0] / nrm;
     double d2v;
     if (g.mode == 1)
-      d2v = s2[i] / (norm * norm);
+      d2v = y[6] / (nrm * nrm);
     else if (g.mode == 0)
       d2v = -3.0 / 7.0 * d1v * d1v;
     else
@@ -57,7 +105,7 @@ __global__ __launch_bounds__(1024) void k_growth(GrowthSetup g, double* __restri
 
 hipError_t launch_growth(const GrowthSetup& g, double* d1n, double* d2n, hipStream_t s) {
   if (g.nk < 2 || g.nk > 1023) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_growth, dim3(1), dim3(((g.nk + 1 + 63) / 64) * 64), 0, s, g, d1n, d2n);
+  hipLaunchKernelGGL(k_growth, dim3((g.nk + GROWTH_NODES - 1) / GROWTH_NODES), dim3(64), 0, s, g, d1n, d2n);
   return hipGetLastError();
 }
 

@@ -85,11 +85,21 @@ struct GrowthTri {
   int with_d2;
 };
 
+// The factors of the growth ODEs that depend on the time x = ln a only.
+struct GrowthAFac {
+  double ia2;   // a^-2
+  double fr;    // 2 - 1.5 Omega_m(a)
+  double gg;    // 1.5 Omega_m(a)
+  double ms;    // m^2(a) (f(R))
+  double gm2;   // (2/27) 4 pi G rho(a) M2(a) (f(R))
+};
+
 // The right-hand side of the growth ODEs with everything that does not
-// depend on a or on the state worked out once per node: powers of a from one
-// exponential, one division for Omega_m(a) and one per distinct wavenumber
-// for 1/Pi (the printed forms of mu, the brace and the M_k are algebraically
-// the same expressions; see brace(), mu_of(), hs_m2(), hs_M2()).
+// depend on a or on the state worked out once per node, and everything that
+// depends on a alone in GrowthAFac (powers of a from one exponential, one
+// division for Omega_m(a)); one reciprocal per distinct wavenumber for 1/Pi
+// remains.  The printed forms of mu, the brace and the M_k are algebraically
+// the same expressions (see brace(), mu_of(), hs_m2(), hs_M2()).
 struct GrowthRhs {
   int gravity;                   // GRAV_*
   double om, ol, mu0;
@@ -120,69 +130,73 @@ struct GrowthRhs {
     with_d2 = g.with_d2;
   }
 
-  // y = [D1(k), D1'(k), D1(k1), D1'(k1), D1(k2), D1'(k2), D2, D2'] (D1(k2)
-  // unused and left alone when sym)
-  __host__ __device__ void eval(double x, const double* y, double* dy) const {
+  __host__ __device__ GrowthAFac afac(double x) const {
+    GrowthAFac f;
     const double ia = exp(-x), ia2 = ia * ia, ia3 = ia2 * ia;
     const double m = om * ia3;
     const double oma = m / (m + ol);
-    const double fr = 2.0 - 1.5 * oma, gg = 1.5 * oma;
+    f.ia2 = ia2;
+    f.fr = 2.0 - 1.5 * oma;
+    f.gg = 1.5 * oma;
+    const double X = m + 4.0 * ol, X2 = X * X;
+    f.ms = m2c * X2 * X;
+    f.gm2 = (2.0 / 27.0) * (Gc * ia3) * (M2c * X2 * X2 * X);
+    return f;
+  }
+
+  // y = [D1(k), D1'(k), D1(k1), D1'(k1), D1(k2), D1'(k2), D2, D2'].  When
+  // sym, the D1(k2) pair takes the same operations on the same values as the
+  // D1(k1) pair and stays equal to it bit for bit.  rcp(p) returns 1/p.
+  template <class Rcp>
+  __host__ __device__ void eval_at(const GrowthAFac& af, const double* y, double* dy, Rcp rcp) const {
+    const double fr = af.fr, gg = af.gg;
     double mk = 1.0, m1 = 1.0, mm2 = 1.0, b = 1.0;  // b: the brace over (1 - cos^2)
     if (gravity == GRAV_MUC) {
       mk = m1 = mm2 = mu0;
       b = mu0;
     } else if (gravity == GRAV_FR) {
-      const double X = m + 4.0 * ol, X2 = X * X;
-      const double ms = m2c * X2 * X;
-      const double qa = q * ia2, pk = qa + ms, ipk = 1.0 / pk;
+      const double ms = af.ms;
+      const double qa = q * af.ia2, ipk = rcp(qa + ms);
       mk = 1.0 + (1.0 / 3.0) * qa * ipk;
-      double ip1 = 0.0, ip2 = 0.0;
       if (with_d2) {
-        const double qa1 = q1 * ia2, p1 = qa1 + ms;
-        ip1 = 1.0 / p1;
+        const double qa1 = q1 * af.ia2, ip1 = rcp(qa1 + ms);
         m1 = 1.0 + (1.0 / 3.0) * qa1 * ip1;
+        double ip2 = ip1;
         if (sym) {
-          ip2 = ip1;
           mm2 = m1;
         } else {
-          const double qa2 = q2 * ia2, p2 = qa2 + ms;
-          ip2 = 1.0 / p2;
+          const double qa2 = q2 * af.ia2;
+          ip2 = rcp(qa2 + ms);
           mm2 = 1.0 + (1.0 / 3.0) * qa2 * ip2;
         }
-        const double G = Gc * ia3, M2 = M2c * X2 * X2 * X;
         double br = mk - c2 * (m1 + mm2 - mk);
         br += ms * ipk * (2.0 * c2 * (m1 + mm2 - 2.0) + r12 * (m1 - 1.0) + r21 * (mm2 - 1.0));
-        br -= (2.0 / 27.0) * G * qa * M2 * ipk * ip1 * ip2;
+        br -= af.gm2 * qa * ipk * ip1 * ip2;
         b = br * ibgr;
       }
     }
+    // every row runs in every case (no branch, so the state stays in
+    // registers): without D2 the rows past the first pair see the initial
+    // coefficients, stay finite and are never read
+    const double p00 = y[0] * y[0], p24 = y[2] * y[4];
+    const double src = winther ? p00 : p24;
     dy[0] = y[1];
     dy[1] = -fr * y[1] + gg * mk * y[0];
-    if (with_d2) {
-      dy[2] = y[3];
-      dy[3] = -fr * y[3] + gg * m1 * y[2];
-      if (sym) {
-        dy[4] = dy[5] = 0.0;
-      } else {
-        dy[4] = y[5];
-        dy[5] = -fr * y[5] + gg * mm2 * y[4];
-      }
-      const double src = winther ? y[0] * y[0] : y[2] * (sym ? y[2] : y[4]);
-      dy[6] = y[7];
-      dy[7] = -fr * y[7] + gg * mk * y[6] - gg * src * b;
-    } else {
-      dy[2] = dy[3] = dy[4] = dy[5] = dy[6] = dy[7] = 0.0;
-    }
+    dy[2] = y[3];
+    dy[3] = -fr * y[3] + gg * m1 * y[2];
+    dy[4] = y[5];
+    dy[5] = -fr * y[5] + gg * mm2 * y[4];
+    dy[6] = y[7];
+    dy[7] = -fr * y[7] + gg * mk * y[6] - gg * src * b;
+  }
+
+  __host__ __device__ void eval(double x, const double* y, double* dy) const {
+    eval_at(afac(x), y, dy, [](double p) { return 1.0 / p; });
   }
 };
 
-// Classical RK4 from ln(a_init) to ln(a) in `steps` equal steps; EdS growing
-// mode start (power-law mode for the constant-mu model).  Returns raw D1, D2.
-__host__ __device__ inline void growth_solve(const Cosmo& c, const GrowthTri& g, double a_init, double a,
-                                             int steps, double& d1, double& d2) {
-  GrowthRhs f;
-  f.init(c, g);
-  double y[8], k1[8], k2[8], k3[8], k4[8], t[8];
+// EdS growing-mode start of the state (power-law mode for the constant-mu model).
+__host__ __device__ inline void growth_start(const Cosmo& c, double a_init, double* y) {
   double dd1, sd1, dd2, sd2;
   if (c.gravity == GRAV_MUC) {
     const double p = (-0.5 + sqrt(0.25 + 6.0 * c.mu0)) / 2.0;
@@ -198,6 +212,16 @@ __host__ __device__ inline void growth_solve(const Cosmo& c, const GrowthTri& g,
     sd2 = -6.0 / 7.0 * a_init * a_init;
   }
   y[0] = dd1; y[1] = sd1; y[2] = dd1; y[3] = sd1; y[4] = dd1; y[5] = sd1; y[6] = dd2; y[7] = sd2;
+}
+
+// Classical RK4 from ln(a_init) to ln(a) in `steps` equal steps from the
+// growing-mode start.  Returns raw D1, D2.
+__host__ __device__ inline void growth_solve(const Cosmo& c, const GrowthTri& g, double a_init, double a,
+                                             int steps, double& d1, double& d2) {
+  GrowthRhs f;
+  f.init(c, g);
+  double y[8], k1[8], k2[8], k3[8], k4[8], t[8];
+  growth_start(c, a_init, y);
   const double x0 = log(a_init), x1 = log(a);
   const double h = (x1 - x0) / steps;
   for (int s = 0; s < steps; ++s) {
