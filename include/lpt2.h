@@ -338,8 +338,11 @@ lpt2_status lpt2_backward(lpt2_plan_t plan, double a, const void* const* noise,
  * each particle carries the mass of its Lagrangian cell); painting the
  * particles on the mesh is the discrete form used here, which conserves the
  * total mass exactly.  delta is a device [n][n][n] output.  Non-finite
- * positions are not painted.  The float atomics make the summation order,
- * and so the last bits, vary from run to run. */
+ * positions, and positions more than 2^30 cells from the origin, are not
+ * painted.  FP32 plans sum each workgroup's weights in 32-bit fixed point
+ * (step 1/(2^22 - 1), exact integer sums) and add them to delta with float
+ * atomics; FP64 plans use double atomics throughout.  The order of the
+ * atomics, and so the last bits of delta, vary from run to run. */
 lpt2_status lpt2_paint_cic(lpt2_plan_t plan, const void* psi1, const void* psi2,
                            void* delta, void* stream);
 
