@@ -42,16 +42,63 @@ COPY_BYTES = 512 << 20
 # the device code of the displacement passes (the counter readings describe
 # those kernels; the host code, the growth and table kernels, the binner and
 # the CIC kernels are left out)
-KERNEL_SOURCES = ("cx.hpp", "fft_core.hpp", "fft_kernels.hip", "kernels.hpp")
+KERNEL_SOURCES = ("cx.hpp", "fft_core.hpp", "fft_passes.hpp", "fft_kernels.hip", "kernels.hpp")
+
+# the access shape of every launch site of the step: (kind, fields read,
+# fields written, tile kind); kind 0 = contiguous lines (z passes), 1 = y
+# columns, 2 = x columns; tile kind = the plan's tile list entry (0 single
+# y FFT, 1 fused y, 2 fused x) that sets the site's columns per tile
+PATTERNS = {
+    "z_r2c_noise": (0, 1, 1, None), "y_fwd_noise": (1, 1, 1, 0), "x_fused_psi1_phi": (2, 1, 5, 2),
+    "y_inv_psi1_phi": (1, 5, 9, 1), "z_c2r_psi1": (0, 3, 3, None), "z_fused_source": (0, 6, 1, None),
+    "y_fwd_source": (1, 1, 1, 0), "x_fused_psi2": (2, 1, 2, 2), "y_inv_psi2": (1, 2, 3, 1), "z_c2r_psi2": (0, 3, 3, None),
+}
 
 
 def source_hash() -> str:
     """Hash of the device code of the displacement passes."""
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    names = list(KERNEL_SOURCES) + sorted(f for f in os.listdir(CSRC) if f.startswith("fft_sizes_"))
+    for f in names:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
+
+
+def pattern_rates(n: int, tiles, reps: int = 10):
+    """Bandwidth of each launch site's access pattern with no arithmetic
+    (libmembench.so: the same fields read and written, the same line or
+    column-tile shape, `tiles` = the plan's [single y, fused y, fused x]
+    widths): a reference for how far each site is from its traffic's rate."""
+    import ctypes as C
+    path = os.path.join(ROOT, "paper_1909_06282_amd", "libmembench.so")
+    if not os.path.exists(path):
+        return None
+    lib = C.CDLL(path)
+    lib.membench_pattern.argtypes = [C.c_int] * 6 + [C.POINTER(C.c_double)]
+    lib.membench_pattern.restype = C.c_int
+    out = {}
+    for site, (kind, nin, nout, tk) in PATTERNS.items():
+        ms = C.c_double(0.0)
+        w = tiles[tk] if tk is not None else 16
+        st = lib.membench_pattern(kind, n, nin, nout, w, reps, C.byref(ms))
+        if st != 0 or ms.value <= 0:
+            out[site] = {"status": st}
+            continue
+        by = (nin + nout) * float(n) ** 3 * 4
+        out[site] = {"kind": ("lines", "y columns", "x columns")[kind], "reads": nin, "writes": nout,
+                     "columns_per_tile": w if tk is not None else None,
+                     "ms": round(ms.value, 4), "GBps": round(by / (ms.value / 1e3) / 1e9, 1)}
+    return out
+
+
+def attach_patterns(breakdown: dict, pat) -> None:
+    """pattern_GBps / of_pattern beside each site's measured rate."""
+    for site, c in (pat or {}).items():
+        b = breakdown.get(site)
+        if b and b.get("GBps") and c.get("GBps"):
+            b["pattern_GBps"] = c["GBps"]
+            b["of_pattern"] = round(b["GBps"] / c["GBps"], 3)
 
 
 def traffic_for(kernel: str, launches_bytes: float):
@@ -66,6 +113,64 @@ def traffic_for(kernel: str, launches_bytes: float):
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
+
+
+def traffic_from(fetch_dir: str, write_dir: str) -> None:
+    """Write profiles/traffic.json and print its table from two rocprofv3 --pmc
+    runs of this script (FETCH_SIZE, then WRITE_SIZE; default workload,
+    --no-extra).  Each counter is scaled by its reading for the 512 MiB device
+    copy of the same run; per launch site the median over the profiled steps."""
+    import csv
+    import glob
+    import statistics
+
+    def load(d, counter):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not f:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        rows = {}
+        with open(f[0]) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    rows.setdefault(int(r["Dispatch_Id"]), (r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
+        return [rows[k] for k in sorted(rows)]
+
+    def per_site(disp):
+        steps = []
+        i = 0
+        while i + len(PATTERNS) <= len(disp):
+            if f"k_zr2c<float, {N}>" in disp[i][0]:
+                steps.append(disp[i:i + len(PATTERNS)])
+                i += len(PATTERNS)
+            else:
+                i += 1
+        return {site: statistics.median(st[k][2] for st in steps) for k, site in enumerate(PATTERNS)}, len(steps)
+
+    def scale(disp):
+        copies = [d for d in disp if "copyBuffer" in d[0]]
+        big = max(d[1] for d in copies)
+        return COPY_BYTES / (statistics.median(d[2] for d in copies if d[1] == big) * 1024)
+
+    fd, wd = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    (fsite, nf), (wsite, nw) = per_site(fd), per_site(wd)
+    fs, ws = scale(fd), scale(wd)
+    kern = {}
+    print("| launch site | fetched GB | written GB | total GB | algorithmic GB | total / algorithmic |")
+    print("|---|---:|---:|---:|---:|---:|")
+    for site, (kind, nin, nout) in PATTERNS.items():
+        fb, wb = fsite[site] * 1024 * fs, wsite[site] * 1024 * ws
+        alg = (nin + nout) * float(N) ** 3 * 4
+        kern[site] = {"fetch_bytes": round(fb), "write_bytes": round(wb), "bytes_per_launch": round(fb + wb)}
+        print(f"| {site} | {fb / 1e9:.3f} | {wb / 1e9:.3f} | {(fb + wb) / 1e9:.3f} | {alg / 1e9:.3f} | {(fb + wb) / alg:.3f} |")
+    rec = {"source_hash": source_hash(), "workload": f"{N}^3 f(R) FP32 displacement (bench.py default workload)",
+           "counter_runs": [fetch_dir, write_dir], "steps": [nf, nw],
+           "scale": {"copy_bytes": COPY_BYTES, "fetch_scale": fs, "write_scale": ws,
+                     "note": "bytes = counter KiB * 1024 * scale; scale = known copy bytes / counter reading "
+                             "of the 512 MiB device copy in the same run"},
+           "kernels": kern}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(f"source hash {rec['source_hash']}; steps {nf}/{nw}; scales {fs:.4f} {ws:.4f}")
 
 
 def cpu_baseline(fr0: float, a: float, seed: int):
@@ -230,9 +335,10 @@ def epochs_timing(reps: int):
             "value": len(a_list) * float(N) ** 3 / (t_ep / 1e3), "unit": "grid-cells/s"}
 
 
-def grid_timing(n: int, box: float, reps: int, note: str):
+def grid_timing(n: int, box: float, reps: int, note: str, with_patterns: bool = False):
     """One realisation of the paper's own grid sizes: n^3 in `box` Mpc/h,
-    |f_R0| = 1e-5, z = 0, FP32, with the per-kernel breakdown."""
+    |f_R0| = 1e-5, z = 0, FP32, with the per-kernel breakdown (and the
+    memory-pattern reference of each site, where libmembench has the size)."""
     import numpy as np
     import torch
     from paper_1909_06282_amd import LPT2Config, Plan
@@ -248,16 +354,25 @@ def grid_timing(n: int, box: float, reps: int, note: str):
     prof = {name: {"avg_ms": round(t / max(l, 1), 4), "GBps": round(by / (t / l / 1e3) / 1e9, 1) if t > 0 else None}
             for name, l, t, by in plan.profile()}
     plan.profile_enable(False)
+    tiles = plan.get_tiles(0)
     plan.close()
-    return {"workload": f"{n}^3 (L={box:g} Mpc/h) |f_R0|=1e-5 z=0 FP32 seed 1 ({note})", "ms_per_step": round(ms, 3),
-            "value": float(n) ** 3 / (ms / 1e3), "unit": "grid-cells/s",
-            "algorithmic_GBps": round(53 * 4 * float(n) ** 3 / (ms / 1e3) / 1e9, 1), "kernels": prof}
+    del w, p1, p2
+    torch.cuda.empty_cache()
+    rec = {"workload": f"{n}^3 (L={box:g} Mpc/h) |f_R0|=1e-5 z=0 FP32 seed 1 ({note})", "ms_per_step": round(ms, 3),
+           "value": float(n) ** 3 / (ms / 1e3), "unit": "grid-cells/s",
+           "algorithmic_GBps": round(53 * 4 * float(n) ** 3 / (ms / 1e3) / 1e9, 1), "tiles": tiles, "kernels": prof}
+    if with_patterns:
+        pat = pattern_rates(n, tiles)
+        if pat:
+            attach_patterns(prof, pat)
+            rec["patterns"] = pat
+    return rec
 
 
-def grid768_timing(reps: int):
+def grid768_timing(reps: int, with_patterns: bool = True):
     """The paper's N-body grid: 768^3 in 750 Mpc/h (three times a power of
     two: a radix-12 first stage)."""
-    return grid_timing(768, 750.0, reps, "radix-12 first stage")
+    return grid_timing(768, 750.0, reps, "radix-12 first stage", with_patterns)
 
 
 def grid700_timing(reps: int):
@@ -313,14 +428,19 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the adjoint and factorisation-choice timings")
     ap.add_argument("--only-768", action="store_true",
                     help="time only the 768^3 grid (for profiling it) and print its record")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
     ap.add_argument("--only-700", action="store_true",
                     help="time only the 700^3 grid (for profiling it) and print its record")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from(*args.traffic_from)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.only_768:
-        print(json.dumps({"grid_768": grid768_timing(max(1, args.steps))}), flush=True)
+        print(json.dumps({"grid_768": grid768_timing(max(1, args.steps), with_patterns=False)}), flush=True)
         return
     if args.only_700:
         print(json.dumps({"grid_700": grid700_timing(max(1, args.steps))}), flush=True)
@@ -373,6 +493,7 @@ def main():
             k[0] += launches
             k[1] += ms
         p.profile_enable(False)
+    tiles512 = plans[FR0S[0]].get_tiles(0)
     ms_per_step = wall * 1e3 / args.steps
     cells = float(N) ** 3
     value = cells * args.steps / wall
@@ -461,6 +582,15 @@ def main():
         "torch_copy_GBps": round(copy_gbs, 1),
         "source_hash": source_hash(),
     }
+    if not args.no_extra:
+        pat = pattern_rates(N, tiles512)
+        if pat:
+            attach_patterns(breakdown, pat)
+            c = pat.get(dname, {})
+            if c.get("GBps"):
+                out["roofline"]["pattern_GBps"] = c["GBps"]
+                out["roofline"]["frac_of_pattern"] = round(achieved / c["GBps"], 4)
+            out["patterns"] = pat
     out.update(extra)
     if not args.no_batch:
         out["batched"] = batched(max(8, args.steps // 2), 3)

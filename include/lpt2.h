@@ -79,7 +79,8 @@ typedef enum {
 typedef enum { LPT2_SPEC_POWER = 0, LPT2_SPEC_RATIO = 1 } lpt2_spec_quantity;
 
 typedef struct {
-  int    n;               /* cells per side: 2^k in 8..512 or 3*2^k in 24..768 */
+  int    n;               /* cells per side: 2^k in 8..512, 3*2^k in 24..768,
+                             or 40, 56, 200, 400, 600, 700 (radices 5, 7)    */
   double box;             /* side length L in Mpc/h, > 0                       */
   double omega_m;         /* flat background: Omega_L = 1 - Omega_m           */
   double h;               /* BBKS shape parameter Gamma = Omega_m h            */
@@ -105,8 +106,9 @@ void lpt2_config_default(lpt2_config* cfg);
 
 /* Create a plan for n_cfgs grid configurations; counts[i] >= 1 realisations
  * of cfgs[i] (counts may be NULL for one realisation each).  Validates every
- * field on the host before any device work: n neither a power of two in
- * 8..512 nor three times one in 24..768 (the paper's 768^3 grid),
+ * field on the host before any device work: n none of a power of two in
+ * 8..512, three times one in 24..768 (the paper's 768^3 grid) or 40, 56,
+ * 200, 400, 600, 700 (the paper's 200-700 Mpc/h boxes at 1 Mpc/h),
  * hs_n != 1 or an unknown precision -> LPT2_EUNSUPPORTED; box <= 0,
  * fr0_abs <= 0 for f(R), bad growth grid or null out -> LPT2_EINVAL.
  * Allocates, on the current device, the twiddles and a workspace of 16

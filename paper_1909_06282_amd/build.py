@@ -1,4 +1,5 @@
-"""Build liblpt2.so (the HIP kernels for gfx950 and the C ABI) in-tree with hipcc.
+"""Build liblpt2.so (the HIP kernels for gfx950 and the C ABI) in-tree with hipcc,
+and libmembench.so (memory-pattern ceilings for bench.py).
 
     python -m paper_1909_06282_amd.build        # or __graft_entry__.build()
 
@@ -59,6 +60,13 @@ def build(verbose: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, OUT)
+    # the memory-pattern ceilings that bench.py reports beside the passes
+    mb = os.path.join(HERE, "libmembench.so")
+    cmd = [hipcc(), "-x", "hip", *FLAGS, "-shared", os.path.join(CSRC, "membench.hip"), "-o", mb + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"membench build failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(mb + ".tmp", mb)
     if verbose:
         print(f"built {OUT}")
     return OUT

@@ -512,7 +512,10 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_colfft(Cx<T>* __r
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
   const int c = threadIdx.x % C::W, t = threadIdx.x / C::W;
-  const long bx = block_index<C>();
+  // one workgroup per tile: each XCD takes one contiguous range of tiles at
+  // every width (measured at n = 512, 128-byte rows: 10% faster than the
+  // plain order, which the persistent passes keep there)
+  const long bx = xcd_block(blockIdx.x, gridDim.x);
   const long plane = bx / bpp;
   const int col = (int)(bx % bpp) * C::W + c;
   const bool act = col < ncols;

@@ -159,3 +159,22 @@ def test_backward_refuses_lists_shorter_than_the_plan_before_any_device_work():
                  ([w, w], [g, g], [g, g], [w])):
         with pytest.raises(ValueError, match="realisations"):
             p.backward(1.0, *args)
+
+
+def test_membench_loads_and_rejects_bad_patterns_without_a_device():
+    # the memory-pattern companion library bench.py reports beside the passes:
+    # argument checks happen before any HIP call
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_1909_06282_amd", "libmembench.so")
+    if not os.path.exists(path):
+        pytest.skip("libmembench.so not built")
+    L = C.CDLL(path)
+    L.membench_pattern.argtypes = [C.c_int] * 6 + [C.POINTER(C.c_double)]
+    L.membench_pattern.restype = C.c_int
+    ms = C.c_double(0.0)
+    assert L.membench_pattern(3, 512, 1, 1, 16, 1, C.byref(ms)) == -1      # unknown kind
+    assert L.membench_pattern(2, 256, 1, 5, 16, 1, C.byref(ms)) == -1      # strided kinds: n = 512, 768
+    assert L.membench_pattern(1, 512, 1, 1, 12, 1, C.byref(ms)) == -1      # width not offered
+    assert L.membench_pattern(0, 512, 9, 8, 16, 1, C.byref(ms)) == -1      # more than 16 fields
+    assert L.membench_pattern(0, 512, 1, 1, 16, 0, C.byref(ms)) == -1      # no timed launch
+    assert L.membench_pattern(0, 512, 1, 1, 16, 1, None) == -1

@@ -236,15 +236,18 @@ def test_c4_batched_graph_fp32_vs_fp64_and_oracle(tmp_path):
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
 def test_mixed_radix_384_displacements(prec, tol):
     # three times a power of two: 384^3 (L = 768, 2 Mpc/h cells) against the
-    # oracle, with the default tiles and with the widest fused-y tile (whose
-    # two LDS exchange buffers do not fit: one buffer, block-wide barriers)
+    # oracle, with the default tiles, the widest fused-y tile (whose two LDS
+    # exchange buffers do not fit: one buffer, block-wide barriers) and the
+    # narrowest column and x tiles (64-byte rows, XCD-contiguous tiles); the
+    # adjoint with the last two changes at once against the default tiles
     print(f"mixed radix 384^3 {prec}", flush=True)
     plan, cfg = _plan(precision=prec, n=384, box=768.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1")
     m = oracle_model(cfg)
     w = white_noise(cfg.n, 2)
     r1, r2 = _oracle_displace(m, w, 2, 1.0)
-    wide = max(plan.tile_options(0)[1])
-    for tiles in ([0, 0, 0], [0, wide, 0]):
+    opts = plan.tile_options(0)
+    alt = [min(opts[0]), max(opts[1]), min(opts[2])]
+    for tiles in ([0, 0, 0], [0, alt[1], 0], [alt[0], 0, alt[2]]):
         plan.set_tiles(0, tiles)
         p1, p2 = plan.displace(1.0, to_dev(w, cfg.dtype))
         torch.cuda.synchronize()
@@ -253,6 +256,18 @@ def test_mixed_radix_384_displacements(prec, tol):
         e1, e2, et = normwise(g1, r1), normwise(g2, r2), normwise(g1 + g2, r1 + r2)
         print(f"  tiles {plan.get_tiles(0)}: psi1 {e1:.3e} psi2 {e2:.3e} total {et:.3e}", flush=True)
         assert e1 < tol and e2 < tol and et < tol
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    gp1 = torch.randn((3, 384, 384, 384), generator=gen, device="cuda", dtype=cfg.dtype)
+    gp2 = torch.randn((3, 384, 384, 384), generator=gen, device="cuda", dtype=cfg.dtype)
+    wd = to_dev(w, cfg.dtype)
+    plan.set_tiles(0, [0, 0, 0])
+    b0 = plan.backward(1.0, wd, gp1, gp2).clone()
+    plan.set_tiles(0, alt)
+    b1 = plan.backward(1.0, wd, gp1, gp2)
+    torch.cuda.synchronize()
+    eb = float((b1.double() - b0.double()).norm() / b0.double().norm())
+    print(f"  adjoint tiles {alt} vs default: relative L2 {eb:.3e}", flush=True)
+    assert eb < (1e-12 if prec == "fp64" else 1e-5)
     plan.close()
 
 
