@@ -157,7 +157,7 @@ def traffic_from(fetch_dir: str, write_dir: str) -> None:
     kern = {}
     print("| launch site | fetched GB | written GB | total GB | algorithmic GB | total / algorithmic |")
     print("|---|---:|---:|---:|---:|---:|")
-    for site, (kind, nin, nout) in PATTERNS.items():
+    for site, (kind, nin, nout, _) in PATTERNS.items():
         fb, wb = fsite[site] * 1024 * fs, wsite[site] * 1024 * ws
         alg = (nin + nout) * float(N) ** 3 * 4
         kern[site] = {"fetch_bytes": round(fb), "write_bytes": round(wb), "bytes_per_launch": round(fb + wb)}
