@@ -28,8 +28,8 @@ Modules
     adjoint    -- gradient of the CIC loss w.r.t. the white noise (autograd)
 
 Readings of passages that are garbled, silent or inconsistent are listed in
-the docstrings of the functions that take them.  Parity-unpinned functions
-say so in their docstrings.
+the docstrings of the functions that take them.  Every function is pinned
+by a test of tests/test_oracle_*.py; none is left "parity unpinned".
 """
 from .model import Model, preset
 from . import fft, cosmology, growth, fields, spectrum, mgsource, cic, adjoint

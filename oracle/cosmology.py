@@ -83,11 +83,10 @@ def big_pi(k, a, m: Model):
 
 
 def bbks_transfer(k, m: Model):
-    """BBKS (Bardeen, Bond, Kaiser & Szalay 1986) transfer function, q = k/Gamma.
-
-    Parity unpinned: no tabulated values of the fit are available here; only
-    its limits (T -> 1 as k -> 0) and its use inside the sigma8 integral are
-    checked."""
+    """BBKS (Bardeen, Bond, Kaiser & Szalay 1986) transfer function, q = k/Gamma,
+    Gamma = Omega_m h.  Pinned to its power-series expansions at small and at
+    large q (exact rational series arithmetic in the tests) and to its
+    dependence on k through k/Gamma."""
     k = np.asarray(k, dtype=np.float64)
     q = k / (m.omega_m * m.h)
     x = 2.34 * q

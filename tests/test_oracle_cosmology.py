@@ -20,8 +20,9 @@ retyped):
     Omega_m(a); and with the published values of G and of the critical
     density, 4 pi G rho_crit Omega_m a^-3 / c^2 in (h/Mpc)^2.
 
-The BBKS transfer function has no pin beyond its limits (no tabulated values
-are available here): parity unpinned.
+  * the BBKS transfer function: its power series at small q and in 1/q at
+    large q, computed with exact rational series arithmetic (see below), and
+    its dependence on k through k/(Omega_m h).
 """
 import math
 
@@ -153,3 +154,70 @@ def test_four_pi_g_rho_from_published_constants():
     want = 4.0 * math.pi * g_newton * rho_crit * m.omega_m / C_KMS ** 2     # (h/Mpc)^2 at a = 1
     assert abs(float(cz.four_pi_g_rho(1.0, m)) / want - 1) < 1e-5
     assert abs(float(cz.four_pi_g_rho(0.5, m)) / (want * 8.0) - 1) < 1e-5
+
+
+# ---- BBKS transfer function: expansions at both ends -------------------------
+# T(q) = [ln(1 + 2.34 q)/(2.34 q)] B(q)^(-1/4), B = 1 + 3.89 q + (16.1 q)^2 +
+# (5.46 q)^3 + (6.71 q)^4, q = k/Gamma, Gamma = Omega_m h.  The pins below
+# expand it as power series with exact rational arithmetic -- the logarithm's
+# Taylor series, series products, and a power of a series by Miller's
+# recurrence (P = B^alpha  =>  B P' = alpha B' P) -- an evaluation route that
+# shares nothing with the oracle's closed-form expression.  Every term of B
+# enters a coefficient of order <= 4 at small q, and the two top terms enter
+# the large-q expansion, so a dropped or mistyped term, a wrong exponent or a
+# wrong argument fails one of them.
+from fractions import Fraction as Fr
+
+BBKS = (Fr("3.89"), Fr("16.1") ** 2, Fr("5.46") ** 3, Fr("6.71") ** 4)
+
+
+def _ser_mul(a, b, n):
+    return [sum(a[i] * b[k - i] for i in range(k + 1)) for k in range(n)]
+
+
+def _ser_pow(b, alpha, n):
+    """b[0] = 1: coefficients of b(x)^alpha by Miller's recurrence."""
+    p = [Fr(1)] + [Fr(0)] * (n - 1)
+    for k in range(1, n):
+        p[k] = sum((alpha * j - (k - j)) * b[j] * p[k - j] for j in range(1, min(k, len(b) - 1) + 1)) / k
+    return p
+
+
+def _bbks_small_q_series(n):
+    c = Fr("2.34")
+    a = [(-c) ** k / (k + 1) for k in range(n)]                 # ln(1 + c q)/(c q)
+    b = [Fr(1), *BBKS] + [Fr(0)] * n
+    return _ser_mul(a, _ser_pow(b, Fr(-1, 4), n), n)
+
+
+@pytest.mark.parametrize("q", [1e-3, 2e-3, 5e-3, 1e-2])
+def test_bbks_matches_its_small_q_expansion(q):
+    coeffs = _bbks_small_q_series(16)
+    series = sum(float(cf) * q ** k for k, cf in enumerate(coeffs))
+    m = oracle.Model(omega_m=0.3, h=0.7)
+    t = float(cz.bbks_transfer(q * m.omega_m * m.h, m))
+    # the first orders by hand: c1 = -(2.34/2 + 3.89/4)
+    assert abs(float(coeffs[1]) + (1.17 + 0.9725)) < 1e-15
+    assert abs(t - series) < 1e-13
+
+
+@pytest.mark.parametrize("q", [1e3, 1e4, 1e5])
+def test_bbks_matches_its_large_q_expansion(q):
+    # T (2.34 q)(6.71 q) / ln(1 + 2.34 q) = (B/(6.71 q)^4)^(-1/4), a series in 1/q
+    b0, b1, b2, b3 = Fr(1), *[BBKS[2] / BBKS[3], BBKS[1] / BBKS[3], BBKS[0] / BBKS[3]]
+    d = [b0, b1, b2, b3, 1 / BBKS[3]]
+    coeffs = _ser_pow(d, Fr(-1, 4), 12)
+    series = sum(float(cf) * (1.0 / q) ** k for k, cf in enumerate(coeffs))
+    m = oracle.Model(omega_m=0.3, h=0.7)
+    t = float(cz.bbks_transfer(q * m.omega_m * m.h, m))
+    got = t * (2.34 * q) * (6.71 * q) / math.log1p(2.34 * q)
+    assert abs(got - series) < 1e-12
+
+
+def test_bbks_depends_on_k_through_k_over_omega_m_h():
+    # Gamma = Omega_m h: scaling h and k together leaves T unchanged
+    k = np.geomspace(1e-4, 10.0, 41)
+    base = cz.bbks_transfer(k, oracle.Model(omega_m=0.3, h=0.7))
+    scaled = cz.bbks_transfer(1.37 * k, oracle.Model(omega_m=0.3, h=0.7 * 1.37))
+    assert np.max(np.abs(scaled / base - 1)) < 1e-13
+    assert float(cz.bbks_transfer(0.0, oracle.Model())) == 1.0
