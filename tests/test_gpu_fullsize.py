@@ -361,7 +361,8 @@ def test_backward_384_wide_fan_in_tile_agrees():
 
 
 @pytest.mark.skipif(os.environ.get("LPT2_ORACLE_768") != "1",
-                    reason="the 768^3 FP64 oracle takes minutes and ~100 GB of host memory; set LPT2_ORACLE_768=1")
+                    reason="the 768^3 FP64 oracle takes two minutes on 16 threads and ~100 GB of host memory; "
+                           "set LPT2_ORACLE_768=1")
 def test_mixed_radix_768_fp64_vs_oracle():
     print("mixed radix 768^3 fp64 vs oracle", flush=True)
     _parity("fp64", 1.0, 1, 1e-12, n=768, box=750.0, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1")
