@@ -838,7 +838,9 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xadj(const Cx<T>*
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
   int phase = 0;
-  const int c = threadIdx.x % C::W, t = threadIdx.x / C::W;
+  using XP = XPair<C::L, C::E, C::RLF, C::TPC, C::W>;  // paired gathers, as in k_xdisp
+  const int c = threadIdx.x % C::W, t = XP::t_of(threadIdx.x / C::W);
+  const bool rev = XP::rev(threadIdx.x / C::W);
   constexpr long NTILES = (NCOL + C::W - 1) / C::W;
   Cx<T> v[C::E], acc[C::E], pf[C::E];
   Cx<T> rf[PAIR ? C::E : 1];
@@ -864,7 +866,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xadj(const Cx<T>*
     const int n2yz = my * my + iz * iz;
 #pragma unroll
     for (int sl = 0; sl < C::E; ++sl) {
-      const int ix = slot_elem<C::L, C::E, C::RLF>(t, sl);
+      const int ix = slot_elem<C::L, C::E, C::RLF>(t, rev ? C::E - 1 - sl : sl);
       const int mx = ix < N / 2 ? ix : ix - N;
       const int n2 = mx * mx + n2yz;
       const bool keep = keep_y && ix != N / 2 && n2 != 0;
@@ -888,10 +890,12 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xadj(const Cx<T>*
       for (int sl = 0; sl < C::E; ++sl) {
         const int ix = slot_elem<C::L, C::E, C::RLF>(t, sl);
         T r;
-        if constexpr (PAIR)
-          r = second ? rf[sl].y : rf[sl].x;
-        else
-          r = rq[sl];
+        if constexpr (PAIR) {
+          const Cx<T> rr = rev ? rf[C::E - 1 - sl] : rf[sl];
+          r = second ? rr.y : rr.x;
+        } else {
+          r = rev ? rq[C::E - 1 - sl] : rq[sl];
+        }
         const T f = mpow<T>(ix < N / 2 ? ix : ix - N, pw) * r;
         // MODE 0: -f v (U) or -i f v (V); MODE 1: i f v
         const Cx<T> u = PAIR ? (second ? mk(v[sl].y * f, -v[sl].x * f) : mk(-v[sl].x * f, -v[sl].y * f))
