@@ -407,8 +407,9 @@ def test_triangle_ratio_matches_oracle():
 
 
 # ---------------------------------------------------------------- adjoint and CIC
-@pytest.mark.parametrize("n", [8, 16, 48, 96])
+@pytest.mark.parametrize("n", [8, 16, 48, 64, 96])
 def test_backward_matches_oracle_autograd(n):
+    # 64: the x passes' paired radial gathers (last radix 8) are on
     print(f"backward fp64 n={n}", flush=True)
     plan, cfg = _plan(n=n, box=2.0 * n, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=64)
     m = oracle_model(cfg)
@@ -420,7 +421,7 @@ def test_backward_matches_oracle_autograd(n):
     assert normwise(got, ref) < 1e-11
 
 
-@pytest.mark.parametrize("n", [32, 48])
+@pytest.mark.parametrize("n", [32, 48, 64])
 def test_backward_fp32_matches_fp64_gpu(n):
     print(f"backward fp32 n={n}", flush=True)
     kw = dict(n=n, box=2.0 * n, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=64)
