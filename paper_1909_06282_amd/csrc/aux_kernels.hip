@@ -551,9 +551,14 @@ hipError_t launch_fill(int prec, void* x, long count, double value, hipStream_t 
   return hipGetLastError();
 }
 
+__global__ void k_zero_u64(unsigned long long* out) { *out = 0ull; }
+
+// *out is set to zero first (by a kernel, so that a caller may capture the
+// sequence in a graph), then the count is added to it
 hipError_t launch_count_nonfinite(int prec, const void* x, long count, unsigned long long* out, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
   if (!x || !out) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, out);
+  if (count <= 0) return hipGetLastError();
   const unsigned blocks = grid_for(count) < 4096 ? grid_for(count) : 4096;
   if (prec == PREC_F32)
     hipLaunchKernelGGL(k_count_nonfinite<float>, dim3(blocks), dim3(256), 0, s, (const float*)x, count, out);

@@ -181,7 +181,8 @@ hipError_t launch_positions(int prec, int n, double box, const void* psi1, const
 hipError_t launch_cic_back(int prec, int n, double box, const void* psi1, const void* psi2, const void* gdelta,
                            void* gpsi, hipStream_t s);
 
-// *out += number of non-finite values of x[0..count) (x holds count reals)
+// *out = number of non-finite values of x[0..count) (x holds count reals),
+// zeroed by a kernel first
 hipError_t launch_count_nonfinite(int prec, const void* x, long count, unsigned long long* out, hipStream_t s);
 // x[0..count) = value (x must hold count values)
 hipError_t launch_fill(int prec, void* x, long count, double value, hipStream_t s);

@@ -1752,11 +1752,9 @@ lpt2_status lpt2_check_finite(lpt2_plan_t p, const void* field, long long count,
   *nonfinite = 0;
   if (count == 0) return LPT2_OK;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = hipMemsetAsync(p->counter, 0, sizeof(unsigned long long), s);
-  if (e != hipSuccess) return hip_fail(p, e, "counter reset");
   RUN("check_finite", (double)count * p->es, launch_count_nonfinite(p->prec, field, count, p->counter, s));
   unsigned long long h = 0;
-  e = hipMemcpyAsync(&h, p->counter, sizeof(h), hipMemcpyDeviceToHost, s);
+  hipError_t e = hipMemcpyAsync(&h, p->counter, sizeof(h), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(p, e, "counter readback");
   *nonfinite = (long long)h;
