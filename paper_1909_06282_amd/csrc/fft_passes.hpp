@@ -512,10 +512,10 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_colfft(Cx<T>* __r
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
   const int c = threadIdx.x % C::W, t = threadIdx.x / C::W;
-  // one workgroup per tile: each XCD takes one contiguous range of tiles at
-  // every width (measured at n = 512, 128-byte rows: 10% faster than the
-  // plain order, which the persistent passes keep there)
-  const long bx = xcd_block(blockIdx.x, gridDim.x);
+  // (XCD-contiguous tiles at 128-byte rows make this pass 10% faster at
+  // n = 512 but the x pass that reads its output 5% slower: the plain order
+  // is kept there)
+  const long bx = block_index<C>();
   const long plane = bx / bpp;
   const int col = (int)(bx % bpp) * C::W + c;
   const bool act = col < ncols;
