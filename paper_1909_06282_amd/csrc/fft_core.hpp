@@ -107,6 +107,23 @@ __device__ __forceinline__ int slot_elem(int t, int slot) {
   return t + (slot / R) * (L / E) + (slot % R) * (L / R);
 }
 
+// v, passed through an empty asm statement when ON.  Everything a transform
+// derives from its thread index (element indices, LDS addresses, mode
+// factors: a few operations per slot) is then worked out again from the
+// opaque copy instead of being hoisted out of a rolled loop and held in VGPRs
+// across it.  Measured per kernel: for the lengths with a factor 5 or 7 the
+// fused y passes stop spilling (n = 700 FP32: 128 VGPRs + 80 bytes of scratch
+// per lane -> 95 VGPRs, the nine-output pass 7.7 -> 5.9 ms) and the source
+// pass drops from 227 to 145 VGPRs (3% faster); for the power-of-two and
+// 3 * 2^k lengths the recomputation costs more than the registers it frees
+// (n = 512: the source pass at 116 instead of 162 VGPRs, four waves per SIMD
+// instead of three, still ran 9% slower), so there it stays off.
+template <bool ON>
+__device__ __forceinline__ int opaque_if(int v) {
+  if constexpr (ON) asm volatile("" : "+v"(v));
+  return v;
+}
+
 // ---- butterflies (in place, natural order in and out) -----------------------
 template <int D, typename T>
 __device__ __forceinline__ void dft4(Cx<T>& x0, Cx<T>& x1, Cx<T>& x2, Cx<T>& x3) {

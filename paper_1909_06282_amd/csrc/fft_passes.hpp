@@ -236,9 +236,10 @@ __global__ __launch_bounds__(256) void k_zsource(const Cx<T>* __restrict__ phi, 
   load_field(0);
 #pragma unroll 1
   for (int f = 0; f < 6; ++f) {
-    c2r_prepare_regs<T, N>(raw, zp.r[f], v, t, lb, stw);
+    const int tf = opaque_if<is_gen(C::L)>(t);
+    c2r_prepare_regs<T, N>(raw, zp.r[f], v, tf, lb, stw);
     if (PF && f < 5) load_field(f + 1);
-    fft<T, C::L, +1, 1, C::SY, true>(v, t, stw, 2, lb);
+    fft<T, C::L, +1, 1, C::SY, true>(v, tf, stw, 2, lb);
     if (f == 0) {
 #pragma unroll
       for (int i = 0; i < C::E; ++i) a[i] = v[i];
@@ -552,7 +553,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
   int phase = 0;
-  const int c = threadIdx.x % C::W, t = threadIdx.x / C::W;
+  const int c = threadIdx.x % C::W, t0 = threadIdx.x / C::W;
   // tile -> (x plane, z column); returns the element offset, act = column exists
   auto tile_off = [&](long tile, bool& act) -> long {
     const long plane = tile / BPP;
@@ -561,7 +562,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
     return plane * (long)N * M + (act ? col : 0);
   };
   Cx<T> v[C::E], y[C::E], pf[C::E];
-  auto load = [&](long tile, int src) {
+  auto load = [&](long tile, int src, int t) {
     bool a;
     const long off = tile_off(tile, a);
     const Cx<T>* b = in + src * fsi + off;
@@ -569,13 +570,14 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
     for (int sl = 0; sl < C::E; ++sl) pf[sl] = b[slot_elem<C::L, C::E, C::R0I>(t, sl) * M];  // column 0 if missing
   };
   long tile = block_index<C>();
-  if (tile < NTILES) load(tile, op.src[0]);
+  if (tile < NTILES) load(tile, op.src[0], t0);
 #pragma unroll 1
   for (; tile < NTILES; tile += gridDim.x) {
     bool act;
     const long off = tile_off(tile, act);
 #pragma unroll 1
     for (int o = 0; o < op.nout; ++o) {
+      const int t = opaque_if<is_gen(C::L)>(t0);
       if (o == 0 || op.src[o] != op.src[o - 1]) {
 #pragma unroll
         for (int sl = 0; sl < C::E; ++sl) v[sl] = pf[sl];
@@ -585,7 +587,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
         // the compiler keeps it in flight instead of waiting at a merge
         const bool same = on < op.nout;
         const long nt = same || tile + gridDim.x >= NTILES ? tile : tile + gridDim.x;
-        load(nt, op.src[same ? on : 0]);
+        load(nt, op.src[same ? on : 0], t);
       }
       const int pw = op.pw[o];
 #pragma unroll
@@ -624,9 +626,9 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_yfanin(const Cx<T
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
   int phase = 0;
-  const int c = threadIdx.x % C::W, t = threadIdx.x / C::W;
+  const int c = threadIdx.x % C::W, t0 = threadIdx.x / C::W;
   Cx<T> v[C::E], acc[C::E], pf[C::E];
-  auto load = [&](long tile, int src) {
+  auto load = [&](long tile, int src, int t) {
     const long plane = tile / BPP;
     const int col = (int)(tile % BPP) * C::W + c;
     const bool a = col < M;
@@ -635,7 +637,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_yfanin(const Cx<T
     for (int sl = 0; sl < C::E; ++sl) pf[sl] = a ? b[slot_elem<C::L, C::E, C::R0F>(t, sl) * M] : zero<T>();
   };
   long tile = block_index<C>();
-  if (tile < NTILES) load(tile, op.src[0]);
+  if (tile < NTILES) load(tile, op.src[0], t0);
 #pragma unroll 1
   for (; tile < NTILES; tile += gridDim.x) {
     const long plane = tile / BPP;
@@ -645,12 +647,13 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_yfanin(const Cx<T
     int o = 0;
 #pragma unroll 1
     for (int k = 0; k < op.nterm; ++k) {
+      const int t = opaque_if<is_gen(C::L)>(t0);
 #pragma unroll
       for (int sl = 0; sl < C::E; ++sl) v[sl] = pf[sl];
       if (k + 1 < op.nterm)
-        load(tile, op.src[k + 1]);
+        load(tile, op.src[k + 1], t);
       else if (tile + gridDim.x < NTILES)
-        load(tile + gridDim.x, op.src[0]);
+        load(tile + gridDim.x, op.src[0], t);
       if constexpr (C::ONE)
         fft<T, C::L, -1, C::W, SY_BLOCK>(v, t, stw, 1, lds + c);
       else

@@ -94,6 +94,21 @@ def test_growth_table_matches_oracle(kw, a):
     assert np.max(np.abs(d2 / o2 - 1)) < 1e-12
 
 
+@pytest.mark.parametrize("nk", [2, 62, 63, 126, 256, 1023])
+def test_growth_table_node_counts(nk):
+    # the growth kernel runs 63 nodes per one-wave block (its last lane the
+    # normalisation run): the smallest and largest node counts, one lane
+    # short of a block, exact multiples of a block, the default
+    print(f"growth nk={nk}", flush=True)
+    plan, cfg = _plan(n=8, box=16.0, nk_growth=nk, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1")
+    k, d1, d2 = plan.growth_table(0.8)
+    kn, o1, o2 = _tables(oracle_model(cfg), 0.8)
+    assert len(k) == nk
+    assert np.max(np.abs(k / kn - 1)) < 1e-14
+    assert np.max(np.abs(d1 / o1 - 1)) < 1e-12
+    assert np.max(np.abs(d2 / o2 - 1)) < 1e-12
+
+
 # ---------------------------------------------------------------- displacements
 def _check_displace(prec, a, tol, seed=1, **kw):
     plan, cfg = _plan(precision=prec, **kw)
@@ -407,9 +422,10 @@ def test_triangle_ratio_matches_oracle():
 
 
 # ---------------------------------------------------------------- adjoint and CIC
-@pytest.mark.parametrize("n", [8, 16, 48, 64, 96])
+@pytest.mark.parametrize("n", [8, 16, 40, 48, 56, 64, 96])
 def test_backward_matches_oracle_autograd(n):
-    # 64: the x passes' paired radial gathers (last radix 8) are on
+    # 64: the x passes' paired radial gathers (last radix 8) are on; 40, 56:
+    # transforms with a factor 5 or 7 (the LDS-staged engine)
     print(f"backward fp64 n={n}", flush=True)
     plan, cfg = _plan(n=n, box=2.0 * n, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=64)
     m = oracle_model(cfg)
@@ -421,7 +437,7 @@ def test_backward_matches_oracle_autograd(n):
     assert normwise(got, ref) < 1e-11
 
 
-@pytest.mark.parametrize("n", [32, 48, 64])
+@pytest.mark.parametrize("n", [32, 40, 48, 56, 64])
 def test_backward_fp32_matches_fp64_gpu(n):
     print(f"backward fp32 n={n}", flush=True)
     kw = dict(n=n, box=2.0 * n, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1", nk_growth=64)
