@@ -169,7 +169,8 @@ hipError_t launch_colfft(int prec, int n, int dir, void* data, size_t cap, long 
 }
 
 hipError_t launch_ycombo(int prec, int n, int nr, const void* in, size_t in_cap, long in_fstride, void* out,
-                         size_t out_cap, long out_fstride, const YOp& op, const void* tw, hipStream_t s, int w) {
+                         size_t out_cap, long out_fstride, const YOp& op, const void* tw, hipStream_t s, int w,
+                         unsigned* tq) {
   if (w == 0) w = default_width(prec, n, KIND_MULTI);
   if (op.nin < 1 || op.nout < 1 || op.nin > YOP_MAX || op.nout > YOP_MAX || nr < 1) return hipErrorInvalidValue;
   if (!supported_n(n) || !in || !out || !tw || in_fstride < 0 || out_fstride < 0) return hipErrorInvalidValue;
@@ -178,7 +179,7 @@ hipError_t launch_ycombo(int prec, int n, int nr, const void* in, size_t in_cap,
   const size_t cb = 2 * esize(prec), field = (size_t)nr * n * n * (n / 2);
   if (((size_t)(op.nin - 1) * in_fstride + field) * cb > in_cap) return hipErrorInvalidValue;
   if (((size_t)(op.nout - 1) * out_fstride + field) * cb > out_cap) return hipErrorInvalidValue;
-#define CALL(NN) return prec == PREC_F32 ? ycombo_t<float, NN>(w, nr, in, in_fstride, out, out_fstride, op, tw, s) : ycombo_t<double, NN>(w, nr, in, in_fstride, out, out_fstride, op, tw, s)
+#define CALL(NN) return prec == PREC_F32 ? ycombo_t<float, NN>(w, nr, in, in_fstride, out, out_fstride, op, tw, s, tq) : ycombo_t<double, NN>(w, nr, in, in_fstride, out, out_fstride, op, tw, s, tq)
   LPT2_SWITCH_N(n, CALL)
 #undef CALL
   return hipErrorInvalidValue;
@@ -211,7 +212,8 @@ hipError_t launch_yfanin(int prec, int n, int nr, const void* in, size_t in_cap,
 }
 
 hipError_t launch_xdisp(int prec, int n, int nr, int mode, const void* in, size_t in_cap, void* out, size_t out_cap,
-                        long out_fstride, const void* tab, size_t tab_cap, const void* tw, hipStream_t s, int w) {
+                        long out_fstride, const void* tab, size_t tab_cap, const void* tw, hipStream_t s, int w,
+                        unsigned* tq) {
   if (w == 0) w = default_width(prec, n, KIND_X);
   if (!supported_n(n) || !in || !out || !tab || !tw || out_fstride < 0 || mode < 0 || mode > 3 || nr < 1)
     return hipErrorInvalidValue;
@@ -221,7 +223,7 @@ hipError_t launch_xdisp(int prec, int n, int nr, int mode, const void* in, size_
   if (nr > 65535) return hipErrorInvalidValue;  // grid.y
   const size_t n2cnt = 3 * (size_t)(n / 2) * (n / 2) + 1;
   if (n2cnt * esize(prec) * (mode == 1 ? 1 : 2) > tab_cap) return hipErrorInvalidValue;
-#define CALL(NN) return prec == PREC_F32 ? xdisp_t<float, NN>(w, nr, mode, in, out, out_fstride, tab, tw, s) : xdisp_t<double, NN>(w, nr, mode, in, out, out_fstride, tab, tw, s)
+#define CALL(NN) return prec == PREC_F32 ? xdisp_t<float, NN>(w, nr, mode, in, out, out_fstride, tab, tw, s, tq) : xdisp_t<double, NN>(w, nr, mode, in, out, out_fstride, tab, tw, s, tq)
   LPT2_SWITCH_N(n, CALL)
 #undef CALL
   return hipErrorInvalidValue;

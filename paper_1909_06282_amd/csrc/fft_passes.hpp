@@ -504,6 +504,84 @@ __device__ __forceinline__ long block_index() {
   return C::XCD ? xcd_block(blockIdx.x, gridDim.x) : (long)blockIdx.x;
 }
 
+// Tile order of the persistent column passes.  Q = false: the grid-stride
+// order from block_index.  Q = true: with a ticket array (q, 16 words, zero
+// between launches) the workgroups fall into G = min(8, grid) groups,
+// workgroup b into group b % G (the XCD it runs on, as dealt above); group x
+// works through the contiguous tile range [x P, (x+1) P), P = ceil(ntiles /
+// G), taking each next tile from a ticket counter.  The workgroups of one XCD
+// then process neighbouring tiles at the same time; in the grid-stride order
+// they drift apart within a few tiles, and tiles under 128 bytes per row
+// fetch the cache lines they share with their neighbours twice (measured at
+// n = 768, 64-byte rows: both x passes read 1.3-1.6x and write 1.1x their
+// bytes).  The last workgroup of a group to find its range empty sets the
+// group's words back to zero, so every launch starts from zero (graph
+// replays included).
+//
+// Every thread of the block calls the members in the same order; cur and nxt
+// are block-uniform (the tickets go through LDS, thread 0 takes them two
+// tiles ahead, and each tile's transforms hold block barriers between the
+// writing and the reading of a ring slot).
+template <typename C, bool Q>
+struct TileOrder {
+  static constexpr long END = 0x7fffffffL;
+  unsigned* q;
+  long ntiles, cur, nxt = END;
+  int lo = 0, hi = 0, x = 0, it = 0;
+  unsigned nblk = 0;
+  bool out = false;  // thread 0: this workgroup's range is exhausted
+  int* ring;         // three LDS slots
+
+  __device__ int take() {  // thread 0 only
+    if (out) return (int)END;
+    const int t = lo + (int)atomicAdd(&q[x], 1u);
+    if (t < hi) return t;
+    out = true;
+    if (atomicAdd(&q[8 + x], 1u) == nblk - 1) {  // the group's last workgroup: reset for the next launch
+      q[x] = 0u;
+      q[8 + x] = 0u;
+    }
+    return (int)END;
+  }
+  // Q: ends with a block barrier, ntiles < 2^31
+  __device__ TileOrder(unsigned* q_, long ntiles_, int* ring_) : q(q_), ntiles(ntiles_), ring(ring_) {
+    if (Q && q) {
+      const int g = gridDim.x < 8 ? (int)gridDim.x : 8;
+      x = (int)(blockIdx.x % g);
+      nblk = (gridDim.x - x + g - 1) / g;
+      const int nt = (int)ntiles, per = (nt + g - 1) / g;
+      lo = x < (nt + per - 1) / per ? x * per : nt;
+      hi = lo < nt - per ? lo + per : nt;
+      if (threadIdx.x == 0) {
+        ring[0] = take();
+        ring[1] = take();
+      }
+      __syncthreads();
+      cur = __builtin_amdgcn_readfirstlane(ring[0]);
+      nxt = __builtin_amdgcn_readfirstlane(ring[1]);
+    } else {
+      cur = block_index<C>();
+    }
+  }
+  __device__ bool valid() const { return cur < ntiles; }
+  __device__ long next() const { return Q && q ? nxt : cur + gridDim.x; }
+  __device__ bool has_next() const { return next() < ntiles; }
+  // at the start of a tile (before its first block barrier)
+  __device__ void begin() {
+    if (Q && q && threadIdx.x == 0) ring[(it + 2) % 3] = take();
+  }
+  // after the tile's last block barrier has been passed
+  __device__ void advance() {
+    if (Q && q) {
+      cur = nxt;
+      nxt = __builtin_amdgcn_readfirstlane(ring[(it + 2) % 3]);
+      ++it;
+    } else {
+      cur += gridDim.x;
+    }
+  }
+};
+
 template <typename T, int N, int WW, int D>
 __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_colfft(Cx<T>* __restrict__ data, int ncols, int bpp,
                                                                   long plane_stride, long rowstride,
@@ -544,13 +622,15 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_colfft(Cx<T>* __r
 template <typename T, int N, int WW>
 __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T>* __restrict__ in, long fsi,
                                                                   Cx<T>* __restrict__ out, long fso, YOp op,
-                                                                  long nplanes, const Cx<T>* __restrict__ tw) {
+                                                                  long nplanes, const Cx<T>* __restrict__ tw,
+                                                                  unsigned* tq) {
   using C = ColCfg<T, N, WW>;
   constexpr int M = N / 2;
   constexpr int BPP = (M + C::W - 1) / C::W;
   const long NTILES = nplanes * BPP;
   __shared__ Cx<T> lds[(C::ONE ? 1 : 2) * C::L * C::W];  // exchange buffers
   __shared__ Cx<T> stw[N];
+  __shared__ int ring[3];
   stage_twiddles<T, N>(stw, tw);
   int phase = 0;
   const int c = threadIdx.x % C::W, t0 = threadIdx.x / C::W;
@@ -569,10 +649,14 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
 #pragma unroll
     for (int sl = 0; sl < C::E; ++sl) pf[sl] = b[slot_elem<C::L, C::E, C::R0I>(t, sl) * M];  // column 0 if missing
   };
-  long tile = block_index<C>();
-  if (tile < NTILES) load(tile, op.src[0], t0);
+  // tickets for the two-buffer tiles of 128-byte rows (n = 512 FP32: 2-4%
+  // faster); the one-buffer tiles need their registers (n = 768: 13% slower)
+  TileOrder<C, !C::ONE && !C::XCD> order(tq, NTILES, ring);
+  if (order.valid()) load(order.cur, op.src[0], t0);
 #pragma unroll 1
-  for (; tile < NTILES; tile += gridDim.x) {
+  for (; order.valid(); order.advance()) {
+    order.begin();
+    const long tile = order.cur;
     bool act;
     const long off = tile_off(tile, act);
 #pragma unroll 1
@@ -586,7 +670,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
         // always one load (after the last tile: the current column again), so
         // the compiler keeps it in flight instead of waiting at a merge
         const bool same = on < op.nout;
-        const long nt = same || tile + gridDim.x >= NTILES ? tile : tile + gridDim.x;
+        const long nt = same || !order.has_next() ? tile : order.next();
         load(nt, op.src[same ? on : 0], t);
       }
       const int pw = op.pw[o];
@@ -720,7 +804,8 @@ template <typename T, int N, int WW, int MODE>
 __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>* __restrict__ in,
                                                                  Cx<T>* __restrict__ out, long fso,
                                                                  const T* __restrict__ tab,
-                                                                 const Cx<T>* __restrict__ tw) {
+                                                                 const Cx<T>* __restrict__ tw, int nr,
+                                                                 unsigned* tq) {
   using C = ColCfg<T, N, WW>;
   constexpr int M = N / 2;
   constexpr long NCOL = (long)N * M;
@@ -728,31 +813,39 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
   static_assert(!C::ONE, "x-pass widths keep two exchange buffers");
   __shared__ Cx<T> lds[2 * C::L * C::W];  // two exchange buffers
   __shared__ Cx<T> stw[N];
+  __shared__ int ring[3];
   stage_twiddles<T, N>(stw, tw);
   int phase = 0;
   using XP = XPair<C::L, C::E, C::RLF, C::TPC, C::W>;
   const int c = threadIdx.x % C::W, t = XP::t_of(threadIdx.x / C::W);
   const bool rev = XP::rev(threadIdx.x / C::W);
-  constexpr long NTILES = (NCOL + C::W - 1) / C::W;
-  in += blockIdx.y * FIELD;               // realisation blockIdx.y
-  out += blockIdx.y * FIELD;
+  constexpr long NTILES = (NCOL + C::W - 1) / C::W;  // per realisation
+  // tickets for tiles under 128 bytes per row (n = 768 FP32, first x pass
+  // 4.9 -> 4.3 ms), the realisations then flattened into one tile space
+  // (tile r NTILES + j: realisation r); the grid-stride order otherwise
+  // (realisation blockIdx.y)
+  constexpr bool Q = C::XCD;
   Cx<T> va[C::E], y[C::E], pf[C::E];
   // radial factors per slot: MODE 0, 2 the (PHI, PSI1) pair, MODE 1 PSI2
   constexpr bool PAIR = MODE != 1;
   Cx<T> rf[PAIR ? C::E : 1];
   T rq[PAIR ? 1 : C::E];
   auto load = [&](long tile) {
-    const long col = tile * C::W + c;
+    const long r = Q ? tile / NTILES : blockIdx.y;
+    const long col = (Q ? tile - r * NTILES : tile) * C::W + c;
     const bool a = col < NCOL;
-    const long cs = a ? col : 0;
+    const Cx<T>* src = in + r * FIELD + (a ? col : 0);
 #pragma unroll
-    for (int sl = 0; sl < C::E; ++sl) pf[sl] = a ? ld_nt(&in[cs + slot_elem<C::L, C::E, C::R0F>(t, sl) * NCOL]) : zero<T>();
+    for (int sl = 0; sl < C::E; ++sl) pf[sl] = a ? ld_nt(&src[slot_elem<C::L, C::E, C::R0F>(t, sl) * NCOL]) : zero<T>();
   };
-  long tile = block_index<C>();
-  if (tile < NTILES) load(tile);
+  TileOrder<C, Q> order(tq, Q ? nr * NTILES : NTILES, ring);
+  if (order.valid()) load(order.cur);
 #pragma unroll 1
-  for (; tile < NTILES; tile += gridDim.x) {
-    const long col = tile * C::W + c;
+  for (; order.valid(); order.advance()) {
+    order.begin();
+    const long tile = order.cur;
+    const long r = Q ? tile / NTILES : blockIdx.y;
+    const long col = (Q ? tile - r * NTILES : tile) * C::W + c;
     const bool act = col < NCOL;
     const long cs = act ? col : 0;
     const int iy = (int)(cs / M), iz = (int)(cs % M);
@@ -780,7 +873,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
     if (EARLY) gather();
   #pragma unroll
     for (int sl = 0; sl < C::E; ++sl) va[sl] = pf[sl];
-    if (tile + gridDim.x < NTILES) load(tile + gridDim.x);  // next tile's column, in flight meanwhile
+    if (order.has_next()) load(order.next());  // next tile's column, in flight meanwhile
     fft<T, C::L, -1, C::W, SY_PING>(va, t, stw, 1, lds + c, C::L * C::W, &phase);
     if (!EARLY) gather();
     constexpr int NOUT = MODE == 0 ? 5 : (MODE == 3 ? 3 : 2);
@@ -809,7 +902,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
       }
       fft<T, C::L, +1, C::W, SY_PING>(y, t, stw, 1, lds + c, C::L * C::W, &phase);
       if (act) {
-        Cx<T>* dst = out + o * fso + cs;
+        Cx<T>* dst = out + r * FIELD + o * fso + cs;
   #pragma unroll
         for (int sl = 0; sl < C::E; ++sl) st_nt(&dst[slot_elem<C::L, C::E, C::RLI>(t, sl) * NCOL], y[sl]);
       }
@@ -1101,24 +1194,24 @@ hipError_t colfft_t(int w, int dir, void* data, long nplanes, long plane_stride,
 
 template <typename T, int N, int WW>
 hipError_t ycombo_w(int nr, const void* in, long fsi, void* out, long fso, const YOp& op, const void* tw,
-                           hipStream_t s) {
+                           hipStream_t s, unsigned* tq) {
   using C = ColCfg<T, N, WW>;
   constexpr int M = N / 2;
   static const long res = resident_blocks(reinterpret_cast<const void*>(&k_ycombo<T, N, WW>), C::BLOCK);
   const long nplanes = (long)nr * N;
   const long blocks = min_l(res, nplanes * ((M + C::W - 1) / C::W));
   hipLaunchKernelGGL((k_ycombo<T, N, WW>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in, fsi,
-                     (Cx<T>*)out, fso, op, nplanes, (const Cx<T>*)tw);
+                     (Cx<T>*)out, fso, op, nplanes, (const Cx<T>*)tw, tq);
   return hipGetLastError();
 }
 
 template <typename T, int N>
 hipError_t ycombo_t(int w, int nr, const void* in, long fsi, void* out, long fso, const YOp& op, const void* tw,
-                           hipStream_t s) {
+                           hipStream_t s, unsigned* tq) {
   constexpr int K = KIND_MULTI;
-  if (w == col_w<T>(N, 0, K)) return ycombo_w<T, N, col_w<T>(N, 0, K)>(nr, in, fsi, out, fso, op, tw, s);
-  if (w == col_w<T>(N, 1, K)) return ycombo_w<T, N, col_w<T>(N, 1, K)>(nr, in, fsi, out, fso, op, tw, s);
-  if (w == col_w<T>(N, 2, K)) return ycombo_w<T, N, col_w<T>(N, 2, K)>(nr, in, fsi, out, fso, op, tw, s);
+  if (w == col_w<T>(N, 0, K)) return ycombo_w<T, N, col_w<T>(N, 0, K)>(nr, in, fsi, out, fso, op, tw, s, tq);
+  if (w == col_w<T>(N, 1, K)) return ycombo_w<T, N, col_w<T>(N, 1, K)>(nr, in, fsi, out, fso, op, tw, s, tq);
+  if (w == col_w<T>(N, 2, K)) return ycombo_w<T, N, col_w<T>(N, 2, K)>(nr, in, fsi, out, fso, op, tw, s, tq);
   return hipErrorInvalidValue;
 }
 
@@ -1147,36 +1240,38 @@ hipError_t yfanin_t(int w, int nr, const void* in, long fsi, void* out, long fso
 
 template <typename T, int N, int WW, int MODE>
 hipError_t xdisp_m(int nr, const void* in, void* out, long fso, const void* tab, const void* tw,
-                          hipStream_t s) {
+                          hipStream_t s, unsigned* tq) {
   using C = ColCfg<T, N, WW>;
   const long ntiles = ((long)N * (N / 2) + C::W - 1) / C::W;  // per realisation
   static const long res = resident_blocks(reinterpret_cast<const void*>(&k_xdisp<T, N, WW, MODE>), C::BLOCK);
-  // the resident blocks shared out over the realisations (grid.y)
-  const dim3 grid((unsigned)min_l((res + nr - 1) / nr, ntiles), (unsigned)nr);
+  // ticket order (rows under 128 bytes): one tile space over the
+  // realisations; else the resident blocks shared out over them (grid.y)
+  const dim3 grid = C::XCD ? dim3((unsigned)min_l(res, nr * ntiles), 1)
+                           : dim3((unsigned)min_l((res + nr - 1) / nr, ntiles), (unsigned)nr);
   hipLaunchKernelGGL((k_xdisp<T, N, WW, MODE>), grid, dim3(C::BLOCK), 0, s, (const Cx<T>*)in, (Cx<T>*)out, fso,
-                     (const T*)tab, (const Cx<T>*)tw);
+                     (const T*)tab, (const Cx<T>*)tw, nr, tq);
   return hipGetLastError();
 }
 
 template <typename T, int N, int WW>
 hipError_t xdisp_w(int nr, int mode, const void* in, void* out, long fso, const void* tab, const void* tw,
-                          hipStream_t s) {
+                          hipStream_t s, unsigned* tq) {
   switch (mode) {
-    case 0: return xdisp_m<T, N, WW, 0>(nr, in, out, fso, tab, tw, s);
-    case 1: return xdisp_m<T, N, WW, 1>(nr, in, out, fso, tab, tw, s);
-    case 2: return xdisp_m<T, N, WW, 2>(nr, in, out, fso, tab, tw, s);
-    case 3: return xdisp_m<T, N, WW, 3>(nr, in, out, fso, tab, tw, s);
+    case 0: return xdisp_m<T, N, WW, 0>(nr, in, out, fso, tab, tw, s, tq);
+    case 1: return xdisp_m<T, N, WW, 1>(nr, in, out, fso, tab, tw, s, tq);
+    case 2: return xdisp_m<T, N, WW, 2>(nr, in, out, fso, tab, tw, s, tq);
+    case 3: return xdisp_m<T, N, WW, 3>(nr, in, out, fso, tab, tw, s, tq);
   }
   return hipErrorInvalidValue;
 }
 
 template <typename T, int N>
 hipError_t xdisp_t(int w, int nr, int mode, const void* in, void* out, long fso, const void* tab,
-                          const void* tw, hipStream_t s) {
+                          const void* tw, hipStream_t s, unsigned* tq) {
   constexpr int K = KIND_X;
-  if (w == col_w<T>(N, 0, K)) return xdisp_w<T, N, col_w<T>(N, 0, K)>(nr, mode, in, out, fso, tab, tw, s);
-  if (w == col_w<T>(N, 1, K)) return xdisp_w<T, N, col_w<T>(N, 1, K)>(nr, mode, in, out, fso, tab, tw, s);
-  if (w == col_w<T>(N, 2, K)) return xdisp_w<T, N, col_w<T>(N, 2, K)>(nr, mode, in, out, fso, tab, tw, s);
+  if (w == col_w<T>(N, 0, K)) return xdisp_w<T, N, col_w<T>(N, 0, K)>(nr, mode, in, out, fso, tab, tw, s, tq);
+  if (w == col_w<T>(N, 1, K)) return xdisp_w<T, N, col_w<T>(N, 1, K)>(nr, mode, in, out, fso, tab, tw, s, tq);
+  if (w == col_w<T>(N, 2, K)) return xdisp_w<T, N, col_w<T>(N, 2, K)>(nr, mode, in, out, fso, tab, tw, s, tq);
   return hipErrorInvalidValue;
 }
 
@@ -1239,11 +1334,11 @@ hipError_t xpass_t(const void* in, long fsi, void* out, long fso, const XOp& op,
                                   hipStream_t);                                                                \
   PREFIX hipError_t colfft_t<T, N>(int, int, void*, long, long, int, long, const void*, hipStream_t);          \
   PREFIX hipError_t ycombo_t<T, N>(int, int, const void*, long, void*, long, const YOp&, const void*,          \
-                                   hipStream_t);                                                               \
+                                   hipStream_t, unsigned*);                                                    \
   PREFIX hipError_t yfanin_t<T, N>(int, int, const void*, long, void*, long, const YFan&, const void*,         \
                                    hipStream_t);                                                               \
   PREFIX hipError_t xdisp_t<T, N>(int, int, int, const void*, void*, long, const void*, const void*,          \
-                                  hipStream_t);                                                                \
+                                  hipStream_t, unsigned*);                                                     \
   PREFIX hipError_t xadj_t<T, N>(int, int, const void*, long, void*, const void*, const void*, hipStream_t);   \
   PREFIX hipError_t xpass_t<T, N>(const void*, long, void*, long, const XOp&, const void*, hipStream_t);
 #define LPT2_DECLARE_SIZE(N) LPT2_PASSES(extern template, float, N) LPT2_PASSES(extern template, double, N)

@@ -82,7 +82,8 @@ int default_width(int prec, int n, int kind);
 // fused inverse y pass over the nr*n planes x n/2 columns of each field
 // (nr realisations stored one after the other inside every field slot)
 hipError_t launch_ycombo(int prec, int n, int nr, const void* in, size_t in_cap, long in_fstride, void* out,
-                         size_t out_cap, long out_fstride, const YOp& op, const void* tw, hipStream_t s, int w = 0);
+                         size_t out_cap, long out_fstride, const YOp& op, const void* tw, hipStream_t s, int w = 0,
+                         unsigned* tq = nullptr);
 // adjoint x pass: mode 0 (tab = the PHI, PSI1 pair; inputs Ubar0..2, Vbar0..1)
 // or mode 1 (tab = PSI2; inputs Qbar0..1), nin input fields in_fstride
 // complex apart -> one output field (the transpose of the displacement x pass)
@@ -107,7 +108,8 @@ hipError_t launch_yfanin(int prec, int n, int nr, const void* in, size_t in_cap,
 // nr realisations one after the other (n^2 (n/2) complex each) in the input
 // and in every output field.
 hipError_t launch_xdisp(int prec, int n, int nr, int mode, const void* in, size_t in_cap, void* out, size_t out_cap,
-                        long out_fstride, const void* tab, size_t tab_cap, const void* tw, hipStream_t s, int w = 0);
+                        long out_fstride, const void* tab, size_t tab_cap, const void* tw, hipStream_t s, int w = 0,
+                        unsigned* tq = nullptr);
 // fused x pass over the n*(n/2) columns of each field
 hipError_t launch_xpass(int prec, int n, const void* in, size_t in_cap, long in_fstride, void* out, size_t out_cap,
                         long out_fstride, const XOp& op, long n2cnt, const void* tw, hipStream_t s);

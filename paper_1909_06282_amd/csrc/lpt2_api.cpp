@@ -62,6 +62,7 @@ struct Grid {
   size_t ws_off = 0;         // this grid's batch region in the workspace
   hipStream_t st = nullptr;  // own stream when the plan holds several grids
   hipEvent_t join = nullptr;
+  unsigned* tq = nullptr;    // tile tickets of the persistent column passes (16 words, zero between launches)
   std::vector<Tables> tables;
   std::vector<Tables> gr_tables;  // GR growth at a (for S_GR and the triangle ratios)
   std::vector<std::pair<double, int>> auto_choice;  // AUTO: (a, chosen candidate)
@@ -575,7 +576,7 @@ lpt2_status xdisp(Ctx& c, const char* name, int mode, const void* in, void* out,
   const size_t cap = sizeof(double) * (size_t)(TAB_ROWS - row) * g.n2cnt;
   RUN(name, c.fields(mode == 0 ? 6 : (mode == 3 ? 4 : 3)),
       launch_xdisp(p->prec, g.n, c.nr, mode, in, c.cap(in), out, c.cap(out), c.sstride(), tab, cap, g.tw, s,
-                   g.tiles[2]));
+                   g.tiles[2], g.tq));
   return LPT2_OK;
 }
 // inverse z pass of nf slots at `in` into the fields of `b` (m_z powers rpow per field)
@@ -614,7 +615,7 @@ lpt2_status ycombo(Ctx& c, const char* name, const void* in, void* out, const YO
   Grid& g = c.g;
   RUN(name, c.fields(op.nin + op.nout),
       launch_ycombo(p->prec, g.n, c.nr, in, c.cap(in), c.sstride(), out, c.cap(out), c.sstride(), op, g.tw, s,
-                    g.tiles[1]));
+                    g.tiles[1], g.tq));
   return LPT2_OK;
 }
 YOp yop(int nin, int nout, const int* src, const int* pw) {
@@ -1382,15 +1383,22 @@ lpt2_status lpt2_plan(const lpt2_config* cfgs, int n_cfgs, const int* counts, lp
       return fail(nullptr, LPT2_EDEVICE, std::string("stream setup: ") + hipGetErrorString(e));
     }
   }
-  e = dev_malloc((void**)&p->bin_partial,
-                 sizeof(double) * (BIN_BLOCKS * (size_t)BIN_MAXBINS * 4 + 4 * BIN_MAXBINS) + 256);
+  // the binner's partial sums and bins, the lpt2_check_finite counter, and
+  // each grid's 16 tile-ticket words (64 bytes, zeroed here once: the
+  // kernels leave them at zero)
+  const size_t small_bytes = sizeof(double) * (BIN_BLOCKS * (size_t)BIN_MAXBINS * 4 + 4 * BIN_MAXBINS) + 256;
+  e = dev_malloc((void**)&p->bin_partial, small_bytes + 64 * p->grids.size());
+  if (e == hipSuccess) e = hipMemset(reinterpret_cast<char*>(p->bin_partial) + small_bytes, 0, 64 * p->grids.size());
   if (e != hipSuccess) {
+    if (p->bin_partial) (void)hipFree(p->bin_partial);
     p->bin_partial = nullptr;
     lpt2_destroy(p);
     return fail(nullptr, LPT2_ENOMEM, "binner allocation failed");
   }
   p->bin_out = p->bin_partial + (size_t)BIN_BLOCKS * BIN_MAXBINS * 4;
   p->counter = reinterpret_cast<unsigned long long*>(p->bin_out + 4 * BIN_MAXBINS);
+  for (size_t i = 0; i < p->grids.size(); ++i)
+    p->grids[i].tq = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(p->bin_partial) + small_bytes + 64 * i);
   char* scr = nullptr;  // the allocation-free entry point's memory on this device
   lpt2_status sst = scratch_address(p, &scr);
   if (sst != LPT2_OK) {

@@ -191,6 +191,34 @@ def test_displace_batched_plan_matches_single():
         assert normwise(q1, r1) < F64_TOL and normwise(q2, r2) < F64_TOL
 
 
+def test_ticket_tile_order_repeats_exactly():
+    # x tiles of 64-byte rows (and the fused y pass's 128-byte two-buffer
+    # tiles) take their tiles from per-XCD tickets that the kernels set back
+    # to zero at the end of every launch: three calls in a row on one plan
+    # give the same bits, two realisations share one ticketed tile space, and
+    # every output equals the oracle's
+    n = 64
+    print(f"ticket tile order n={n}", flush=True)
+    from paper_1909_06282_amd import Plan
+    cfg = gpu_config(precision="fp32", n=n, box=2.0 * n, gravity="fr_hs", fr0_abs=1e-5, factorisation="t1",
+                     nk_growth=64)
+    plan = Plan(cfg, counts=[2])
+    opts = plan.tile_options(0)
+    plan.set_tiles(0, [0, 0, min(opts[2])])
+    assert plan.get_tiles(0)[2] * 8 < 128
+    ws = [white_noise(n, 21), white_noise(n, 22)]
+    runs = [plan.displace(1.0, [to_dev(w, torch.float32) for w in ws]) for _ in range(3)]
+    torch.cuda.synchronize()
+    for p1, p2 in runs[1:]:
+        for a, b in zip(p1 + p2, runs[0][0] + runs[0][1]):
+            assert torch.equal(a, b)
+    m = oracle_model(cfg)
+    for w, q1, q2 in zip(ws, runs[0][0], runs[0][1]):
+        r1, r2 = fields.displace(w, m, 1.0, _tables(m, 1.0))
+        assert normwise(q1, r1) < F32_TOL and normwise(q2, r2) < F32_TOL
+    plan.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_zero_noise_gives_zero_displacements(prec):
     # the degenerate input: every mode is zero, so are psi1, psi2 (exactly)
