@@ -114,10 +114,11 @@ __device__ __forceinline__ int slot_elem(int t, int slot) {
 // across it.  Measured per kernel: for the lengths with a factor 5 or 7 the
 // fused y passes stop spilling (n = 700 FP32: 128 VGPRs + 80 bytes of scratch
 // per lane -> 95 VGPRs, the nine-output pass 7.7 -> 5.9 ms) and the source
-// pass drops from 227 to 145 VGPRs (3% faster); for the power-of-two and
-// 3 * 2^k lengths the recomputation costs more than the registers it frees
-// (n = 512: the source pass at 116 instead of 162 VGPRs, four waves per SIMD
-// instead of three, still ran 9% slower), so there it stays off.
+// pass drops from 227 to 145 VGPRs (3% faster); so do the one-buffer fused y
+// passes at n = 768 (with the ticket tile order: 128 VGPRs + 60 bytes ->
+// 110 VGPRs); elsewhere the recomputation costs more than the registers it
+// frees (n = 512: the source pass at 116 instead of 162 VGPRs, four waves per
+// SIMD instead of three, still ran 9% slower), so there it stays off.
 template <bool ON>
 __device__ __forceinline__ int opaque_if(int v) {
   if constexpr (ON) asm volatile("" : "+v"(v));

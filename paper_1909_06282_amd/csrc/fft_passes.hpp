@@ -649,9 +649,10 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
 #pragma unroll
     for (int sl = 0; sl < C::E; ++sl) pf[sl] = b[slot_elem<C::L, C::E, C::R0I>(t, sl) * M];  // column 0 if missing
   };
-  // tickets for the two-buffer tiles of 128-byte rows (n = 512 FP32: 2-4%
-  // faster); the one-buffer tiles need their registers (n = 768: 13% slower)
-  TileOrder<C, !C::ONE && !C::XCD> order(tq, NTILES, ring);
+  // tickets for tiles of 128-byte rows (n = 512 FP32: 2-4% faster; the
+  // one-buffer tiles at n = 768 with the opaque index below, which keeps them
+  // from spilling: 11% faster)
+  TileOrder<C, !C::XCD> order(tq, NTILES, ring);
   if (order.valid()) load(order.cur, op.src[0], t0);
 #pragma unroll 1
   for (; order.valid(); order.advance()) {
@@ -661,7 +662,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
     const long off = tile_off(tile, act);
 #pragma unroll 1
     for (int o = 0; o < op.nout; ++o) {
-      const int t = opaque_if<is_gen(C::L)>(t0);
+      const int t = opaque_if<is_gen(C::L) || C::ONE>(t0);
       if (o == 0 || op.src[o] != op.src[o - 1]) {
 #pragma unroll
         for (int sl = 0; sl < C::E; ++sl) v[sl] = pf[sl];
