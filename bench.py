@@ -47,7 +47,10 @@ KERNEL_SOURCES = ("cx.hpp", "fft_core.hpp", "fft_passes.hpp", "fft_kernels.hip",
 # the access shape of every launch site of the step: (kind, fields read,
 # fields written, tile kind); kind 0 = contiguous lines (z passes), 1 = y
 # columns, 2 = x columns; tile kind = the plan's tile list entry (0 single
-# y FFT, 1 fused y, 2 fused x) that sets the site's columns per tile
+# y FFT, 1 fused y, 2 fused x) that sets the site's columns per tile.  The
+# pattern takes its tiles in the order the library's pass does: the fused y
+# passes from per-XCD tickets at 128-byte rows, the fused x passes under 128
+# bytes, the grid-stride order otherwise.
 PATTERNS = {
     "z_r2c_noise": (0, 1, 1, None), "y_fwd_noise": (1, 1, 1, 0), "x_fused_psi1_phi": (2, 1, 5, 2),
     "y_inv_psi1_phi": (1, 5, 9, 1), "z_c2r_psi1": (0, 3, 3, None), "z_fused_source": (0, 6, 1, None),
@@ -81,13 +84,15 @@ def pattern_rates(n: int, tiles, reps: int = 10):
     for site, (kind, nin, nout, tk) in PATTERNS.items():
         ms = C.c_double(0.0)
         w = tiles[tk] if tk is not None else 16
-        st = lib.membench_pattern(kind, n, nin, nout, w, reps, C.byref(ms))
+        tickets = (tk == 1 and w * 8 >= 128) or (tk == 2 and w * 8 < 128)
+        st = lib.membench_pattern(kind + (8 if tickets else 0), n, nin, nout, w, reps, C.byref(ms))
         if st != 0 or ms.value <= 0:
             out[site] = {"status": st}
             continue
         by = (nin + nout) * float(n) ** 3 * 4
         out[site] = {"kind": ("lines", "y columns", "x columns")[kind], "reads": nin, "writes": nout,
                      "columns_per_tile": w if tk is not None else None,
+                     "order": "tickets" if tickets else "grid-stride",
                      "ms": round(ms.value, 4), "GBps": round(by / (ms.value / 1e3) / 1e9, 1)}
     return out
 

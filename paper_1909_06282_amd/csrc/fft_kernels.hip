@@ -198,14 +198,15 @@ static bool yfan_ok(const YFan& op) {
 }
 
 hipError_t launch_yfanin(int prec, int n, int nr, const void* in, size_t in_cap, long in_fstride, void* out,
-                         size_t out_cap, long out_fstride, const YFan& op, const void* tw, hipStream_t s, int w) {
+                         size_t out_cap, long out_fstride, const YFan& op, const void* tw, hipStream_t s, int w,
+                         unsigned* tq) {
   if (w == 0) w = default_width(prec, n, KIND_MULTI);
   if (!yfan_ok(op) || nr < 1) return hipErrorInvalidValue;
   if (!supported_n(n) || !in || !out || !tw || in_fstride < 0 || out_fstride < 0) return hipErrorInvalidValue;
   const size_t cb = 2 * esize(prec), field = (size_t)nr * n * n * (n / 2);
   if (((size_t)(op.nin - 1) * in_fstride + field) * cb > in_cap) return hipErrorInvalidValue;
   if (((size_t)(op.nout - 1) * out_fstride + field) * cb > out_cap) return hipErrorInvalidValue;
-#define CALL(NN) return prec == PREC_F32 ? yfanin_t<float, NN>(w, nr, in, in_fstride, out, out_fstride, op, tw, s) : yfanin_t<double, NN>(w, nr, in, in_fstride, out, out_fstride, op, tw, s)
+#define CALL(NN) return prec == PREC_F32 ? yfanin_t<float, NN>(w, nr, in, in_fstride, out, out_fstride, op, tw, s, tq) : yfanin_t<double, NN>(w, nr, in, in_fstride, out, out_fstride, op, tw, s, tq)
   LPT2_SWITCH_N(n, CALL)
 #undef CALL
   return hipErrorInvalidValue;
@@ -230,7 +231,8 @@ hipError_t launch_xdisp(int prec, int n, int nr, int mode, const void* in, size_
 }
 
 hipError_t launch_xadj(int prec, int n, int mode, const void* in, size_t in_cap, long in_fstride, void* out,
-                       size_t out_cap, const void* tab, size_t tab_cap, const void* tw, hipStream_t s, int w) {
+                       size_t out_cap, const void* tab, size_t tab_cap, const void* tw, hipStream_t s, int w,
+                       unsigned* tq) {
   if (w == 0) w = default_width(prec, n, KIND_X);
   if (!supported_n(n) || !in || !out || !tab || !tw || in_fstride < 0 || mode < 0 || mode > 1) return hipErrorInvalidValue;
   const int nin = mode == 0 ? 5 : 2;
@@ -239,7 +241,7 @@ hipError_t launch_xadj(int prec, int n, int mode, const void* in, size_t in_cap,
   // table entries up to |m|^2 = 3 (n/2)^2: pairs for mode 0, single values for mode 1
   const size_t n2cnt = 3 * (size_t)(n / 2) * (n / 2) + 1;
   if (n2cnt * esize(prec) * (mode == 0 ? 2 : 1) > tab_cap) return hipErrorInvalidValue;
-#define CALL(NN) return prec == PREC_F32 ? xadj_t<float, NN>(w, mode, in, in_fstride, out, tab, tw, s) : xadj_t<double, NN>(w, mode, in, in_fstride, out, tab, tw, s)
+#define CALL(NN) return prec == PREC_F32 ? xadj_t<float, NN>(w, mode, in, in_fstride, out, tab, tw, s, tq) : xadj_t<double, NN>(w, mode, in, in_fstride, out, tab, tw, s, tq)
   LPT2_SWITCH_N(n, CALL)
 #undef CALL
   return hipErrorInvalidValue;

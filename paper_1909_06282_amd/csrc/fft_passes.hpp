@@ -519,22 +519,27 @@ __device__ __forceinline__ long block_index() {
 // replays included).
 //
 // Every thread of the block calls the members in the same order; cur and nxt
-// are block-uniform (the tickets go through LDS, thread 0 takes them two
-// tiles ahead, and each tile's transforms hold block barriers between the
-// writing and the reading of a ring slot).
+// are block-uniform (the tickets go through LDS: thread 0 asks for each one
+// a tile before it reads the answer, so the atomic's latency hides behind a
+// tile's work, and writes the tile to a ring slot two tiles ahead of its use;
+// each tile's transforms hold block barriers between the writing and the
+// reading of a slot).
 template <typename C, bool Q>
 struct TileOrder {
   static constexpr long END = 0x7fffffffL;
   unsigned* q;
   long ntiles, cur, nxt = END;
   int lo = 0, hi = 0, x = 0, it = 0;
-  unsigned nblk = 0;
-  bool out = false;  // thread 0: this workgroup's range is exhausted
-  int* ring;         // three LDS slots
+  unsigned nblk = 0, pend = 0;  // thread 0: a ticket taken one tile ahead of its use
+  bool out = false;             // thread 0: this workgroup's range is exhausted
+  int* ring;                    // three LDS slots
 
-  __device__ int take() {  // thread 0 only
+  __device__ void ask() {  // thread 0: the next ticket (used a tile later, so its latency is hidden)
+    if (!out) pend = atomicAdd(&q[x], 1u);
+  }
+  __device__ int tile_of_pend() {  // thread 0: the tile of the ticket asked for last
     if (out) return (int)END;
-    const int t = lo + (int)atomicAdd(&q[x], 1u);
+    const int t = lo + (int)pend;
     if (t < hi) return t;
     out = true;
     if (atomicAdd(&q[8 + x], 1u) == nblk - 1) {  // the group's last workgroup: reset for the next launch
@@ -553,8 +558,11 @@ struct TileOrder {
       lo = x < (nt + per - 1) / per ? x * per : nt;
       hi = lo < nt - per ? lo + per : nt;
       if (threadIdx.x == 0) {
-        ring[0] = take();
-        ring[1] = take();
+        ask();
+        ring[0] = tile_of_pend();
+        ask();
+        ring[1] = tile_of_pend();
+        ask();
       }
       __syncthreads();
       cur = __builtin_amdgcn_readfirstlane(ring[0]);
@@ -568,7 +576,10 @@ struct TileOrder {
   __device__ bool has_next() const { return next() < ntiles; }
   // at the start of a tile (before its first block barrier)
   __device__ void begin() {
-    if (Q && q && threadIdx.x == 0) ring[(it + 2) % 3] = take();
+    if (Q && q && threadIdx.x == 0) {
+      ring[(it + 2) % 3] = tile_of_pend();
+      ask();
+    }
   }
   // after the tile's last block barrier has been passed
   __device__ void advance() {
@@ -702,13 +713,15 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_ycombo(const Cx<T
 template <typename T, int N, int WW>
 __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_yfanin(const Cx<T>* __restrict__ in, long fsi,
                                                                   Cx<T>* __restrict__ out, long fso, YFan op,
-                                                                  long nplanes, const Cx<T>* __restrict__ tw) {
+                                                                  long nplanes, const Cx<T>* __restrict__ tw,
+                                                                  unsigned* tq) {
   using C = ColCfg<T, N, WW>;
   constexpr int M = N / 2;
   constexpr int BPP = (M + C::W - 1) / C::W;
   const long NTILES = nplanes * BPP;
   __shared__ Cx<T> lds[(C::ONE ? 1 : 2) * C::L * C::W];  // exchange buffers
   __shared__ Cx<T> stw[N];
+  __shared__ int ring[3];
   stage_twiddles<T, N>(stw, tw);
   int phase = 0;
   const int c = threadIdx.x % C::W, t0 = threadIdx.x / C::W;
@@ -721,10 +734,13 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_yfanin(const Cx<T
 #pragma unroll
     for (int sl = 0; sl < C::E; ++sl) pf[sl] = a ? b[slot_elem<C::L, C::E, C::R0F>(t, sl) * M] : zero<T>();
   };
-  long tile = block_index<C>();
-  if (tile < NTILES) load(tile, op.src[0], t0);
+  // the tile order and opaque index of the fused y pass of the displacement
+  TileOrder<C, !C::XCD> order(tq, NTILES, ring);
+  if (order.valid()) load(order.cur, op.src[0], t0);
 #pragma unroll 1
-  for (; tile < NTILES; tile += gridDim.x) {
+  for (; order.valid(); order.advance()) {
+    order.begin();
+    const long tile = order.cur;
     const long plane = tile / BPP;
     const int col = (int)(tile % BPP) * C::W + c;
     const bool act = col < M;
@@ -732,13 +748,13 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_yfanin(const Cx<T
     int o = 0;
 #pragma unroll 1
     for (int k = 0; k < op.nterm; ++k) {
-      const int t = opaque_if<is_gen(C::L)>(t0);
+      const int t = opaque_if<is_gen(C::L) || C::ONE>(t0);
 #pragma unroll
       for (int sl = 0; sl < C::E; ++sl) v[sl] = pf[sl];
       if (k + 1 < op.nterm)
         load(tile, op.src[k + 1], t);
-      else if (tile + gridDim.x < NTILES)
-        load(tile + gridDim.x, op.src[0], t);
+      else if (order.has_next())
+        load(order.next(), op.src[0], t);
       if constexpr (C::ONE)
         fft<T, C::L, -1, C::W, SY_BLOCK>(v, t, stw, 1, lds + c);
       else
@@ -924,7 +940,7 @@ template <typename T, int N, int WW, int MODE>
 __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xadj(const Cx<T>* __restrict__ in, long fsi,
                                                                 Cx<T>* __restrict__ out,
                                                                 const T* __restrict__ tab,
-                                                                const Cx<T>* __restrict__ tw) {
+                                                                const Cx<T>* __restrict__ tw, unsigned* tq) {
   using C = ColCfg<T, N, WW>;
   constexpr int M = N / 2;
   constexpr long NCOL = (long)N * M;
@@ -933,6 +949,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xadj(const Cx<T>*
   static_assert(!C::ONE, "x-pass widths keep two exchange buffers");
   __shared__ Cx<T> lds[2 * C::L * C::W];  // two exchange buffers
   __shared__ Cx<T> stw[N];
+  __shared__ int ring[3];
   stage_twiddles<T, N>(stw, tw);
   int phase = 0;
   using XP = XPair<C::L, C::E, C::RLF, C::TPC, C::W>;  // paired gathers, as in k_xdisp
@@ -950,10 +967,13 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xadj(const Cx<T>*
     for (int sl = 0; sl < C::E; ++sl)
       pf[sl] = a ? ld_nt(&in[k * fsi + cs + slot_elem<C::L, C::E, C::R0F>(t, sl) * NCOL]) : zero<T>();
   };
-  long tile = block_index<C>();
-  if (tile < NTILES) load(tile, 0);
+  // the tile order of the displacement x pass
+  TileOrder<C, C::XCD> order(tq, NTILES, ring);
+  if (order.valid()) load(order.cur, 0);
 #pragma unroll 1
-  for (; tile < NTILES; tile += gridDim.x) {
+  for (; order.valid(); order.advance()) {
+    order.begin();
+    const long tile = order.cur;
     const long col = tile * C::W + c;
     const bool act = col < NCOL;
     const long cs = act ? col : 0;
@@ -978,8 +998,8 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xadj(const Cx<T>*
       for (int sl = 0; sl < C::E; ++sl) v[sl] = pf[sl];
       if (k + 1 < NIN)
         load(tile, k + 1);
-      else if (tile + gridDim.x < NTILES)
-        load(tile + gridDim.x, 0);
+      else if (order.has_next())
+        load(order.next(), 0);
       fft<T, C::L, -1, C::W, SY_PING>(v, t, stw, 1, lds + c, C::L * C::W, &phase);
       const bool second = PAIR && k >= 3;
       const int pw = second ? k - 3 : k;
@@ -1110,6 +1130,14 @@ static long resident_blocks(const void* kernel, int block) {
 
 static inline long min_l(long a, long b) { return a < b ? a : b; }
 
+// The ticket array for a persistent launch of `blocks` workgroups over
+// `ntiles` tiles, or none (the grid-stride order) where a workgroup would
+// take fewer than 8 tiles: there the tickets taken before the first tile
+// cost more than the order gains (n = 128: fan-in y pass 12 -> 30 us).
+static inline unsigned* tickets_for(unsigned* tq, long ntiles, long blocks) {
+  return ntiles >= 8 * blocks ? tq : nullptr;
+}
+
 template <typename T, int N>
 hipError_t zr2c_t(const Batch& b, void* ws, const void* tw, hipStream_t s) {
   using C = LineCfg<N>;
@@ -1200,9 +1228,10 @@ hipError_t ycombo_w(int nr, const void* in, long fsi, void* out, long fso, const
   constexpr int M = N / 2;
   static const long res = resident_blocks(reinterpret_cast<const void*>(&k_ycombo<T, N, WW>), C::BLOCK);
   const long nplanes = (long)nr * N;
-  const long blocks = min_l(res, nplanes * ((M + C::W - 1) / C::W));
+  const long ntiles = nplanes * ((M + C::W - 1) / C::W);
+  const long blocks = min_l(res, ntiles);
   hipLaunchKernelGGL((k_ycombo<T, N, WW>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in, fsi,
-                     (Cx<T>*)out, fso, op, nplanes, (const Cx<T>*)tw, tq);
+                     (Cx<T>*)out, fso, op, nplanes, (const Cx<T>*)tw, tickets_for(tq, ntiles, blocks));
   return hipGetLastError();
 }
 
@@ -1218,24 +1247,25 @@ hipError_t ycombo_t(int w, int nr, const void* in, long fsi, void* out, long fso
 
 template <typename T, int N, int WW>
 hipError_t yfanin_w(int nr, const void* in, long fsi, void* out, long fso, const YFan& op, const void* tw,
-                           hipStream_t s) {
+                           hipStream_t s, unsigned* tq) {
   using C = ColCfg<T, N, WW>;
   constexpr int M = N / 2;
   static const long res = resident_blocks(reinterpret_cast<const void*>(&k_yfanin<T, N, WW>), C::BLOCK);
   const long nplanes = (long)nr * N;
-  const long blocks = min_l(res, nplanes * ((M + C::W - 1) / C::W));
+  const long ntiles = nplanes * ((M + C::W - 1) / C::W);
+  const long blocks = min_l(res, ntiles);
   hipLaunchKernelGGL((k_yfanin<T, N, WW>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in, fsi,
-                     (Cx<T>*)out, fso, op, nplanes, (const Cx<T>*)tw);
+                     (Cx<T>*)out, fso, op, nplanes, (const Cx<T>*)tw, tickets_for(tq, ntiles, blocks));
   return hipGetLastError();
 }
 
 template <typename T, int N>
 hipError_t yfanin_t(int w, int nr, const void* in, long fsi, void* out, long fso, const YFan& op, const void* tw,
-                           hipStream_t s) {
+                           hipStream_t s, unsigned* tq) {
   constexpr int K = KIND_MULTI;
-  if (w == col_w<T>(N, 0, K)) return yfanin_w<T, N, col_w<T>(N, 0, K)>(nr, in, fsi, out, fso, op, tw, s);
-  if (w == col_w<T>(N, 1, K)) return yfanin_w<T, N, col_w<T>(N, 1, K)>(nr, in, fsi, out, fso, op, tw, s);
-  if (w == col_w<T>(N, 2, K)) return yfanin_w<T, N, col_w<T>(N, 2, K)>(nr, in, fsi, out, fso, op, tw, s);
+  if (w == col_w<T>(N, 0, K)) return yfanin_w<T, N, col_w<T>(N, 0, K)>(nr, in, fsi, out, fso, op, tw, s, tq);
+  if (w == col_w<T>(N, 1, K)) return yfanin_w<T, N, col_w<T>(N, 1, K)>(nr, in, fsi, out, fso, op, tw, s, tq);
+  if (w == col_w<T>(N, 2, K)) return yfanin_w<T, N, col_w<T>(N, 2, K)>(nr, in, fsi, out, fso, op, tw, s, tq);
   return hipErrorInvalidValue;
 }
 
@@ -1250,7 +1280,7 @@ hipError_t xdisp_m(int nr, const void* in, void* out, long fso, const void* tab,
   const dim3 grid = C::XCD ? dim3((unsigned)min_l(res, nr * ntiles), 1)
                            : dim3((unsigned)min_l((res + nr - 1) / nr, ntiles), (unsigned)nr);
   hipLaunchKernelGGL((k_xdisp<T, N, WW, MODE>), grid, dim3(C::BLOCK), 0, s, (const Cx<T>*)in, (Cx<T>*)out, fso,
-                     (const T*)tab, (const Cx<T>*)tw, nr, tq);
+                     (const T*)tab, (const Cx<T>*)tw, nr, tickets_for(tq, nr * ntiles, grid.x));
   return hipGetLastError();
 }
 
@@ -1277,28 +1307,29 @@ hipError_t xdisp_t(int w, int nr, int mode, const void* in, void* out, long fso,
 }
 
 template <typename T, int N, int WW, int MODE>
-hipError_t xadj_m(const void* in, long fsi, void* out, const void* tab, const void* tw, hipStream_t s) {
+hipError_t xadj_m(const void* in, long fsi, void* out, const void* tab, const void* tw, hipStream_t s, unsigned* tq) {
   using C = ColCfg<T, N, WW>;
   const long ntiles = ((long)N * (N / 2) + C::W - 1) / C::W;
   static const long res = resident_blocks(reinterpret_cast<const void*>(&k_xadj<T, N, WW, MODE>), C::BLOCK);
-  hipLaunchKernelGGL((k_xadj<T, N, WW, MODE>), dim3((unsigned)min_l(res, ntiles)), dim3(C::BLOCK), 0, s,
-                     (const Cx<T>*)in, fsi, (Cx<T>*)out, (const T*)tab, (const Cx<T>*)tw);
+  const long blocks = min_l(res, ntiles);
+  hipLaunchKernelGGL((k_xadj<T, N, WW, MODE>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, (const Cx<T>*)in, fsi,
+                     (Cx<T>*)out, (const T*)tab, (const Cx<T>*)tw, tickets_for(tq, ntiles, blocks));
   return hipGetLastError();
 }
 
 template <typename T, int N, int WW>
 hipError_t xadj_w(int mode, const void* in, long fsi, void* out, const void* tab, const void* tw,
-                         hipStream_t s) {
-  return mode == 0 ? xadj_m<T, N, WW, 0>(in, fsi, out, tab, tw, s) : xadj_m<T, N, WW, 1>(in, fsi, out, tab, tw, s);
+                         hipStream_t s, unsigned* tq) {
+  return mode == 0 ? xadj_m<T, N, WW, 0>(in, fsi, out, tab, tw, s, tq) : xadj_m<T, N, WW, 1>(in, fsi, out, tab, tw, s, tq);
 }
 
 template <typename T, int N>
 hipError_t xadj_t(int w, int mode, const void* in, long fsi, void* out, const void* tab, const void* tw,
-                         hipStream_t s) {
+                         hipStream_t s, unsigned* tq) {
   constexpr int K = KIND_X;
-  if (w == col_w<T>(N, 0, K)) return xadj_w<T, N, col_w<T>(N, 0, K)>(mode, in, fsi, out, tab, tw, s);
-  if (w == col_w<T>(N, 1, K)) return xadj_w<T, N, col_w<T>(N, 1, K)>(mode, in, fsi, out, tab, tw, s);
-  if (w == col_w<T>(N, 2, K)) return xadj_w<T, N, col_w<T>(N, 2, K)>(mode, in, fsi, out, tab, tw, s);
+  if (w == col_w<T>(N, 0, K)) return xadj_w<T, N, col_w<T>(N, 0, K)>(mode, in, fsi, out, tab, tw, s, tq);
+  if (w == col_w<T>(N, 1, K)) return xadj_w<T, N, col_w<T>(N, 1, K)>(mode, in, fsi, out, tab, tw, s, tq);
+  if (w == col_w<T>(N, 2, K)) return xadj_w<T, N, col_w<T>(N, 2, K)>(mode, in, fsi, out, tab, tw, s, tq);
   return hipErrorInvalidValue;
 }
 
@@ -1337,10 +1368,11 @@ hipError_t xpass_t(const void* in, long fsi, void* out, long fso, const XOp& op,
   PREFIX hipError_t ycombo_t<T, N>(int, int, const void*, long, void*, long, const YOp&, const void*,          \
                                    hipStream_t, unsigned*);                                                    \
   PREFIX hipError_t yfanin_t<T, N>(int, int, const void*, long, void*, long, const YFan&, const void*,         \
-                                   hipStream_t);                                                               \
+                                   hipStream_t, unsigned*);                                                    \
   PREFIX hipError_t xdisp_t<T, N>(int, int, int, const void*, void*, long, const void*, const void*,          \
                                   hipStream_t, unsigned*);                                                     \
-  PREFIX hipError_t xadj_t<T, N>(int, int, const void*, long, void*, const void*, const void*, hipStream_t);   \
+  PREFIX hipError_t xadj_t<T, N>(int, int, const void*, long, void*, const void*, const void*, hipStream_t,    \
+                                 unsigned*);                                                                   \
   PREFIX hipError_t xpass_t<T, N>(const void*, long, void*, long, const XOp&, const void*, hipStream_t);
 #define LPT2_DECLARE_SIZE(N) LPT2_PASSES(extern template, float, N) LPT2_PASSES(extern template, double, N)
 #define LPT2_INSTANTIATE_SIZE(N) LPT2_PASSES(template, float, N) LPT2_PASSES(template, double, N)

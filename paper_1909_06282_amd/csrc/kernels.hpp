@@ -88,7 +88,8 @@ hipError_t launch_ycombo(int prec, int n, int nr, const void* in, size_t in_cap,
 // or mode 1 (tab = PSI2; inputs Qbar0..1), nin input fields in_fstride
 // complex apart -> one output field (the transpose of the displacement x pass)
 hipError_t launch_xadj(int prec, int n, int mode, const void* in, size_t in_cap, long in_fstride, void* out,
-                       size_t out_cap, const void* tab, size_t tab_cap, const void* tw, hipStream_t s, int w = 0);
+                       size_t out_cap, const void* tab, size_t tab_cap, const void* tw, hipStream_t s, int w = 0,
+                       unsigned* tq = nullptr);
 // fan-in y pass of the adjoint: output o sums terms first[o] .. first[o+1]-1;
 // term k is the forward y-FFT of input field src[k] times m_y^py[k] m_z^pz[k]
 // (powers 0..2; first[0] = 0, first[nout] = nterm, every output has a term)
@@ -99,7 +100,8 @@ struct YFan {
   int src[YFAN_MAX], py[YFAN_MAX], pz[YFAN_MAX];
 };
 hipError_t launch_yfanin(int prec, int n, int nr, const void* in, size_t in_cap, long in_fstride, void* out,
-                         size_t out_cap, long out_fstride, const YFan& op, const void* tw, hipStream_t s, int w = 0);
+                         size_t out_cap, long out_fstride, const YFan& op, const void* tw, hipStream_t s, int w = 0,
+                         unsigned* tq = nullptr);
 // displacement x pass: mode 0 (tab = interleaved PHI, PSI1 per |m|^2; five
 // outputs U0,U1,U2,V0,V1), mode 1 (tab = PSI2; outputs Q0,Q1), mode 2
 // (tab = the PHI, PSI1 pair; outputs V0,V1) or mode 3 (the pair; outputs

@@ -766,7 +766,8 @@ lpt2_status xadj(Ctx& c, const char* name, int mode, const void* in, void* out, 
   const void* tab = t->radial + (size_t)row * g.n2cnt;
   const size_t cap = sizeof(double) * (size_t)(TAB_ROWS - row) * g.n2cnt;
   RUN(name, c.fields(mode == 0 ? 6 : 3),
-      launch_xadj(p->prec, g.n, mode, in, c.cap(in), c.sstride(), out, c.cap(out), tab, cap, g.tw, s, g.tiles[2]));
+      launch_xadj(p->prec, g.n, mode, in, c.cap(in), c.sstride(), out, c.cap(out), tab, cap, g.tw, s, g.tiles[2],
+                  g.tq));
   return LPT2_OK;
 }
 // fan-in y pass over the c.nr realisations of each of op.nin slots at `in`
@@ -776,7 +777,7 @@ lpt2_status yfan(Ctx& c, const char* name, const void* in, void* out, const YFan
   Grid& g = c.g;
   RUN(name, c.fields(op.nterm + op.nout),
       launch_yfanin(p->prec, g.n, c.nr, in, c.cap(in), c.sstride(), out, c.cap(out), c.sstride(), op, g.tw, s,
-                    g.tiles[1]));
+                    g.tiles[1], g.tq));
   return LPT2_OK;
 }
 // terms (src, m_y power, m_z power) of the outputs one after the other, nper[o] for output o

@@ -173,6 +173,8 @@ def test_membench_loads_and_rejects_bad_patterns_without_a_device():
     L.membench_pattern.restype = C.c_int
     ms = C.c_double(0.0)
     assert L.membench_pattern(3, 512, 1, 1, 16, 1, C.byref(ms)) == -1      # unknown kind
+    assert L.membench_pattern(8, 512, 1, 1, 16, 1, C.byref(ms)) == -1      # lines have no ticket order
+    assert L.membench_pattern(11, 512, 1, 1, 16, 1, C.byref(ms)) == -1
     assert L.membench_pattern(2, 256, 1, 5, 16, 1, C.byref(ms)) == -1      # strided kinds: n = 512, 768
     assert L.membench_pattern(1, 512, 1, 1, 12, 1, C.byref(ms)) == -1      # width not offered
     assert L.membench_pattern(0, 512, 9, 8, 16, 1, C.byref(ms)) == -1      # more than 16 fields
