@@ -828,13 +828,19 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
   constexpr long NCOL = (long)N * M;
   constexpr long FIELD = (long)N * NCOL;  // one realisation's half spectrum
   static_assert(!C::ONE, "x-pass widths keep two exchange buffers");
-  __shared__ Cx<T> lds[2 * C::L * C::W];  // two exchange buffers
+  // the two-output pass under 128-byte rows keeps one exchange buffer (two
+  // barriers per exchange), so that two workgroups fit a CU, with the opaque
+  // thread index that brings it to 125 VGPRs (n = 768 FP32: 2.47 -> 2.07-
+  // 2.14 ms; the five-output pass, at 150 VGPRs one workgroup either way,
+  // lost 15%, and n = 700 lost 13%)
+  constexpr bool X1 = MODE == 1 && C::XCD && !is_gen(C::L);
+  __shared__ Cx<T> lds[(X1 ? 1 : 2) * C::L * C::W];  // exchange buffers
   __shared__ Cx<T> stw[N];
   __shared__ int ring[3];
   stage_twiddles<T, N>(stw, tw);
   int phase = 0;
   using XP = XPair<C::L, C::E, C::RLF, C::TPC, C::W>;
-  const int c = threadIdx.x % C::W, t = XP::t_of(threadIdx.x / C::W);
+  const int c = threadIdx.x % C::W, t0 = XP::t_of(threadIdx.x / C::W);
   const bool rev = XP::rev(threadIdx.x / C::W);
   constexpr long NTILES = (NCOL + C::W - 1) / C::W;  // per realisation
   // tickets for tiles under 128 bytes per row (n = 768 FP32, first x pass
@@ -847,7 +853,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
   constexpr bool PAIR = MODE != 1;
   Cx<T> rf[PAIR ? C::E : 1];
   T rq[PAIR ? 1 : C::E];
-  auto load = [&](long tile) {
+  auto load = [&](long tile, int t) {
     const long r = Q ? tile / NTILES : blockIdx.y;
     const long col = (Q ? tile - r * NTILES : tile) * C::W + c;
     const bool a = col < NCOL;
@@ -856,10 +862,11 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
     for (int sl = 0; sl < C::E; ++sl) pf[sl] = a ? ld_nt(&src[slot_elem<C::L, C::E, C::R0F>(t, sl) * NCOL]) : zero<T>();
   };
   TileOrder<C, Q> order(tq, Q ? nr * NTILES : NTILES, ring);
-  if (order.valid()) load(order.cur);
+  if (order.valid()) load(order.cur, t0);
 #pragma unroll 1
   for (; order.valid(); order.advance()) {
     order.begin();
+    const int t = opaque_if<X1>(t0);
     const long tile = order.cur;
     const long r = Q ? tile / NTILES : blockIdx.y;
     const long col = (Q ? tile - r * NTILES : tile) * C::W + c;
@@ -890,12 +897,16 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
     if (EARLY) gather();
   #pragma unroll
     for (int sl = 0; sl < C::E; ++sl) va[sl] = pf[sl];
-    if (order.has_next()) load(order.next());  // next tile's column, in flight meanwhile
-    fft<T, C::L, -1, C::W, SY_PING>(va, t, stw, 1, lds + c, C::L * C::W, &phase);
+    if (order.has_next()) load(order.next(), t);  // next tile's column, in flight meanwhile
+    if constexpr (X1)
+      fft<T, C::L, -1, C::W, SY_BLOCK>(va, t, stw, 1, lds + c);
+    else
+      fft<T, C::L, -1, C::W, SY_PING>(va, t, stw, 1, lds + c, C::L * C::W, &phase);
     if (!EARLY) gather();
     constexpr int NOUT = MODE == 0 ? 5 : (MODE == 3 ? 3 : 2);
   #pragma unroll 1
     for (int o = 0; o < NOUT; ++o) {
+      const int t = opaque_if<X1>(t0);
       // MODE 0: o < 3 -> -m_x^o PHI X ; o = 3, 4 -> i m_x^(o-3) PSI1 X.  MODE 1: -i m_x^o PSI2 X.
       // MODE 2: i m_x^o PSI1 X
       const bool second = (MODE == 0 && o >= 3) || MODE == 2;
@@ -917,7 +928,10 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xdisp(const Cx<T>
         else
           y[sl] = mk(a.y * f, -a.x * f);
       }
-      fft<T, C::L, +1, C::W, SY_PING>(y, t, stw, 1, lds + c, C::L * C::W, &phase);
+      if constexpr (X1)
+        fft<T, C::L, +1, C::W, SY_BLOCK>(y, t, stw, 1, lds + c);
+      else
+        fft<T, C::L, +1, C::W, SY_PING>(y, t, stw, 1, lds + c, C::L * C::W, &phase);
       if (act) {
         Cx<T>* dst = out + r * FIELD + o * fso + cs;
   #pragma unroll
