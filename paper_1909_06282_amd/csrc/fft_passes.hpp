@@ -581,9 +581,11 @@ struct TileOrder {
       ask();
     }
   }
-  // after the tile's last block barrier has been passed
+  // after the tile's last block barrier has been passed (a transform of one
+  // stage exchanges nothing through LDS, so there the barrier is taken here)
   __device__ void advance() {
     if (Q && q) {
+      if constexpr (!is_gen(C::L) && plan_stages(C::L) <= 1) __syncthreads();
       cur = nxt;
       nxt = __builtin_amdgcn_readfirstlane(ring[(it + 2) % 3]);
       ++it;
