@@ -115,7 +115,10 @@ void lpt2_config_default(lpt2_config* cfg);
  * half-spectrum slots per realisation of a batch: the realisations of one
  * configuration are transformed up to 64 at a time (fewer where 16 slots of
  * that many fields would pass 16 GiB), and every configuration has a region
- * of its own.  On failure *out is NULL. */
+ * of its own; and one small buffer: the shell binner's partial sums, the
+ * lpt2_check_finite counter and, per configuration, the 16 tile-ticket words
+ * of the column passes (zeroed here; every pass leaves them at zero).  On
+ * failure *out is NULL. */
 lpt2_status lpt2_plan(const lpt2_config* cfgs, int n_cfgs, const int* counts, lpt2_plan_t* out);
 
 /* Release every device and host resource of the plan (NULL is a no-op). */
