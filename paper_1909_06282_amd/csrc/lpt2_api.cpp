@@ -1389,12 +1389,15 @@ lpt2_status lpt2_plan(const lpt2_config* cfgs, int n_cfgs, const int* counts, lp
   // kernels leave them at zero)
   const size_t small_bytes = sizeof(double) * (BIN_BLOCKS * (size_t)BIN_MAXBINS * 4 + 4 * BIN_MAXBINS) + 256;
   e = dev_malloc((void**)&p->bin_partial, small_bytes + 64 * p->grids.size());
-  if (e == hipSuccess) e = hipMemset(reinterpret_cast<char*>(p->bin_partial) + small_bytes, 0, 64 * p->grids.size());
   if (e != hipSuccess) {
-    if (p->bin_partial) (void)hipFree(p->bin_partial);
     p->bin_partial = nullptr;
     lpt2_destroy(p);
     return fail(nullptr, LPT2_ENOMEM, "binner allocation failed");
+  }
+  e = hipMemset(reinterpret_cast<char*>(p->bin_partial) + small_bytes, 0, 64 * p->grids.size());
+  if (e != hipSuccess) {
+    lpt2_destroy(p);
+    return fail(nullptr, LPT2_EDEVICE, std::string("tile tickets: ") + hipGetErrorString(e));
   }
   p->bin_out = p->bin_partial + (size_t)BIN_BLOCKS * BIN_MAXBINS * 4;
   p->counter = reinterpret_cast<unsigned long long*>(p->bin_out + 4 * BIN_MAXBINS);
