@@ -116,9 +116,12 @@ __device__ __forceinline__ int slot_elem(int t, int slot) {
 // per lane -> 95 VGPRs, the nine-output pass 7.7 -> 5.9 ms) and the source
 // pass drops from 227 to 145 VGPRs (3% faster); so do the one-buffer fused y
 // passes at n = 768 (with the ticket tile order: 128 VGPRs + 60 bytes ->
-// 110 VGPRs); elsewhere the recomputation costs more than the registers it
-// frees (n = 512: the source pass at 116 instead of 162 VGPRs, four waves per
-// SIMD instead of three, still ran 9% slower), so there it stays off.
+// 110 VGPRs); so do the z and x passes of the full modified-gravity source
+// (n = 256: the z pass of the f(R) pairs 200 -> 166 VGPRs, three waves per
+// SIMD instead of two; the ratio spectrum 3.65 -> 3.26 ms); elsewhere the
+// recomputation costs more than the registers it frees (n = 512: the source
+// pass at 116 instead of 162 VGPRs, four waves per SIMD instead of three,
+// still ran 9% slower), so there it stays off.
 template <bool ON>
 __device__ __forceinline__ int opaque_if(int v) {
   if constexpr (ON) asm volatile("" : "+v"(v));

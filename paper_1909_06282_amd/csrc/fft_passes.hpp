@@ -302,9 +302,10 @@ __global__ __launch_bounds__(256) void k_zmg(const Cx<T>* __restrict__ in, long 
   load_field(0);
 #pragma unroll 1
   for (int f = 0; f < NF; ++f) {
-    c2r_prepare_regs<T, N>(raw, 0, v, t, lb, stw);
+    const int tf = opaque_if<true>(t);
+    c2r_prepare_regs<T, N>(raw, 0, v, tf, lb, stw);
     if (PF && f < NF - 1) load_field(f + 1);
-    fft<T, C::L, +1, 1, C::SY, true>(v, t, stw, 2, lb);
+    fft<T, C::L, +1, 1, C::SY, true>(v, tf, stw, 2, lb);
     if constexpr (KIND == 2) {
       if (f == 6) {
 #pragma unroll
@@ -1069,7 +1070,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xpass(const Cx<T>
   __shared__ Cx<T> lds[C::L * C::W];
   __shared__ Cx<T> stw[N];
   stage_twiddles<T, N>(stw, tw);
-  const int c = threadIdx.x % C::W, t = threadIdx.x / C::W;
+  const int c = threadIdx.x % C::W, t0 = threadIdx.x / C::W;
   const long col = block_index<C>() * C::W + c;
   const bool act = col < NCOL;
   const long cs = act ? col : 0;
@@ -1079,11 +1080,13 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xpass(const Cx<T>
   const long n2yz = (long)my * my + (long)iz * iz;
   Cx<T> v[C::E], y[C::E];
   if (op.nin == 1) {
+    const int t = t0;
 #pragma unroll
     for (int sl = 0; sl < C::E; ++sl) v[sl] = act ? in[cs + slot_elem<C::L, C::E, C::R0F>(t, sl) * NCOL] : zero<T>();
     fft<T, C::L, -1, C::W>(v, t, stw, 1, lds + c);
 #pragma unroll 1
     for (int o = 0; o < op.nout; ++o) {
+      const int t = opaque_if<true>(t0);
 #pragma unroll
       for (int sl = 0; sl < C::E; ++sl) {
         const int ix = slot_elem<C::L, C::E, C::RLF>(t, sl);
@@ -1108,6 +1111,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xpass(const Cx<T>
     for (int sl = 0; sl < C::E; ++sl) y[sl] = zero<T>();
 #pragma unroll 1
     for (int f = 0; f < op.nin; ++f) {
+      const int t = opaque_if<true>(t0);
       const Cx<T>* src = in + f * fsi + cs;
 #pragma unroll
       for (int sl = 0; sl < C::E; ++sl) v[sl] = act ? src[slot_elem<C::L, C::E, C::R0F>(t, sl) * NCOL] : zero<T>();
@@ -1121,6 +1125,7 @@ __global__ __launch_bounds__((ColCfg<T, N, WW>::BLOCK)) void k_xpass(const Cx<T>
       }
     }
     Cx<T>* dst = out + cs;
+    const int t = t0;
     if (op.inverse) {
       fft<T, C::L, +1, C::W>(y, t, stw, 1, lds + c);
       if (act) {
