@@ -172,7 +172,9 @@ lpt2_status lpt2_displace(lpt2_plan_t plan, double a, const void* const* noise,
  *     overlap on one GPU (other streams, other plans, other threads) race on
  *     the scratch: the caller must order them.
  *   - Results equal lpt2_displace's (the same kernels and tables); per-launch
- *     profiling is not recorded. */
+ *     profiling is not recorded.  The tile tickets of the column passes, if
+ *     a pass takes them, stay in the plan's small buffer (made with the
+ *     plan, left at zero by every pass). */
 #define LPT2_NOALLOC_SLOT_BYTES ((unsigned long)64 << 20)
 #define LPT2_NOALLOC_TABLE_BYTES ((unsigned long)2 << 20)
 lpt2_status lpt2_displace_noalloc(lpt2_plan_t plan, double a, const void* noise, void* psi1,
